@@ -1,0 +1,253 @@
+"""Pins of the CPU oracle against what the physics and the mathematics fix (no GPU).
+
+Each test checks the oracle against something other than itself: closed forms
+(Onsager, Yang, the Ising-copy mappings of the cube and square models, the
+four-state Potts duality of the tetrahedron model), brute-force partition
+functions of small clusters, a library eigensolver on synthetic matrices, and
+invariants stated in Sec. II of the paper (C real symmetric, rho PSD, the entropy
+bound of Algorithm 3).  A plausible mistake -- a wrong leg order of W, a K/2
+coupling, a dropped bond, a transposed operand, a wrong normalization -- fails
+at least one of them (see test_planted_leg_order and test_planted_half_coupling).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import ctmrg_inputs as I
+import exact as E
+from oracle import ctmrg_oracle as O
+
+
+# --------------------------------------------------------------------------- Jacobi
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (60, 3), (151, 4)])
+def test_jacobi_known_spectrum(n, seed):
+    lam = I.graded_spectrum(seed, n)
+    A = I.random_symmetric_with_spectrum(seed, lam)
+    ev, vec = O.jacobi(A)
+    scale = np.abs(lam).max()
+    assert np.allclose(np.sort(ev), np.sort(lam), rtol=0, atol=1e-13 * scale * max(1, n) ** 0.5)
+    assert np.abs(A @ vec - vec * ev).max() <= 1e-12 * scale
+    assert np.abs(vec.T @ vec - np.eye(n)).max() <= 1e-12
+    # the special case that reduces to a library routine
+    assert np.allclose(np.sort(ev), np.linalg.eigvalsh(A), rtol=0, atol=1e-12 * scale)
+
+
+def test_jacobi_degenerate_and_zero():
+    A = np.zeros((5, 5))
+    ev, vec = O.jacobi(A)
+    assert np.all(ev == 0) and np.allclose(vec, np.eye(5))
+    lam = np.array([2.0, 2.0, 2.0, -2.0, 0.0, 0.0, 1e-9])
+    A = I.random_symmetric_with_spectrum(9, lam)
+    ev, vec = O.jacobi(A)
+    assert np.allclose(np.sort(ev), np.sort(lam), atol=1e-14)
+    assert np.abs(vec.T @ vec - np.eye(7)).max() < 1e-13
+
+
+def test_sort_and_cut():
+    lam = np.array([0.5, -1.0, 1.0, 0.25, -0.25, 1e-20])
+    order = O.sort_spectrum(lam)
+    assert list(lam[order]) == [1.0, -1.0, 0.5, 0.25, -0.25, 1e-20]
+    ls = lam[order]
+    # |1| = |-1|: m=1 would split the pair, so nothing smaller than 2 is admissible
+    assert O.cut_dimension(ls, 1, 1e-10, 1e-13) == 1  # fallback keeps the rank-limited count
+    assert O.cut_dimension(ls, 2, 1e-10, 1e-13) == 2
+    assert O.cut_dimension(ls, 4, 1e-10, 1e-13) == 3  # 0.25 / -0.25 pair would be split
+    assert O.cut_dimension(ls, 6, 1e-10, 1e-13) == 5  # 1e-20 is below the rank threshold
+
+
+# --------------------------------------------------------------------------- weight
+
+def test_weight_values_and_symmetry():
+    V = I.dodecahedron()
+    q, K = 20, 1.0 / 0.4398
+    W = O.weight(V, K)
+    assert W.shape == (q, q, q, q)
+    assert math.isclose(W[0, 0, 0, 0], math.exp(4 * K), rel_tol=1e-14)
+    # dot products from one vertex: {1, sqrt5/3, 1/3, -1/3, -sqrt5/3, -1} with multiplicities {1,3,6,6,3,1}
+    d = np.round(V @ V[0], 12)
+    vals, counts = np.unique(d, return_counts=True)
+    r5 = math.sqrt(5) / 3
+    assert np.allclose(vals, [-1, -r5, -1 / 3, 1 / 3, r5, 1])
+    assert list(counts) == [1, 3, 6, 6, 3, 1]
+    # the plaquette's dihedral symmetry: cyclic order s -> sigma -> sigma' -> s'
+    cyc = W.transpose(1, 3, 0, 2)      # (s,sigma,s',sigma') -> rotate the four corners
+    assert np.allclose(W, cyc, rtol=1e-14)
+    refl = W.transpose(1, 0, 3, 2)     # swap s<->sigma and s'<->sigma'
+    assert np.allclose(W, refl, rtol=1e-14)
+    Wm = O.weight_matrix(V, K)
+    assert np.allclose(Wm, Wm.T)
+
+
+# --------------------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize(
+    "name,V,K,kmax,m",
+    [
+        ("ising", I.ising(), 0.4, 4, 64),
+        ("three-vectors", I.tetrahedron()[:3], 0.7, 3, 27),
+        ("tetrahedron", I.tetrahedron(), 0.9, 2, 16),
+        ("dodecahedron", I.dodecahedron(), 1.0 / 0.44, 2, 20),
+    ],
+)
+def test_bruteforce_clusters(name, V, K, kmax, m):
+    """Untruncated CTMRG: ln Tr C'_k^4 = 4 ln b_k equals ln Z of the 2k x 2k cluster with fixed perimeter."""
+    o = O.OracleCTMRG(V, K, m)
+    for k in range(1, kmax + 1):
+        o.step()
+        assert np.all(np.abs(o.last.Pt - o.last.Pt.transpose(0, 2, 1)) <= 1e-12 * o.last.n_P)
+        ref = E.cluster_lnZ_transfer(V, K, k)
+        assert abs(4 * o.ln_b - ref) <= 1e-12 * abs(ref), (k, 4 * o.ln_b, ref)
+
+
+def test_bruteforce_by_enumeration():
+    V = I.ising()
+    for k, K in [(1, 0.3), (1, 0.8)]:
+        o = O.OracleCTMRG(V, K, 8)
+        for _ in range(k):
+            o.step()
+        assert math.isclose(4 * o.ln_b, math.log(E.cluster_Z_enumerate(V, K, k)), rel_tol=1e-13)
+
+
+def _literal_weight(V, K):
+    """Algorithm 3's reshaping read literally: w_{(s,sigma),(s',sigma')} = W_{s sigma s' sigma'}
+    with Eq. 1's cyclic order s, sigma, s', sigma' (so s' opposite s)."""
+    G = V @ V.T
+    return np.exp(K * (G[:, :, None, None] + G.T[None, :, :, None] + G[None, None, :, :]
+                       + G.T[:, None, None, :]))
+
+
+def test_planted_leg_order(monkeypatch):
+    """The literal leg order builds a different network: it fails the brute-force pin at k=2."""
+    V, K = I.tetrahedron()[:3], 0.7
+    monkeypatch.setattr(O, "weight", _literal_weight)
+    o = O.OracleCTMRG(V, K, 27)
+    o.step()
+    assert abs(4 * o.ln_b - E.cluster_lnZ_transfer(V, K, 1)) < 1e-12  # one vertex: same
+    o.step()
+    assert abs(4 * o.ln_b - E.cluster_lnZ_transfer(V, K, 2)) > 1e-3
+
+
+def test_planted_half_coupling(monkeypatch):
+    """A K/2 coupling (face weight on every plaquette) fails the Onsager pin."""
+    real = O.weight
+    monkeypatch.setattr(O, "weight", lambda V, K: real(V, 0.5 * K))
+    o, obs = O.run_fixed_point(I.ising(), 0.5, 16, tol=1e-12)
+    assert abs(obs["minus_beta_f"] - E.ising_minus_beta_f(0.5)) > 1e-2
+
+
+# --------------------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("T,m", [(2.0, 16), (1.5, 12), (2.1, 24)])
+def test_ising_onsager_yang(T, m):
+    K = 1.0 / T
+    o, obs = O.run_fixed_point(I.ising(), K, m, tol=1e-13)
+    assert obs["converged"]
+    assert abs(obs["minus_beta_f"] - E.ising_minus_beta_f(K)) <= 1e-10 * E.ising_minus_beta_f(K)
+    assert abs(obs["E"] - E.ising_energy(K)) <= 1e-8
+    assert abs(obs["M"] - E.ising_magnetization(K)) <= 1e-8
+    assert abs(obs["ln_kappa_ratio"] - obs["ln_kappa_W"]) <= 1e-10
+
+
+def test_ising_disordered():
+    K = 1.0 / 2.5
+    o, obs = O.run_fixed_point(I.ising(), K, 16, tol=1e-13)
+    assert abs(obs["minus_beta_f"] - E.ising_minus_beta_f(K)) <= 1e-10 * E.ising_minus_beta_f(K)
+    assert abs(obs["E"] - E.ising_energy(K)) <= 1e-8
+    assert abs(obs["M"]) <= 1e-5
+
+
+def test_ising_energy_is_dF_dK():
+    """E per site = -d(-beta f)/dK: finite difference of the oracle's own free energy."""
+    K, h = 0.5, 1e-4
+    fp = O.run_fixed_point(I.ising(), K + h, 16, tol=1e-14)[1]["minus_beta_f"]
+    fm = O.run_fixed_point(I.ising(), K - h, 16, tol=1e-14)[1]["minus_beta_f"]
+    e = O.run_fixed_point(I.ising(), K, 16, tol=1e-14)[1]["E"]
+    assert abs(-(fp - fm) / (2 * h) - e) < 1e-7
+
+
+def test_cube_is_three_ising_copies():
+    T = 0.6
+    K = 1.0 / T
+    o, obs = O.run_fixed_point(I.cube(), K, 27, tol=1e-12)
+    assert abs(obs["minus_beta_f"] - 3 * E.ising_minus_beta_f(K / 3)) <= 1e-11
+    assert abs(obs["E"] - E.ising_energy(K / 3)) <= 1e-9
+    assert abs(obs["M"] - E.ising_magnetization(K / 3)) <= 1e-9
+
+
+def test_square_is_two_ising_copies():
+    K = 1.0
+    o, obs = O.run_fixed_point(I.square(), K, 36, tol=1e-12)
+    assert abs(obs["minus_beta_f"] - 2 * E.ising_minus_beta_f(K / 2)) <= 1e-12
+    assert abs(obs["E"] - E.ising_energy(K / 2)) <= 1e-10
+    assert abs(obs["M"] - E.ising_magnetization(K / 2)) <= 1e-10
+
+
+def test_tetrahedron_potts_duality():
+    """Off-critical pin of the q=4 tetrahedron model: f(K) - f(K*) from the Potts duality."""
+    K = 1.0
+    Ks = E.tetra_dual_K(K)
+    assert 1.0 / Ks > E.TC_TETRA > 1.0 / K
+    a = O.run_fixed_point(I.tetrahedron(), K, 32, tol=1e-12)[1]
+    b = O.run_fixed_point(I.tetrahedron(), Ks, 32, tol=1e-12)[1]
+    assert abs(a["minus_beta_f"] - b["minus_beta_f"] - E.tetra_duality_offset(K)) <= 1e-12
+
+
+def test_tetrahedron_critical_point():
+    """Ordered just below T_c = 4/(3 ln 3), disordered just above; E(T_c) = -4/3 (loose: critical)."""
+    lo = O.run_fixed_point(I.tetrahedron(), 1.0 / (0.9 * E.TC_TETRA), 16, tol=1e-11)[1]
+    hi = O.run_fixed_point(I.tetrahedron(), 1.0 / (1.1 * E.TC_TETRA), 16, tol=1e-11)[1]
+    assert lo["M"] > 0.5 and abs(hi["M"]) < 1e-3
+    # at criticality the finite-m error decays slowly (logarithmic corrections of the
+    # four-state Potts class): only require it to shrink with m and stay within 3e-2
+    c8 = O.run_fixed_point(I.tetrahedron(), 1.0 / E.TC_TETRA, 8, tol=1e-9, max_steps=4000)[1]
+    c24 = O.run_fixed_point(I.tetrahedron(), 1.0 / E.TC_TETRA, 24, tol=1e-9, max_steps=4000)[1]
+    assert abs(c24["E"] + 4.0 / 3.0) < abs(c8["E"] + 4.0 / 3.0) < 0.1
+    assert abs(c24["E"] + 4.0 / 3.0) < 3e-2
+
+
+# --------------------------------------------------------------------------- invariants
+
+def test_invariants_dodecahedron():
+    V = I.dodecahedron()
+    o = O.OracleCTMRG(V, 1.0 / 0.5, 8)
+    for _ in range(6):
+        r = o.step(keep_cext=True)
+        assert r.asym <= 1e-13
+        assert math.isclose(np.sum(r.w ** 4), 1.0, rel_tol=1e-13)
+        rank = int(np.sum(np.abs(r.lam) > 1e-13 * abs(r.lam[0])))
+        assert -1e-15 <= r.S_E <= math.log(rank) + 1e-12
+        assert np.abs(r.P - r.P.transpose(0, 2, 1)).max() <= 1e-12
+        # rho = C'^4 is positive semi-definite
+        assert np.all(r.lam ** 4 >= 0)
+        assert np.abs(r.U.T @ r.U - np.eye(r.m_eff)).max() <= 1e-12
+
+
+def _dodeca_obs(V, m=8, steps=40, s0=0):
+    o = O.OracleCTMRG(V, 1.0 / 0.5, m, s0=s0)
+    for _ in range(steps):
+        o.step()
+    return o.observables()
+
+
+def test_relabelling_invariance():
+    """Observables depend only on dot products: a vertex permutation (boundary spin kept) and a
+    global rotation leave them unchanged; so does moving the boundary to any other vertex."""
+    V = I.dodecahedron()
+    ref = _dodeca_obs(V)
+    perm = I.random_permutation(3, 20)
+    a = _dodeca_obs(V[perm])
+    b = _dodeca_obs(V @ I.random_rotation(5).T)
+    c = _dodeca_obs(V, s0=13)
+    for obs in (a, b, c):
+        for key in ("f", "E", "M", "S_E", "ln_kappa_ratio"):
+            assert abs(obs[key] - ref[key]) <= 1e-10 * max(1.0, abs(ref[key])), key
+
+
+def test_free_and_fixed_boundary_agree_above_tc():
+    K = 1.0 / 2.8
+    a = O.run_fixed_point(I.ising(), K, 16, bc="fixed", tol=1e-13)[1]
+    b = O.run_fixed_point(I.ising(), K, 16, bc="free", tol=1e-13)[1]
+    assert abs(a["f"] - b["f"]) <= 1e-11 * abs(a["f"])
+    assert abs(b["M"]) < 1e-8
