@@ -1,0 +1,178 @@
+/*
+ * ctmrg.h -- C ABI of the MI355X (gfx950) CTMRG library.
+ *
+ * The library runs the corner-transfer-matrix renormalization group step of
+ * Ueda, Okunishi, Yunoki and Nishino, "Corner transfer matrix renormalization
+ * group analysis of the two-dimensional dodecahedron model" (Sec. III,
+ * Algorithm 3) for a q-state vector-spin model on the square lattice whose
+ * Boltzmann weight sits on every other plaquette (Sec. II, Eqs. 1-2):
+ *
+ *   W[s,sg,s',sg'] = exp(K (v_s.v_sg + v_sg.v_sg' + v_sg'.v_s' + v_s'.v_s)),  K = 1/T,
+ *
+ * with the corners of a plaquette in the cyclic order s, sg, sg', s' (s and s'
+ * are the two legs that border the same edge of the extended corner).
+ *
+ * State: the corner matrix is kept diagonal, C = diag(omega) (m values), and the
+ * half-row transfer tensor P is stored as q symmetric m x m slices P_s, laid out
+ * side by side as the m x (q m) row-major matrix A[gamma][s*m + alpha] = P_s[gamma][alpha]
+ * (the paper's P with its (state, spin) column index).  Rows and columns beyond
+ * the current kept dimension m_eff are zero.  Every combined index of an
+ * (m q) x (m q) matrix is spin-major: row (s, alpha) -> s*m + alpha.
+ *
+ * One step (ctmrg_step):
+ *   1. X_{s sg} = P_s Omega P_sg for all q^2 spin pairs   (Algorithm 3, the product P^t P')
+ *   2. C'_{s' sg'} = sum_{s,sg} W[s,sg,s',sg'] X_{s sg}     (the product with w; C' is (mq)x(mq))
+ *   3. all eigenvalues of C'; eigenvectors of the m largest |lambda| (the EigenExa call)
+ *   4. keep m_eff <= m of them without splitting a multiplet (|l_j|-|l_{j+1}| > gap_tol |l_1|)
+ *   5. P~_{sg'} = sum_{s'} U_{s'}^t (sum_{s,sg} W[s,sg,s',sg'] P_s U_sg)  (second Sub-CTMRG and U^t X)
+ *   6. P <- P~ / max|P~|;  Omega <- lambda_kept / (sum over all mq eigenvalues of lambda^4)^(1/4)
+ *   7. S_E = -sum w^4 ln w^4 over all eigenvalues (Eq. 6), Delta = max_j |w_j^4(k) - w_j^4(k-1)|.
+ *
+ * Memory and ownership: every call copies its host inputs; outputs go to
+ * caller-provided host memory.  The context owns all device memory it uses
+ * (allocated by ctmrg_init, freed by ctmrg_destroy).  A context is bound to the
+ * device that was current at ctmrg_init and to one HIP stream (its own, or the
+ * caller's hip_stream); contexts are not thread-safe, use one per thread.
+ *
+ * Errors: every call returns a ctmrg_status; no C++ exception crosses the ABI.
+ * The message of the last failure is available from ctmrg_last_error.
+ */
+#ifndef CTMRG_H
+#define CTMRG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CTMRG_OK = 0,
+    CTMRG_E_INVALID_ARG = 1,   /* bad size, null pointer, non-unit vector, K <= 0, ... */
+    CTMRG_E_OUT_OF_MEMORY = 2, /* device or host allocation failed */
+    CTMRG_E_HIP = 3,           /* a HIP runtime call failed */
+    CTMRG_E_NOT_CONVERGED = 4, /* max_steps reached; the state is kept and can be resumed */
+    CTMRG_E_NUMERICAL = 5,     /* NaN/Inf, or a bounded kernel wait hit its limit */
+    CTMRG_E_STATE = 6,         /* wrong call order (e.g. observables before two steps) */
+    CTMRG_E_UNSUPPORTED = 7    /* option not available in this build */
+} ctmrg_status;
+
+typedef enum { CTMRG_FP64 = 0, CTMRG_FP32 = 1 } ctmrg_precision;
+typedef enum { CTMRG_BC_FIXED = 0, CTMRG_BC_FREE = 1 } ctmrg_bc;
+
+typedef struct {
+    int precision;        /* ctmrg_precision of the contractions; the eigensolver is always FP64 */
+    int bc;               /* ctmrg_bc: fixed (all boundary spins = boundary_spin) or free      */
+    int boundary_spin;    /* vertex index of the fixed boundary spin (the paper's s = 1)       */
+    int band;             /* eigensolver half-bandwidth: 16 or 32 (default)                    */
+    double gap_tol;       /* multiplet gap, relative to |lambda_1| (default 1e-10)             */
+    double rank_tol;      /* eigenvalues with |l| <= rank_tol |l_1| are never kept (1e-13)     */
+    void *hip_stream;     /* hipStream_t to run on; NULL = a stream owned by the context       */
+} ctmrg_options;
+
+typedef struct {
+    double f;              /* free energy per site, -(T/2) ln kappa_W                            */
+    double E;              /* energy per site from the central plaquette, (1/2) <h_4>           */
+    double M;              /* magnetization, Eq. 5 (fixed BC: v_{s0}.v_s; free BC: |<v_s>|)      */
+    double S_E;            /* entanglement entropy of the last step, Eq. 6                      */
+    double ln_kappa_W;     /* ln of the partition function per vertex from the normalizations  */
+    double ln_kappa_ratio; /* the same from Z_d Z_b / Z_h^2 on the current state                 */
+    double delta;          /* convergence measure of the last step                              */
+    double c_paper;        /* |1 - S_E(k)/S_E(k-1)|, the paper's stopping quantity              */
+    int m_eff;             /* kept dimension of the last step                                   */
+    int steps;             /* steps taken since init / import                                   */
+} ctmrg_observables_t;
+
+typedef struct ctmrg_ctx ctmrg_ctx;
+
+/* Defaults: FP64, fixed boundary, boundary_spin 0, band 32, gap_tol 1e-10, rank_tol 1e-13. */
+ctmrg_status ctmrg_default_options(ctmrg_options *opt);
+
+/* Create a context for q spins (vertex_vectors: q x dim row-major unit vectors,
+ * copied), coupling K = 1/T > 0 and cutoff m >= 1.  opt may be NULL (defaults).
+ * The state is initialized as in Algorithm 3: P_s = [delta_{s,s0}] (fixed) or
+ * [1] (free), Omega = [1].  Requires a gfx950 device; allocates all memory. */
+ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, int m, const ctmrg_options *opt,
+                        ctmrg_ctx **out);
+
+/* Change K (rebuilds W) and reset the state to the initial one; buffers are reused. */
+ctmrg_status ctmrg_set_K(ctmrg_ctx *ctx, double K);
+
+/* Run nsteps CTMRG steps.  delta_out (nullable) receives Delta of the last step. */
+ctmrg_status ctmrg_step(ctmrg_ctx *ctx, int nsteps, double *delta_out);
+
+/* Step until Delta < tol (after at least two steps) or max_steps steps were taken.
+ * Returns CTMRG_E_NOT_CONVERGED if max_steps is reached (the state is kept). */
+ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *ctx, double tol, int max_steps, int *steps_out, double *delta_out);
+
+/* Observables of the current state (needs >= 2 steps).  kept_spectrum (nullable,
+ * m entries) receives omega (normalized kept eigenvalues, zero padded). */
+ctmrg_status ctmrg_observables(ctmrg_ctx *ctx, ctmrg_observables_t *out, double *kept_spectrum);
+
+/* Fixed-point adjoint (dF/dK, d2F/dK2).  Not available in this build:
+ * returns CTMRG_E_UNSUPPORTED. */
+ctmrg_status ctmrg_backward(ctmrg_ctx *ctx, const double obs_bar[3], double *K_bar, double *d2F_dK2);
+
+/* Checkpoint of the state (P, Omega, the normalization history, step count).
+ * Call with host_buf NULL to get the size in *bytes. */
+ctmrg_status ctmrg_export_state(ctmrg_ctx *ctx, void *host_buf, size_t *bytes);
+ctmrg_status ctmrg_import_state(ctmrg_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Replace the state by caller data: P as q slices of d x d (P[(s*d + a)*d + b]),
+ * omega (d values), d <= m.  The normalization history is reset. */
+ctmrg_status ctmrg_set_state(ctmrg_ctx *ctx, int d, const double *P, const double *omega);
+
+/* Device bytes a context with these sizes allocates. */
+ctmrg_status ctmrg_workspace_size(int q, int m, const ctmrg_options *opt, size_t *bytes);
+
+/* Inspection of device buffers (host copies), for tests and checkpoints:
+ *  CTMRG_BUF_P        m x (q m)  current P in the A layout above
+ *  CTMRG_BUF_OMEGA    m          current omega (zero padded)
+ *  CTMRG_BUF_SPECTRUM q m        all eigenvalues of the last C', ascending
+ *  CTMRG_BUF_U        (q m) x m  kept eigenvectors of the last step (row-major, zero columns past m_eff)
+ *  CTMRG_BUF_CEXT     (q m)^2    C' of the last ctmrg_extend call (row-major)
+ *  CTMRG_BUF_W        q^2 x q^2  the weight matrix W[(s,sg),(s',sg')]                  */
+typedef enum {
+    CTMRG_BUF_P = 0,
+    CTMRG_BUF_OMEGA = 1,
+    CTMRG_BUF_SPECTRUM = 2,
+    CTMRG_BUF_U = 3,
+    CTMRG_BUF_CEXT = 4,
+    CTMRG_BUF_W = 5
+} ctmrg_buffer;
+ctmrg_status ctmrg_get_buffer(ctmrg_ctx *ctx, int which, double *host_dst, size_t count);
+
+/* Steps 1-2 only (extension and W-mix) on the current state; C' stays readable
+ * through CTMRG_BUF_CEXT until the next step. */
+ctmrg_status ctmrg_extend(ctmrg_ctx *ctx);
+
+/* Standalone use of the eigensolver on a host symmetric n x n matrix (row-major,
+ * lower triangle read): all eigenvalues ascending (evals, n values) and the k
+ * eigenvectors of largest |lambda| (evecs, n x k row-major, sign convention:
+ * the first entry of largest magnitude is positive), ordered by descending
+ * |lambda|, ties to the larger lambda.  kept_vals receives those k eigenvalues.
+ * band as in ctmrg_options (0 = default). */
+ctmrg_status ctmrg_eigh_topk(int n, const double *A, int k, int band, double *evals, double *kept_vals,
+                             double *evecs);
+
+/* Stage timing with HIP events on the context's stream.  While enabled, each
+ * step synchronizes once more at its end and accumulates the device time of
+ * its stages (milliseconds, summed over the steps since enabling):
+ *   0 extension products X        1 W-mix of X (C')          2 dense->band
+ *   3 band->tridiagonal           4 bisection (all values)    5 selection/cut/entropy
+ *   6 inverse iteration           7 orthonormalization        8 back-transform (band)
+ *   9 back-transform (dense)     10 half-row products Y      11 W-mix of Y
+ *  12 projection U^T Z           13 normalization            14 whole step
+ * Enabling resets the sums. */
+#define CTMRG_NUM_STAGES 15
+ctmrg_status ctmrg_set_profiling(ctmrg_ctx *ctx, int enable);
+ctmrg_status ctmrg_get_stage_times(ctmrg_ctx *ctx, double *ms, int *nsteps);
+
+const char *ctmrg_last_error(const ctmrg_ctx *ctx);
+void ctmrg_destroy(ctmrg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTMRG_H */

@@ -107,7 +107,7 @@ int oracle_jacobi(int n, double *A, double *evals, double *evecs, int max_sweeps
                 ++rotations;
             }
             /* Rows: A <- J^T A (pairs of rows p,q). */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= 128)
             for (int i = 0; i < half; ++i) {
                 if (!rot[i].active) continue;
                 double *rp = A + (size_t)rot[i].p * n;
@@ -120,7 +120,7 @@ int oracle_jacobi(int n, double *A, double *evals, double *evecs, int max_sweeps
                 }
             }
             /* Columns: A <- A J, and the eigenvector matrix V <- V J. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= 128)
             for (int k = 0; k < n; ++k) {
                 double *ak = A + (size_t)k * n;
                 double *vk = evecs + (size_t)k * n;

@@ -1,0 +1,125 @@
+// Shared device helpers for the CTMRG library (gfx950, HIP).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+#define CTMRG_DEVINL __device__ __forceinline__
+
+// Agent-scope fences: make this thread's global stores visible to every
+// workgroup of the device, and make other workgroups' stores visible to it.
+CTMRG_DEVINL void fence_release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+CTMRG_DEVINL void fence_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+CTMRG_DEVINL unsigned atomic_load_acquire(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+CTMRG_DEVINL void atomic_store_release(unsigned *p, unsigned v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+CTMRG_DEVINL unsigned atomic_add_acqrel(unsigned *p, unsigned v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Error flags raised by kernels (bitwise OR into a device word).
+enum {
+    KERR_BARRIER_TIMEOUT = 1,
+    KERR_PIPELINE_TIMEOUT = 2,
+    KERR_NONFINITE = 4,
+    KERR_NO_CONVERGENCE = 8,
+};
+CTMRG_DEVINL void raise_error(unsigned *err, unsigned code)
+{
+    __hip_atomic_fetch_or(err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin limit of every bounded wait (each iteration sleeps ~64 clocks).
+#define CTMRG_SPIN_LIMIT (1u << 26)
+
+// Grid-wide barrier for a launch whose workgroups are all resident (cooperative
+// launch).  bar[0] counts arrivals, bar[1] is the generation.  `gen` is the
+// generation this workgroup read at kernel start; it is advanced on each call.
+// Returns false (and raises KERR_BARRIER_TIMEOUT) if the wait hit the spin limit.
+CTMRG_DEVINL bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, unsigned *err)
+{
+    __shared__ int ok_shared;
+    fence_release_agent();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned arrived = atomic_add_acqrel(&bar[0], 1u);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomic_store_release(&bar[1], gen + 1u);
+        } else {
+            unsigned spins = 0;
+            while (atomic_load_acquire(&bar[1]) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > CTMRG_SPIN_LIMIT) {
+                    raise_error(err, KERR_BARRIER_TIMEOUT);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        ok_shared = ok;
+    }
+    gen += 1u;
+    __syncthreads();
+    fence_acquire_agent();
+    return ok_shared != 0;
+}
+
+// Block-wide sum of one double per thread (blockDim.x a multiple of 64, <= 1024).
+CTMRG_DEVINL double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+CTMRG_DEVINL double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <int NT>
+CTMRG_DEVINL double block_sum(double v, double *red /* >= NT/64 doubles */)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    return s;
+}
+
+template <int NT>
+CTMRG_DEVINL double block_max(double v, double *red)
+{
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < NT / 64; ++i) s = fmax(s, red[i]);
+    return s;
+}
+
+// Counter-based uniform random number in [-1, 1) (SplitMix64 finalizer of a 64-bit key).
+CTMRG_DEVINL double hash_uniform(uint64_t key)
+{
+    uint64_t z = key + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}

@@ -1,0 +1,542 @@
+// Context, step orchestration and the C ABI declared in include/ctmrg.h.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "contract.h"
+#include "ctmrg.h"
+#include "eig.h"
+
+using namespace ctm;
+
+struct ctmrg_ctx {
+    int q = 0, dim = 0, m = 0, N = 0;
+    double K = 0.0;
+    ctmrg_options opt{};
+    std::vector<double> V;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // device state and work buffers
+    double *dV = nullptr, *dW = nullptr, *dWH = nullptr;
+    double *dA = nullptr, *dOA = nullptr, *dPt = nullptr;
+    double *dOmega = nullptr, *dOmNew = nullptr, *dSel = nullptr;
+    double *dX = nullptr, *dC = nullptr, *dU = nullptr;
+    double *dPart = nullptr, *dObs = nullptr, *dH = nullptr, *dWork = nullptr;
+    size_t work_elems = 0;
+    Book *dBook = nullptr;
+    PostOut *dPost = nullptr;
+    PostOut *hPost = nullptr;
+    EigWork eig;
+    // host-side status
+    int m_eff = 1;
+    int steps = 0;
+    double delta = INFINITY;
+    double c_paper = INFINITY;
+    double S_last = 0.0;
+    bool have_U = false;
+    bool cext_valid = false;
+    // stage timing (HIP events on the context's stream)
+    bool profile = false;
+    hipEvent_t ev[MK_COUNT] = {};
+    double stage_ms[MK_COUNT] = {};
+    int timed_steps = 0;
+    std::string err;
+};
+
+namespace {
+
+const uint32_t kStateMagic = 0x534d5443u;  // "CTMS"
+
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t q, m, m_eff, steps, bc, s0;
+    double K, delta, c_paper;
+    Book book;
+};
+
+ctmrg_status fail(ctmrg_ctx *c, ctmrg_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+ctmrg_status hip_fail(ctmrg_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, e == hipErrorOutOfMemory ? CTMRG_E_OUT_OF_MEMORY : CTMRG_E_HIP,
+                std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr)                                   \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+    } while (0)
+
+bool valid_band(int b) { return b == 16 || b == 32; }
+
+ctmrg_status check_device(ctmrg_ctx *c)
+{
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(c, hipGetDeviceProperties(&prop, dev));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(c, CTMRG_E_UNSUPPORTED, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+    c->device = dev;
+    return CTMRG_OK;
+}
+
+void free_all(ctmrg_ctx *c)
+{
+    double *bufs[] = {c->dV, c->dW, c->dWH, c->dA, c->dOA, c->dPt, c->dOmega, c->dOmNew, c->dSel,
+                      c->dX, c->dC, c->dU, c->dPart, c->dObs, c->dH, c->dWork};
+    for (double *p : bufs)
+        if (p) (void)hipFree(p);
+    if (c->dBook) (void)hipFree(c->dBook);
+    if (c->dPost) (void)hipFree(c->dPost);
+    if (c->hPost) (void)hipHostFree(c->hPost);
+    eig_free(c->eig);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    for (int i = 0; i < MK_COUNT; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+}
+
+size_t context_bytes(int q, int m, int band)
+{
+    const size_t N = (size_t)q * m;
+    const size_t q4 = (size_t)q * q * q * q;
+    size_t s = 0;
+    s += sizeof(double) * (q * 3 + 2 * q4);
+    s += sizeof(double) * 3 * (size_t)m * N;
+    s += sizeof(double) * (3 * (size_t)m + 8);
+    s += sizeof(double) * 2 * N * N;
+    s += sizeof(double) * N * m;
+    s += sizeof(double) * (4096 + 64 + q + q4 + 64 * q4);
+    s += sizeof(Book) + sizeof(PostOut);
+    s += eig_bytes((int)N, m, band);
+    return s;
+}
+
+ctmrg_status reset_state(ctmrg_ctx *c)
+{
+    HIPCHK(c, init_state(c->dA, c->dOmega, c->q, c->m, c->opt.bc, c->opt.boundary_spin, c->dBook, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->m_eff = 1;
+    c->steps = 0;
+    c->delta = INFINITY;
+    c->c_paper = INFINITY;
+    c->S_last = 0.0;
+    c->have_U = false;
+    c->cext_valid = false;
+    return CTMRG_OK;
+}
+
+ctmrg_status check_kernel_errors(ctmrg_ctx *c)
+{
+    unsigned e = eig_take_errors(c->eig);
+    if (e & (KERR_BARRIER_TIMEOUT | KERR_PIPELINE_TIMEOUT))
+        return fail(c, CTMRG_E_NUMERICAL, "a bounded kernel wait hit its spin limit (code " + std::to_string(e) + ")");
+    if (e & KERR_NONFINITE) return fail(c, CTMRG_E_NUMERICAL, "inverse iteration produced a non-finite vector");
+    return CTMRG_OK;
+}
+
+ctmrg_status one_step(ctmrg_ctx *c)
+{
+    const int q = c->q, m = c->m, N = c->N;
+    hipStream_t s = c->stream;
+    c->eig.marks = c->profile ? c->ev : nullptr;
+    mark(c->eig, MK_START, s);
+    // extension: X = A^T Omega A, C' = W-mix(X)
+    HIPCHK(c, extension_products(c->dA, c->dOmega, c->dOA, c->dX, q, m, s));
+    mark(c->eig, MK_EXT, s);
+    HIPCHK(c, weight_mix(c->dW, c->dX, c->dC, q, m, s));
+    mark(c->eig, MK_WMIX1, s);
+    c->cext_valid = false;
+    // eigenvalues, selection, normalization, entropy, convergence
+    HIPCHK(c, eig_values(c->eig, c->dC, N, N, s));
+    HIPCHK(c, eig_post(c->eig, N, m, c->opt.gap_tol, c->opt.rank_tol, c->dOmega, c->dOmNew, c->dSel, c->dPost, s));
+    mark(c->eig, MK_POST, s);
+    HIPCHK(c, hipMemcpyAsync(c->hPost, c->dPost, sizeof(PostOut), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    ctmrg_status st = check_kernel_errors(c);
+    if (st != CTMRG_OK) return st;
+    const PostOut po = *c->hPost;
+    if (!std::isfinite(po.n_C) || !(po.n_C > 0.0) || !std::isfinite(po.S_E))
+        return fail(c, CTMRG_E_NUMERICAL, "non-finite spectrum of the extended corner");
+    // eigenvectors of the kept states
+    HIPCHK(c, eig_vectors(c->eig, nullptr, 0, N, po.m_eff, c->dSel, po.nclusters, c->dU, m, s));
+    // half-row: Y = A^T U~, Z = W-mix(Y), P~ = U^T Z
+    HIPCHK(c, halfrow_products(c->dA, c->dU, c->dX, q, m, s));
+    mark(c->eig, MK_HALF, s);
+    HIPCHK(c, weight_mix(c->dW, c->dX, c->dC, q, m, s));
+    mark(c->eig, MK_WMIX2, s);
+    HIPCHK(c, projection(c->dU, c->dC, c->dPt, q, m, s));
+    mark(c->eig, MK_PROJ, s);
+    HIPCHK(c, normalize_and_book(c->dPt, c->dA, q, m, c->dPart, c->dBook, &c->dPost->n_C, &c->dPost->S_E, s));
+    HIPCHK(c, hipMemcpyAsync(c->dOmega, c->dOmNew, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+    mark(c->eig, MK_NORM, s);
+    if (c->profile) {
+        HIPCHK(c, hipStreamSynchronize(s));
+        // stage i spans marks (from[i], to[i])
+        static const int from[] = {MK_START, MK_EXT, MK_WMIX1, MK_STAGE1, MK_BULGE, MK_BISECT, MK_VEC_START, MK_INVIT,
+                                   MK_NS, MK_BT2, MK_BT1, MK_HALF, MK_WMIX2, MK_PROJ};
+        static const int to[] = {MK_EXT, MK_WMIX1, MK_STAGE1, MK_BULGE, MK_BISECT, MK_POST, MK_INVIT, MK_NS,
+                                 MK_BT2, MK_BT1, MK_HALF, MK_WMIX2, MK_PROJ, MK_NORM};
+        for (int i = 0; i < 14; ++i) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev[from[i]], c->ev[to[i]]));
+            c->stage_ms[i] += ms;
+        }
+        float tot = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&tot, c->ev[MK_START], c->ev[MK_NORM]));
+        c->stage_ms[14] += tot;
+        c->timed_steps += 1;
+    }
+    c->eig.marks = nullptr;
+    c->c_paper = (c->steps > 0 && c->S_last != 0.0) ? fabs(1.0 - po.S_E / c->S_last) : INFINITY;
+    c->S_last = po.S_E;
+    c->m_eff = po.m_eff;
+    c->delta = po.delta;
+    c->have_U = true;
+    c->steps += 1;
+    return CTMRG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctmrg_status ctmrg_default_options(ctmrg_options *opt)
+{
+    if (!opt) return CTMRG_E_INVALID_ARG;
+    opt->precision = CTMRG_FP64;
+    opt->bc = CTMRG_BC_FIXED;
+    opt->boundary_spin = 0;
+    opt->band = 32;
+    opt->gap_tol = 1e-10;
+    opt->rank_tol = 1e-13;
+    opt->hip_stream = nullptr;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_workspace_size(int q, int m, const ctmrg_options *opt, size_t *bytes)
+{
+    if (q < 2 || m < 1 || !bytes) return CTMRG_E_INVALID_ARG;
+    ctmrg_options o;
+    ctmrg_default_options(&o);
+    if (opt) o = *opt;
+    if (!valid_band(o.band)) return CTMRG_E_INVALID_ARG;
+    *bytes = context_bytes(q, m, o.band);
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, int m, const ctmrg_options *opt,
+                        ctmrg_ctx **out)
+{
+    if (!out) return CTMRG_E_INVALID_ARG;
+    *out = nullptr;
+    if (q < 2 || dim < 1 || dim > 3 || m < 1 || !vertex_vectors || !(K > 0.0) || !std::isfinite(K))
+        return CTMRG_E_INVALID_ARG;
+    for (int s = 0; s < q; ++s) {
+        double n2 = 0.0;
+        for (int x = 0; x < dim; ++x) n2 += vertex_vectors[s * dim + x] * vertex_vectors[s * dim + x];
+        if (fabs(sqrt(n2) - 1.0) > 1e-10) return CTMRG_E_INVALID_ARG;
+    }
+    ctmrg_options o;
+    ctmrg_default_options(&o);
+    if (opt) o = *opt;
+    if (!valid_band(o.band) || o.boundary_spin < 0 || o.boundary_spin >= q || (o.bc != 0 && o.bc != 1))
+        return CTMRG_E_INVALID_ARG;
+    if (o.precision != CTMRG_FP64) return CTMRG_E_UNSUPPORTED;
+    const long N = (long)q * m;
+    if (N > 65536) return CTMRG_E_INVALID_ARG;
+
+    ctmrg_ctx *c = new (std::nothrow) ctmrg_ctx();
+    if (!c) return CTMRG_E_OUT_OF_MEMORY;
+    c->q = q; c->dim = dim; c->m = m; c->N = (int)N; c->K = K; c->opt = o;
+    c->V.assign(vertex_vectors, vertex_vectors + (size_t)q * dim);
+    ctmrg_status st = check_device(c);
+    if (st != CTMRG_OK) { *out = c; return st; }
+    if (o.hip_stream) {
+        c->stream = (hipStream_t)o.hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            *out = c;
+            return fail(c, CTMRG_E_HIP, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    const size_t q4 = (size_t)q * q * q * q;
+    c->work_elems = 64 * q4;
+    struct Req { double **p; size_t n; };
+    Req reqs[] = {
+        {&c->dV, (size_t)q * dim}, {&c->dW, q4}, {&c->dWH, q4},
+        {&c->dA, (size_t)m * N}, {&c->dOA, (size_t)m * N}, {&c->dPt, (size_t)m * N},
+        {&c->dOmega, (size_t)m}, {&c->dOmNew, (size_t)m}, {&c->dSel, (size_t)m + 8},
+        {&c->dX, (size_t)N * N}, {&c->dC, (size_t)N * N}, {&c->dU, (size_t)N * m},
+        {&c->dPart, 4096}, {&c->dObs, (size_t)64 + q}, {&c->dH, q4}, {&c->dWork, c->work_elems},
+    };
+    for (auto &r : reqs) {
+        hipError_t e = hipMalloc((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
+        if (e != hipSuccess) { *out = c; return hip_fail(c, e, "hipMalloc"); }
+    }
+    hipError_t e = hipMalloc((void **)&c->dBook, sizeof(Book));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->dPost, sizeof(PostOut));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->hPost, sizeof(PostOut), hipHostMallocDefault);
+    if (e == hipSuccess) e = eig_alloc(c->eig, (int)N, m, o.band);
+    if (e != hipSuccess) { *out = c; return hip_fail(c, e, "allocation"); }
+    e = hipMemcpy(c->dV, c->V.data(), sizeof(double) * q * dim, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { *out = c; return hip_fail(c, e, "hipMemcpy"); }
+    e = build_weight(c->dV, q, dim, K, c->dW, c->dWH, c->stream);
+    if (e != hipSuccess) { *out = c; return hip_fail(c, e, "build_weight"); }
+    st = reset_state(c);
+    *out = c;
+    return st;
+}
+
+ctmrg_status ctmrg_set_K(ctmrg_ctx *c, double K)
+{
+    if (!c) return CTMRG_E_INVALID_ARG;
+    if (!(K > 0.0) || !std::isfinite(K)) return fail(c, CTMRG_E_INVALID_ARG, "K must be positive");
+    c->K = K;
+    HIPCHK(c, build_weight(c->dV, c->q, c->dim, K, c->dW, c->dWH, c->stream));
+    return reset_state(c);
+}
+
+ctmrg_status ctmrg_step(ctmrg_ctx *c, int nsteps, double *delta_out)
+{
+    if (!c || nsteps < 0) return CTMRG_E_INVALID_ARG;
+    for (int i = 0; i < nsteps; ++i) {
+        ctmrg_status st = one_step(c);
+        if (st != CTMRG_OK) return st;
+    }
+    if (delta_out) *delta_out = c->delta;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *c, double tol, int max_steps, int *steps_out, double *delta_out)
+{
+    if (!c || max_steps < 0 || !(tol >= 0.0)) return CTMRG_E_INVALID_ARG;
+    int taken = 0;
+    ctmrg_status st = CTMRG_E_NOT_CONVERGED;
+    while (taken < max_steps) {
+        ctmrg_status s1 = one_step(c);
+        if (s1 != CTMRG_OK) { st = s1; break; }
+        ++taken;
+        if (c->steps >= 2 && c->delta < tol) { st = CTMRG_OK; break; }
+    }
+    if (steps_out) *steps_out = taken;
+    if (delta_out) *delta_out = c->delta;
+    if (st == CTMRG_E_NOT_CONVERGED) c->err = "max_steps reached before Delta < tol";
+    return st;
+}
+
+ctmrg_status ctmrg_observables(ctmrg_ctx *c, ctmrg_observables_t *out, double *kept_spectrum)
+{
+    if (!c || !out) return CTMRG_E_INVALID_ARG;
+    if (c->steps < 2 || !c->have_U) return fail(c, CTMRG_E_STATE, "observables need at least two steps");
+    HIPCHK(c, observables(c->dA, c->dOmega, c->dU, c->dW, c->dWH, c->dV, c->dOA, c->dX, c->dH, c->dWork,
+                          c->work_elems, c->q, c->dim, c->m, c->opt.bc, c->opt.boundary_spin, c->dObs, c->stream));
+    double obs[8];
+    Book bk;
+    HIPCHK(c, hipMemcpyAsync(obs, c->dObs, sizeof(obs), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&bk, c->dBook, sizeof(Book), hipMemcpyDeviceToHost, c->stream));
+    if (kept_spectrum)
+        HIPCHK(c, hipMemcpyAsync(kept_spectrum, c->dOmega, sizeof(double) * c->m, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double T = 1.0 / c->K;
+    out->ln_kappa_W = log(bk.nP_prev) + 0.5 * log(bk.nC / bk.nC_prev);
+    out->f = -0.5 * T * out->ln_kappa_W;
+    out->ln_kappa_ratio = log(obs[2]) + log(obs[0]) - 2.0 * log(obs[1]);
+    out->E = 0.5 * obs[3] / obs[2];
+    out->M = obs[5] / obs[6];
+    out->S_E = bk.S;
+    out->delta = c->delta;
+    out->c_paper = (bk.S_prev != 0.0) ? fabs(1.0 - bk.S / bk.S_prev) : INFINITY;
+    out->m_eff = c->m_eff;
+    out->steps = c->steps;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_backward(ctmrg_ctx *c, const double *, double *, double *)
+{
+    return fail(c, CTMRG_E_UNSUPPORTED, "the fixed-point adjoint is not part of this build");
+}
+
+ctmrg_status ctmrg_export_state(ctmrg_ctx *c, void *host_buf, size_t *bytes)
+{
+    if (!c || !bytes) return CTMRG_E_INVALID_ARG;
+    const size_t need = sizeof(StateHeader) + sizeof(double) * ((size_t)c->m * c->N + c->m);
+    if (!host_buf) { *bytes = need; return CTMRG_OK; }
+    if (*bytes < need) return fail(c, CTMRG_E_INVALID_ARG, "buffer too small");
+    StateHeader h{};
+    h.magic = kStateMagic; h.version = 1; h.q = c->q; h.m = c->m; h.m_eff = c->m_eff; h.steps = c->steps;
+    h.bc = c->opt.bc; h.s0 = c->opt.boundary_spin; h.K = c->K; h.delta = c->delta; h.c_paper = c->c_paper;
+    HIPCHK(c, hipMemcpyAsync(&h.book, c->dBook, sizeof(Book), hipMemcpyDeviceToHost, c->stream));
+    char *p = (char *)host_buf;
+    double *pa = (double *)(p + sizeof(StateHeader));
+    HIPCHK(c, hipMemcpyAsync(pa, c->dA, sizeof(double) * (size_t)c->m * c->N, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(pa + (size_t)c->m * c->N, c->dOmega, sizeof(double) * c->m, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    memcpy(p, &h, sizeof(h));
+    *bytes = need;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_import_state(ctmrg_ctx *c, const void *host_buf, size_t bytes)
+{
+    if (!c || !host_buf) return CTMRG_E_INVALID_ARG;
+    const size_t need = sizeof(StateHeader) + sizeof(double) * ((size_t)c->m * c->N + c->m);
+    if (bytes < need) return fail(c, CTMRG_E_INVALID_ARG, "state buffer too small");
+    StateHeader h;
+    memcpy(&h, host_buf, sizeof(h));
+    if (h.magic != kStateMagic || h.version != 1 || h.q != c->q || h.m != c->m)
+        return fail(c, CTMRG_E_INVALID_ARG, "state does not match this context");
+    const double *pa = (const double *)((const char *)host_buf + sizeof(StateHeader));
+    HIPCHK(c, hipMemcpyAsync(c->dA, pa, sizeof(double) * (size_t)c->m * c->N, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->dOmega, pa + (size_t)c->m * c->N, sizeof(double) * c->m, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->dBook, &h.book, sizeof(Book), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->m_eff = h.m_eff; c->steps = h.steps; c->delta = h.delta; c->c_paper = h.c_paper;
+    c->have_U = false;
+    c->cext_valid = false;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_set_state(ctmrg_ctx *c, int d, const double *P, const double *omega)
+{
+    if (!c || !P || !omega || d < 1 || d > c->m) return CTMRG_E_INVALID_ARG;
+    const int q = c->q, m = c->m;
+    const long N = c->N;
+    std::vector<double> A((size_t)m * N, 0.0), om(m, 0.0);
+    for (int s = 0; s < q; ++s)
+        for (int g = 0; g < d; ++g)
+            for (int a = 0; a < d; ++a) A[(size_t)g * N + (size_t)s * m + a] = P[((size_t)s * d + g) * d + a];
+    for (int i = 0; i < d; ++i) om[i] = omega[i];
+    HIPCHK(c, hipMemcpyAsync(c->dA, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->dOmega, om.data(), sizeof(double) * m, hipMemcpyHostToDevice, c->stream));
+    Book b{};
+    b.nC_prev = b.nC = b.nP_prev = b.nP = 1.0;
+    HIPCHK(c, hipMemcpyAsync(c->dBook, &b, sizeof(Book), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->m_eff = d; c->steps = 0; c->delta = INFINITY; c->c_paper = INFINITY;
+    c->have_U = false; c->cext_valid = false;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_extend(ctmrg_ctx *c)
+{
+    if (!c) return CTMRG_E_INVALID_ARG;
+    HIPCHK(c, extension_products(c->dA, c->dOmega, c->dOA, c->dX, c->q, c->m, c->stream));
+    HIPCHK(c, weight_mix(c->dW, c->dX, c->dC, c->q, c->m, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cext_valid = true;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_get_buffer(ctmrg_ctx *c, int which, double *dst, size_t count)
+{
+    if (!c || !dst) return CTMRG_E_INVALID_ARG;
+    const size_t N = c->N, m = c->m;
+    const double *src = nullptr;
+    size_t n = 0;
+    switch (which) {
+    case CTMRG_BUF_P: src = c->dA; n = m * N; break;
+    case CTMRG_BUF_OMEGA: src = c->dOmega; n = m; break;
+    case CTMRG_BUF_SPECTRUM: src = c->eig.evals; n = N; break;
+    case CTMRG_BUF_U:
+        if (!c->have_U) return fail(c, CTMRG_E_STATE, "no eigenvectors yet");
+        src = c->dU; n = N * m; break;
+    case CTMRG_BUF_CEXT:
+        if (!c->cext_valid) return fail(c, CTMRG_E_STATE, "call ctmrg_extend first");
+        src = c->dC; n = N * N; break;
+    case CTMRG_BUF_W: src = c->dW; n = (size_t)c->q * c->q * c->q * c->q; break;
+    default: return fail(c, CTMRG_E_INVALID_ARG, "unknown buffer");
+    }
+    if (count < n) return fail(c, CTMRG_E_INVALID_ARG, "destination too small");
+    HIPCHK(c, hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_eigh_topk(int n, const double *A, int k, int band, double *evals, double *kept_vals,
+                             double *evecs)
+{
+    if (n < 1 || k < 1 || k > n || !A || !evals || !kept_vals || !evecs) return CTMRG_E_INVALID_ARG;
+    if (band == 0) band = 32;
+    if (!valid_band(band)) return CTMRG_E_INVALID_ARG;
+    ctmrg_ctx tmp;
+    ctmrg_status st = check_device(&tmp);
+    if (st != CTMRG_OK) return st;
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return CTMRG_E_HIP;
+    EigWork w;
+    double *dA = nullptr, *dU = nullptr, *dom = nullptr, *domn = nullptr, *dsel = nullptr;
+    PostOut *dpo = nullptr;
+    PostOut po{};
+    hipError_t e = eig_alloc(w, n, k, band);
+    if (e == hipSuccess) e = hipMalloc((void **)&dA, sizeof(double) * (size_t)n * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&dU, sizeof(double) * (size_t)n * k);
+    if (e == hipSuccess) e = hipMalloc((void **)&dom, sizeof(double) * (size_t)k);
+    if (e == hipSuccess) e = hipMalloc((void **)&domn, sizeof(double) * (size_t)k);
+    if (e == hipSuccess) e = hipMalloc((void **)&dsel, sizeof(double) * (size_t)k + 8 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&dpo, sizeof(PostOut));
+    if (e == hipSuccess) e = hipMemsetAsync(dom, 0, sizeof(double) * k, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dA, A, sizeof(double) * (size_t)n * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = eig_values(w, dA, n, n, s);
+    if (e == hipSuccess) e = eig_post(w, n, k, -1.0, -1.0, dom, domn, dsel, dpo, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&po, dpo, sizeof(PostOut), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    unsigned kerr = 0;
+    if (e == hipSuccess) kerr = eig_take_errors(w);
+    if (e == hipSuccess && kerr == 0) e = eig_vectors(w, nullptr, 0, n, po.m_eff, dsel, po.nclusters, dU, k, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(evals, w.evals, sizeof(double) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(kept_vals, dsel, sizeof(double) * k, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(evecs, dU, sizeof(double) * (size_t)n * k, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && kerr == 0) kerr = eig_take_errors(w);
+    (void)hipFree(dA); (void)hipFree(dU); (void)hipFree(dom); (void)hipFree(domn); (void)hipFree(dsel); (void)hipFree(dpo);
+    eig_free(w);
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? CTMRG_E_OUT_OF_MEMORY : CTMRG_E_HIP;
+    if (kerr) return CTMRG_E_NUMERICAL;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_set_profiling(ctmrg_ctx *c, int enable)
+{
+    if (!c) return CTMRG_E_INVALID_ARG;
+    if (enable && !c->ev[0]) {
+        for (int i = 0; i < MK_COUNT; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
+    }
+    c->profile = enable != 0;
+    for (int i = 0; i < MK_COUNT; ++i) c->stage_ms[i] = 0.0;
+    c->timed_steps = 0;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_get_stage_times(ctmrg_ctx *c, double *ms, int *nsteps)
+{
+    if (!c || !ms || !nsteps) return CTMRG_E_INVALID_ARG;
+    for (int i = 0; i < CTMRG_NUM_STAGES; ++i) ms[i] = c->stage_ms[i];
+    *nsteps = c->timed_steps;
+    return CTMRG_OK;
+}
+
+const char *ctmrg_last_error(const ctmrg_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void ctmrg_destroy(ctmrg_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Symmetric eigensolver for the extended corner matrix (the diagonalization
+// step of Algorithm 3, Sec. III): all eigenvalues plus the eigenvectors of
+// the m largest in magnitude.
+//
+//   stage 1  dense -> band (half-bandwidth b): blocked Householder QR of each
+//            b-column panel below the band (one cooperative kernel per panel,
+//            one grid barrier per column) and a two-sided compact-WY update of
+//            the trailing matrix with GEMMs on the matrix cores;
+//   stage 2  band -> tridiagonal: pipelined bulge chasing, one workgroup per
+//            sweep, a sweep trailing its predecessor by three steps;
+//   values   all N eigenvalues by Sturm-count bisection;
+//   vectors  inverse iteration on the tridiagonal for the kept eigenvalues,
+//            re-orthogonalization inside tight clusters, then a Newton-Schulz
+//            polar step (GEMMs) for global orthonormality;
+//   back     the stage-2 reflectors grouped b sweeps at a time into block
+//            reflectors applied in a wavefront order, then the stage-1 panels
+//            as GEMMs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ctm {
+
+struct EigWork {
+    int Nmax = 0, kmax = 0, b = 0, Tmax = 0, nJmax = 0;
+    // stage 1
+    double *Vx = nullptr;      // explicit V of every panel, concatenated (sum n_p * b)
+    double *Tp = nullptr;      // T of every panel (npanel * b * b)
+    double *tau1 = nullptr;    // (npanel * b)
+    double *VW = nullptr;      // n x 2b  [V | W]
+    double *WV = nullptr;      // n x 2b  [W | V]
+    double *Y = nullptr;       // n x b
+    double *X = nullptr;       // n x b
+    double *sm = nullptr;      // 4 * b * b
+    double *part = nullptr;    // cooperative partial sums
+    double *splitk = nullptr;  // split-K partials
+    size_t splitk_elems = 0;
+    // stage 2
+    double *band = nullptr;    // N x 2b column-major band
+    double *refl = nullptr;    // (N * Tmax * b) reflectors
+    double *rtau = nullptr;    // (N * Tmax)
+    unsigned *progress = nullptr;  // N
+    double *T2 = nullptr;      // nJ * Tmax * b * b
+    // tridiagonal
+    double *d = nullptr, *e = nullptr, *e2 = nullptr;  // N
+    double *evals = nullptr;   // N, ascending
+    double *ZT = nullptr;      // N x kmax (row-major, ld kmax)
+    double *Ztmp = nullptr;    // N x kmax
+    double *G = nullptr;       // kmax x kmax
+    double *lu = nullptr;      // inverse-iteration scratch (4 N kmax)
+    int *ipiv = nullptr;       // N kmax
+    int *clist = nullptr;      // kmax: kept indices in ascending-eigenvalue order
+    int *cstart = nullptr;     // kmax + 1 cluster offsets
+    unsigned *bar = nullptr;   // grid barrier words (2)
+    unsigned *err = nullptr;   // kernel error flags
+    hipEvent_t *marks = nullptr;  // optional stage-boundary events (see MarkId)
+};
+
+// Stage boundaries recorded when EigWork::marks is set (indices into marks).
+enum MarkId {
+    MK_START = 0, MK_EXT = 1, MK_WMIX1 = 2, MK_STAGE1 = 3, MK_BULGE = 4, MK_BISECT = 5, MK_POST = 6,
+    MK_INVIT = 7, MK_NS = 8, MK_BT2 = 9, MK_BT1 = 10, MK_HALF = 11, MK_WMIX2 = 12, MK_PROJ = 13,
+    MK_NORM = 14, MK_VEC_START = 15, MK_COUNT = 16
+};
+inline void mark(const EigWork &w, int id, hipStream_t s)
+{
+    if (w.marks) (void)hipEventRecord(w.marks[id], s);
+}
+
+// Post-eigenvalue results shared with the host (one small struct per step).
+struct PostOut {
+    int m_eff;
+    int rank;
+    int nclusters;
+    int pad;
+    double n_C;
+    double S_E;
+    double delta;
+    double lam1;
+    double sum_w4_kept;
+};
+
+hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b);
+void eig_free(EigWork &w);
+size_t eig_bytes(int Nmax, int kmax, int b);
+
+// Stages 1 and 2 plus bisection: A (N x N, row-major, lda) is destroyed.
+// On return w.evals holds all eigenvalues in ascending order.
+hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s);
+
+// Selection of the m largest |lambda| with the multiplet-preserving cut,
+// normalization n_C, entropy, convergence measure against the previous kept
+// spectrum omega_prev (m entries, zero padded).  Writes omega_new (m entries, zero padded) and out.
+hipError_t eig_post(EigWork &w, int N, int m, double gap_tol, double rank_tol, const double *omega4_prev,
+                    double *omega_new, double *selval, PostOut *out_dev, hipStream_t s);
+
+// Eigenvectors of the kept eigenvalues selval[0..me) (in kept order), written
+// to U (N x ldu row-major; columns me..ldu-1 zeroed), sign-fixed.
+// Requires the stage-1/2 data of the last eig_values call on the same matrix.
+hipError_t eig_vectors(EigWork &w, const double *A_reflectors, long lda, int N, int me, const double *selval,
+                       int nclusters, double *U, int ldu, hipStream_t s);
+
+// Error flags accumulated by the kernels (0 = none); clears them.
+unsigned eig_take_errors(EigWork &w);
+
+}  // namespace ctm

@@ -1,0 +1,1079 @@
+// Symmetric eigensolver for the extended corner matrix; see eig.h.
+#include <float.h>
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "eig.h"
+#include "gemm.h"
+
+namespace ctm {
+
+// ============================================================================
+// Geometry shared by host and device
+// ============================================================================
+
+// Panels of stage 1: panel i covers columns [i*b, i*b + b), its Householder
+// vectors act on rows [r0, N) with r0 = i*b + b; panels exist while N - r0 >= 2.
+static int num_panels(int N, int b)
+{
+    int np = 0;
+    for (int p = 0; p + b <= N - 2; p += b) ++np;
+    return np;
+}
+static long panel_v_offset(int N, int b, int pi)
+{
+    long off = 0;
+    for (int i = 0; i < pi; ++i) off += (long)(N - (i + 1) * b) * b;
+    return off;
+}
+
+// Steps of bulge-chasing sweep j (columns j = 0 .. N-3): step t works on rows
+// R_t = [r0, r0 + b) with r0 = j + 1 + t b.
+__host__ __device__ inline int bulge_nsteps(int N, int b, int j)
+{
+    int t = 0;
+    while (true) {
+        const int r0 = j + 1 + t * b;
+        if (r0 >= N) return t;
+        const int r1 = min(r0 + b, N);
+        if (t > 0 && r1 - r0 < 2) return t;
+        ++t;
+        if (r1 >= N) return t;
+    }
+}
+
+static int max_steps(int N, int b) { return N > 2 ? bulge_nsteps(N, b, 0) : 0; }
+
+// ============================================================================
+// Stage 1: Householder QR of one panel (cooperative; one grid barrier per column)
+// ============================================================================
+
+// Rows per workgroup: the panel slice of a workgroup is 4096 doubles (32 KB).
+static inline int pqr_rows(int b) { return 4096 / b; }
+static inline size_t pqr_smem(int b) { return sizeof(double) * (4096 + 256 + 8 + 3 * b + 2 * b * b); }
+
+__global__ void __launch_bounds__(256)
+panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, double *tau_out, double *T_out,
+                double *part, unsigned *bar, unsigned *err)
+{
+    extern __shared__ double sm[];
+    const int rows = 4096 / b;
+    const int RG = 256 / b;  // row groups; column lane = tid % b
+    double *pan = sm;                 // [rows][b]
+    double *red = pan + 4096;         // [RG][b] = 256
+    double *bc = red + 256;           // 8 scalars
+    double *wv = bc + 8;              // [b]  w_c
+    double *sv = wv + b;              // [b]  S_c
+    double *tl = sv + b;              // [b]  taus
+    double *gram = tl + b;            // [b][b]
+    double *Tm = gram + b * b;        // [b][b]
+
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+    const int row0 = g * rows;
+    const int nloc = min(rows, n - row0);
+    unsigned gen = atomic_load_acquire(&bar[1]);
+    double *rowbuf = part + 2L * G * b;          // [2][b]
+    double *gpart = rowbuf + 2L * b;             // [G][b*b]
+
+    for (int idx = tid; idx < rows * b; idx += 256) {
+        const int r = idx / b, c = idx - (idx / b) * b;
+        pan[idx] = (r < nloc) ? A[(long)(r0 + row0 + r) * lda + p + c] : 0.0;
+    }
+    __syncthreads();
+
+    const int cl = tid % b, rg = tid / b;
+    for (int i = 0; i < b; ++i) {
+        const int buf = i & 1;
+        double s = 0.0;
+        if (cl >= i) {
+            for (int r = rg; r < nloc; r += RG)
+                if (row0 + r > i) s += pan[r * b + i] * pan[r * b + cl];
+        }
+        red[rg * b + cl] = s;
+        __syncthreads();
+        if (tid < b) {
+            double t = 0.0;
+            for (int k = 0; k < RG; ++k) t += red[k * b + tid];
+            part[((long)buf * G + g) * b + tid] = t;
+            if (i >= row0 && i < row0 + nloc) rowbuf[buf * b + tid] = pan[(i - row0) * b + tid];
+        }
+        grid_barrier(bar, G, gen, err);
+        if (tid < b) {
+            double t = 0.0;
+            for (int k = 0; k < G; ++k) t += part[((long)buf * G + k) * b + tid];
+            sv[tid] = t;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const double alpha = rowbuf[buf * b + i];
+            const double xn2 = sv[i];
+            double beta, tau, scale;
+            if (xn2 == 0.0) {
+                beta = alpha; tau = 0.0; scale = 0.0;
+            } else {
+                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            bc[0] = beta; bc[1] = tau; bc[2] = scale;
+            tl[i] = tau;
+        }
+        __syncthreads();
+        if (tid < b && tid > i) wv[tid] = rowbuf[buf * b + tid] + bc[2] * sv[tid];
+        __syncthreads();
+        const double beta = bc[0], tau_i = bc[1], scale = bc[2];
+        // columns right of i first (they read the old column i)
+        for (int idx = tid; idx < nloc * b; idx += 256) {
+            const int r = idx / b, c = idx - (idx / b) * b, gr = row0 + r;
+            if (gr < i || c <= i) continue;
+            const double v = (gr == i) ? 1.0 : pan[r * b + i] * scale;
+            pan[idx] -= tau_i * v * wv[c];
+        }
+        __syncthreads();
+        for (int r = tid; r < nloc; r += 256) {
+            const int gr = row0 + r;
+            if (gr < i) continue;
+            pan[r * b + i] = (gr == i) ? beta : pan[r * b + i] * scale;
+        }
+        __syncthreads();
+    }
+
+    // write back R (on and above the diagonal) and V (below), and the explicit V
+    for (int idx = tid; idx < nloc * b; idx += 256) {
+        const int r = idx / b, c = idx - (idx / b) * b, gr = row0 + r;
+        const double val = pan[idx];
+        A[(long)(r0 + gr) * lda + p + c] = val;
+        Vx[(long)gr * b + c] = (gr == c) ? 1.0 : (gr > c ? val : 0.0);
+    }
+    // partial Gram matrix V^T V of this slice
+    for (int idx = tid; idx < b * b; idx += 256) {
+        const int c1 = idx / b, c2 = idx - (idx / b) * b;
+        double s = 0.0;
+        for (int r = 0; r < nloc; ++r) {
+            const int gr = row0 + r;
+            const double v1 = (gr == c1) ? 1.0 : (gr > c1 ? pan[r * b + c1] : 0.0);
+            const double v2 = (gr == c2) ? 1.0 : (gr > c2 ? pan[r * b + c2] : 0.0);
+            s += v1 * v2;
+        }
+        gpart[(long)g * b * b + idx] = s;
+    }
+    grid_barrier(bar, G, gen, err);
+    if (g != 0) return;
+    for (int idx = tid; idx < b * b; idx += 256) {
+        double s = 0.0;
+        for (int k = 0; k < G; ++k) s += gpart[(long)k * b * b + idx];
+        gram[idx] = s;
+        Tm[idx] = 0.0;
+    }
+    __syncthreads();
+    // T (upper triangular): T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] (V^T v_i)[0:i]
+    for (int i = 0; i < b; ++i) {
+        if (tid < i) {
+            double s = 0.0;
+            for (int l = tid; l < i; ++l) s += Tm[tid * b + l] * gram[l * b + i];
+            Tm[tid * b + i] = -tl[i] * s;
+        } else if (tid == i) {
+            Tm[i * b + i] = tl[i];
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < b * b; idx += 256) T_out[idx] = Tm[idx];
+    if (tid < b) tau_out[tid] = tl[tid];
+}
+
+// Epilogue that forms W = X - 1/2 V S and the two concatenated operands
+// [V | W] and [W | V] of the rank-2b trailing update.
+struct EpiWform {
+    const double *X; const double *V; double *VW; double *WV; int b;
+    __device__ void operator()(int i, int j, double acc, int) const
+    {
+        const double w = X[(long)i * b + j] - 0.5 * acc;
+        const double v = V[(long)i * b + j];
+        VW[(long)i * 2 * b + j] = v;
+        VW[(long)i * 2 * b + b + j] = w;
+        WV[(long)i * 2 * b + j] = w;
+        WV[(long)i * 2 * b + b + j] = v;
+    }
+};
+
+// Lower band (r - c in [0, b]) of the stage-1 result into column-major band
+// storage with 2b diagonals (the upper b hold the bulges of stage 2).
+__global__ void extract_band_kernel(const double *A, long lda, int N, int b, double *band)
+{
+    const int ld = 2 * b;
+    const long total = (long)N * ld;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int c = (int)(idx / ld), k = (int)(idx - (long)c * ld);
+        band[idx] = (k <= b && c + k < N) ? A[(long)(c + k) * lda + c] : 0.0;
+    }
+}
+
+// ============================================================================
+// Stage 2: pipelined bulge chasing
+// ============================================================================
+
+__global__ void __launch_bounds__(256)
+bulge_kernel(double *band, int N, int b, double *refl, double *rtau, int Tmax, unsigned *progress, unsigned *err)
+{
+    extern __shared__ double sh[];
+    double *L = sh;
+    double *D = L + b * b;
+    double *B = D + b * b;
+    double *v = B + b * b;
+    double *w = v + b;
+    double *pp = w + b;
+    double *y = pp + b;
+    double *sc = y + b;
+    __shared__ int abort_flag;
+    const int ld = 2 * b;
+    const int tid = threadIdx.x;
+
+    for (int j = blockIdx.x; j < N - 2; j += gridDim.x) {
+        const int ns = bulge_nsteps(N, b, j);
+        const int nsprev = (j > 0) ? bulge_nsteps(N, b, j - 1) : 0;
+        for (int t = 0; t < ns; ++t) {
+            if (j > 0) {
+                if (tid == 0) {
+                    const unsigned need = (unsigned)min(t + 3, nsprev);
+                    unsigned spins = 0;
+                    int ok = 1;
+                    while (atomic_load_acquire(&progress[j - 1]) < need) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++spins > CTMRG_SPIN_LIMIT) {
+                            raise_error(err, KERR_PIPELINE_TIMEOUT);
+                            ok = 0;
+                            break;
+                        }
+                    }
+                    abort_flag = !ok;
+                }
+                __syncthreads();
+                if (abort_flag) return;
+            }
+            fence_acquire_agent();
+            int r0, c0, ncl;
+            if (t == 0) { r0 = j + 1; c0 = j; ncl = 1; }
+            else { r0 = j + 1 + t * b; c0 = j + 1 + (t - 1) * b; ncl = b; }
+            const int r1 = min(r0 + b, N), len = r1 - r0;
+            const int n0 = r1, n1 = min(r1 + b, N), nbl = n1 - n0;
+
+            for (int idx = tid; idx < len * ncl; idx += 256) {
+                const int r = idx / ncl, c = idx - (idx / ncl) * ncl;
+                L[r * b + c] = band[(long)(c0 + c) * ld + (r0 + r - c0 - c)];
+            }
+            for (int idx = tid; idx < len * len; idx += 256) {
+                const int r = idx / len, c = idx - (idx / len) * len;
+                const int rr = max(r, c), cc = min(r, c);
+                D[r * b + c] = band[(long)(r0 + cc) * ld + (rr - cc)];
+            }
+            for (int idx = tid; idx < nbl * len; idx += 256) {
+                const int r = idx / len, c = idx - (idx / len) * len;
+                B[r * b + c] = band[(long)(r0 + c) * ld + (n0 + r - r0 - c)];
+            }
+            __syncthreads();
+            if (tid < 64) {
+                double xs = 0.0;
+                for (int r = 1 + tid; r < len; r += 64) xs += L[r * b] * L[r * b];
+                xs = wave_sum(xs);
+                const double alpha = L[0];
+                double beta, tau, scale;
+                if (xs == 0.0) { beta = alpha; tau = 0.0; scale = 0.0; }
+                else {
+                    beta = -copysign(sqrt(alpha * alpha + xs), alpha);
+                    tau = (beta - alpha) / beta;
+                    scale = 1.0 / (alpha - beta);
+                }
+                if (tid == 0) { sc[0] = beta; sc[1] = tau; }
+                for (int r = tid; r < len; r += 64) v[r] = (r == 0) ? 1.0 : L[r * b] * scale;
+            }
+            __syncthreads();
+            const double beta = sc[0], tau = sc[1];
+            if (tid < b) {
+                const int c = tid;
+                if (c >= 1 && c < ncl) {
+                    double s = 0.0;
+                    for (int r = 0; r < len; ++r) s += v[r] * L[r * b + c];
+                    w[c] = s;
+                }
+            } else if (tid < 2 * b) {
+                const int r = tid - b;
+                if (r < len) {
+                    double s = 0.0;
+                    for (int c = 0; c < len; ++c) s += D[r * b + c] * v[c];
+                    pp[r] = tau * s;
+                }
+            } else if (tid < 3 * b) {
+                const int r = tid - 2 * b;
+                if (r < nbl) {
+                    double s = 0.0;
+                    for (int c = 0; c < len; ++c) s += B[r * b + c] * v[c];
+                    y[r] = s;
+                }
+            }
+            __syncthreads();
+            if (tid < 64) {
+                double s = 0.0;
+                for (int r = tid; r < len; r += 64) s += v[r] * pp[r];
+                s = wave_sum(s);
+                if (tid == 0) sc[2] = 0.5 * tau * s;
+            }
+            __syncthreads();
+            const double kk = sc[2];
+            for (int idx = tid; idx < len * ncl; idx += 256) {
+                const int r = idx / ncl, c = idx - (idx / ncl) * ncl;
+                if (c == 0) L[r * b] = (r == 0) ? beta : 0.0;
+                else L[r * b + c] -= tau * v[r] * w[c];
+            }
+            for (int idx = tid; idx < len * len; idx += 256) {
+                const int r = idx / len, c = idx - (idx / len) * len;
+                const double wr = pp[r] - kk * v[r], wc = pp[c] - kk * v[c];
+                D[r * b + c] -= v[r] * wc + wr * v[c];
+            }
+            for (int idx = tid; idx < nbl * len; idx += 256) {
+                const int r = idx / len, c = idx - (idx / len) * len;
+                B[r * b + c] -= tau * y[r] * v[c];
+            }
+            __syncthreads();
+            for (int idx = tid; idx < len * ncl; idx += 256) {
+                const int r = idx / ncl, c = idx - (idx / ncl) * ncl;
+                band[(long)(c0 + c) * ld + (r0 + r - c0 - c)] = L[r * b + c];
+            }
+            for (int idx = tid; idx < len * len; idx += 256) {
+                const int r = idx / len, c = idx - (idx / len) * len;
+                if (r >= c) band[(long)(r0 + c) * ld + (r - c)] = D[r * b + c];
+            }
+            for (int idx = tid; idx < nbl * len; idx += 256) {
+                const int r = idx / len, c = idx - (idx / len) * len;
+                band[(long)(r0 + c) * ld + (n0 + r - r0 - c)] = B[r * b + c];
+            }
+            for (int r = tid; r < b; r += 256) refl[((long)j * Tmax + t) * b + r] = (r < len) ? v[r] : 0.0;
+            if (tid == 0) rtau[(long)j * Tmax + t] = tau;
+            fence_release_agent();
+            __syncthreads();
+            if (tid == 0) atomic_store_release(&progress[j], (unsigned)(t + 1));
+        }
+    }
+}
+
+__global__ void band_to_tridiag_kernel(const double *band, int N, int b, double *d, double *e, double *e2)
+{
+    const int ld = 2 * b;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
+        d[c] = band[(long)c * ld];
+        const double ec = (c < N - 1) ? band[(long)c * ld + 1] : 0.0;
+        e[c] = ec;
+        e2[c] = ec * ec;
+    }
+}
+
+// ============================================================================
+// Eigenvalues: Sturm-count bisection
+// ============================================================================
+
+// bounds[0..3] = Gershgorin lower, upper, pivmin, ||T|| (max |row sum|)
+__global__ void __launch_bounds__(256) tridiag_bounds_kernel(const double *d, const double *e, int N, double *bounds)
+{
+    __shared__ double red[4];
+    double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 0.0;
+    for (int i = threadIdx.x; i < N; i += 256) {
+        const double el = (i > 0) ? fabs(e[i - 1]) : 0.0;
+        const double er = (i < N - 1) ? fabs(e[i]) : 0.0;
+        lo = fmin(lo, d[i] - el - er);
+        hi = fmax(hi, d[i] + el + er);
+        emax2 = fmax(emax2, er * er);
+    }
+    lo = -block_max<256>(-lo, red);
+    hi = block_max<256>(hi, red);
+    emax2 = block_max<256>(emax2, red);
+    if (threadIdx.x == 0) {
+        const double tn = fmax(fabs(lo), fabs(hi));
+        const double slack = 2.0 * DBL_EPSILON * tn + DBL_MIN;
+        bounds[0] = lo - slack;
+        bounds[1] = hi + slack;
+        bounds[2] = DBL_MIN * fmax(1.0, emax2);
+        bounds[3] = tn;
+    }
+}
+
+__device__ inline int sturm_count(const double *d, const double *e2, int N, double x, double pivmin)
+{
+    int cnt = 0;
+    double q = d[0] - x;
+    if (q < 0.0) ++cnt;
+    for (int i = 1; i < N; ++i) {
+        if (fabs(q) < pivmin) q = -pivmin;
+        q = d[i] - x - e2[i - 1] / q;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+__global__ void __launch_bounds__(256) bisect_kernel(const double *d, const double *e2, int N, const double *bounds, double *evals)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double lo = bounds[0], hi = bounds[1];
+    const double pivmin = bounds[2], tn = bounds[3];
+    const double abstol = DBL_EPSILON * tn;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (hi - lo <= fmax(abstol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
+        if (sturm_count(d, e2, N, mid, pivmin) <= k) lo = mid;
+        else hi = mid;
+    }
+    evals[k] = 0.5 * (lo + hi);
+}
+
+// ============================================================================
+// Selection, cut, normalization, entropy, convergence (one workgroup)
+// ============================================================================
+
+__global__ void __launch_bounds__(256)
+post_eigen_kernel(const double *ev, int N, int m, double gap_tol, double rank_tol, const double *om4_prev,
+                  double *omega_new, double *selval, int *selpos, int *clist, int *cstart, PostOut *out)
+{
+    __shared__ double red[4];
+    __shared__ int s_me, s_nb;
+    __shared__ double s_l1;
+    const int tid = threadIdx.x;
+    const int kk = min(m + 1, N);
+    if (tid == 0) {
+        // merge from both ends of the ascending list: descending |lambda|, ties to the larger lambda
+        int hi = N - 1, lo = 0, nb = 0;
+        for (int q = 0; q < kk; ++q) {
+            int pick;
+            if (lo > hi) break;
+            const double a = fabs(ev[hi]), c = fabs(ev[lo]);
+            if (a >= c) { pick = hi; --hi; }
+            else { pick = lo; ++lo; }
+            selval[q] = ev[pick];
+            selpos[q] = pick;
+        }
+        const double l1 = fabs(selval[0]);
+        const int jmax = min(m, N);
+        int me = -1;
+        for (int j = jmax; j >= 1; --j) {
+            const double aj = fabs(selval[j - 1]);
+            if (aj <= rank_tol * l1) continue;
+            if (j == N || aj - fabs(selval[j]) > gap_tol * l1) { me = j; break; }
+        }
+        if (me < 0) {
+            int c = 0;
+            for (int j = 0; j < jmax; ++j) c += (fabs(selval[j]) > rank_tol * l1) ? 1 : 0;
+            me = max(1, c);
+        }
+        // the kept set in ascending-eigenvalue order is the bottom run [0, nb) of the
+        // ascending list followed by the top run [N - nt, N); bottom picks come in the order 0, 1, 2, ...
+        {
+            int l = 0, bc = 0;
+            for (int q = 0; q < me; ++q) {
+                if (selpos[q] == l) { ++l; ++bc; }
+            }
+            nb = bc;
+        }
+        const int nt = me - nb;
+        for (int q = 0; q < me; ++q) {
+            const int pos = selpos[q];
+            const int slot = (pos < nb) ? pos : nb + (pos - (N - nt));
+            clist[slot] = q;
+        }
+        int ncl = 0;
+        cstart[0] = 0;
+        for (int s = 1; s <= me; ++s) {
+            bool split = true;
+            if (s < me) {
+                const int pa = selpos[clist[s - 1]], pb = selpos[clist[s]];
+                split = !(pb == pa + 1 && ev[pb] - ev[pa] <= 1e-10 * l1);
+            }
+            if (split) cstart[++ncl] = s;
+        }
+        s_me = me;
+        s_nb = ncl;
+        s_l1 = l1;
+        out->m_eff = me;
+        out->nclusters = ncl;
+        out->lam1 = l1;
+    }
+    __syncthreads();
+    const double l1 = s_l1;
+    const int me = s_me;
+    double s4 = 0.0, rk = 0.0;
+    for (int i = tid; i < N; i += 256) {
+        const double x = ev[i] / l1;
+        s4 += (x * x) * (x * x);
+        rk += (fabs(ev[i]) > rank_tol * l1) ? 1.0 : 0.0;
+    }
+    s4 = block_sum<256>(s4, red);
+    rk = block_sum<256>(rk, red);
+    const double nC = l1 * sqrt(sqrt(s4));
+    double se = 0.0;
+    for (int i = tid; i < N; i += 256) {
+        const double wv = ev[i] / nC;
+        const double w4 = (wv * wv) * (wv * wv);
+        if (w4 > 0.0) se -= w4 * log(w4);
+    }
+    se = block_sum<256>(se, red);
+    double dl = 0.0, kept4 = 0.0;
+    for (int j = tid; j < m; j += 256) {
+        const double om = (j < me) ? selval[j] / nC : 0.0;
+        omega_new[j] = om;
+        const double o4 = (om * om) * (om * om);
+        kept4 += o4;
+        const double op = om4_prev[j];
+        dl = fmax(dl, fabs(o4 - (op * op) * (op * op)));
+    }
+    dl = block_max<256>(dl, red);
+    kept4 = block_sum<256>(kept4, red);
+    if (tid == 0) {
+        out->n_C = nC;
+        out->S_E = se;
+        out->delta = dl;
+        out->rank = (int)rk;
+        out->sum_w4_kept = kept4;
+    }
+}
+
+// ============================================================================
+// Eigenvectors of the tridiagonal: inverse iteration
+// ============================================================================
+
+// One thread per tight cluster; the LU scratch of thread c is interleaved
+// (element i of array a at lu[(a*N + i)*nth + c]) so that the lanes of a wave
+// touch adjacent addresses.
+__global__ void __launch_bounds__(64)
+invit_kernel(const double *d, const double *e, int N, const double *selval, const int *clist, const int *cstart,
+             int ncl, double *ZT, int ldz, double *lu, int *ipiv, const double *bounds, unsigned *err)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nth = gridDim.x * blockDim.x;
+    if (c >= ncl) return;
+    const double tn = bounds[3];
+    const double pivmin = fmax(DBL_EPSILON * tn, DBL_MIN);
+#define DL(i) lu[((long)0 * N + (i)) * nth + c]
+#define DD(i) lu[((long)1 * N + (i)) * nth + c]
+#define DU(i) lu[((long)2 * N + (i)) * nth + c]
+#define DU2(i) lu[((long)3 * N + (i)) * nth + c]
+#define IP(i) ipiv[(long)(i) * nth + c]
+#define X(i) ZT[(long)(i) * ldz + j]
+    for (int q = cstart[c]; q < cstart[c + 1]; ++q) {
+        const int j = clist[q];
+        const double lam = selval[j];
+        // LU with partial pivoting of T - lam I
+        for (int i = 0; i < N; ++i) {
+            DD(i) = d[i] - lam;
+            if (i < N - 1) { DL(i) = e[i]; DU(i) = e[i]; }
+            DU2(i) = 0.0;
+        }
+        for (int i = 0; i < N - 1; ++i) {
+            const double di = DD(i), li = DL(i);
+            if (fabs(di) >= fabs(li)) {
+                const double piv = (fabs(di) < pivmin) ? (di < 0.0 ? -pivmin : pivmin) : di;
+                DD(i) = piv;
+                const double f = li / piv;
+                DL(i) = f;
+                DD(i + 1) = DD(i + 1) - f * DU(i);
+                IP(i) = 0;
+            } else {
+                const double f = di / li;
+                DD(i) = li;
+                DL(i) = f;
+                const double tmp = DU(i);
+                DU(i) = DD(i + 1);
+                DD(i + 1) = tmp - f * DD(i + 1);
+                if (i < N - 2) {
+                    DU2(i) = DU(i + 1);
+                    DU(i + 1) = -f * DU(i + 1);
+                }
+                IP(i) = 1;
+            }
+        }
+        if (fabs(DD(N - 1)) < pivmin) DD(N - 1) = (DD(N - 1) < 0.0 ? -pivmin : pivmin);
+        // start vector
+        double nrm = 0.0;
+        for (int i = 0; i < N; ++i) {
+            const double x = hash_uniform(((uint64_t)(j + 1) << 32) ^ (uint64_t)i);
+            X(i) = x;
+            nrm += x * x;
+        }
+        nrm = 1.0 / sqrt(nrm);
+        for (int i = 0; i < N; ++i) X(i) *= nrm;
+        for (int it = 0; it < 3; ++it) {
+            // forward: L with row interchanges
+            for (int i = 0; i < N - 1; ++i) {
+                if (IP(i) == 0) {
+                    X(i + 1) = X(i + 1) - DL(i) * X(i);
+                } else {
+                    const double t = X(i);
+                    X(i) = X(i + 1);
+                    X(i + 1) = t - DL(i) * X(i);
+                }
+            }
+            // backward: U with two superdiagonals
+            X(N - 1) = X(N - 1) / DD(N - 1);
+            if (N > 1) X(N - 2) = (X(N - 2) - DU(N - 2) * X(N - 1)) / DD(N - 2);
+            for (int i = N - 3; i >= 0; --i) X(i) = (X(i) - DU(i) * X(i + 1) - DU2(i) * X(i + 2)) / DD(i);
+            // scale down, then orthogonalize against the earlier members of the cluster
+            double mx = 0.0;
+            for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(X(i)));
+            if (!(mx > 0.0) || !isfinite(mx)) {
+                raise_error(err, KERR_NONFINITE);
+                mx = 1.0;
+            }
+            for (int i = 0; i < N; ++i) X(i) /= mx;
+            for (int qq = cstart[c]; qq < q; ++qq) {
+                const int jp = clist[qq];
+                double dot = 0.0;
+                for (int i = 0; i < N; ++i) dot += ZT[(long)i * ldz + jp] * X(i);
+                for (int i = 0; i < N; ++i) X(i) -= dot * ZT[(long)i * ldz + jp];
+            }
+            nrm = 0.0;
+            for (int i = 0; i < N; ++i) nrm += X(i) * X(i);
+            nrm = (nrm > 0.0) ? 1.0 / sqrt(nrm) : 0.0;
+            for (int i = 0; i < N; ++i) X(i) *= nrm;
+        }
+    }
+#undef DL
+#undef DD
+#undef DU
+#undef DU2
+#undef IP
+#undef X
+}
+
+// H = 1.5 I - 0.5 G (Newton-Schulz step for the polar factor)
+__global__ void ns_matrix_kernel(double *G, int k)
+{
+    const long total = (long)k * k;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / k), j = (int)(idx - (long)i * k);
+        G[idx] = (i == j ? 1.5 : 0.0) - 0.5 * G[idx];
+    }
+}
+
+// ============================================================================
+// Back-transform of stage 2: grouped block reflectors in wavefront order
+// ============================================================================
+//
+// Group (J, t) = reflectors of sweeps J b .. J b + b - 1 at step t; they act on
+// rows [J b + 1 + t b, J b + 1 + t b + 2b - 1).  The stage-2 transform applied to
+// Z is, group J from last to first, G(J,0) then G(J,1) ... , where
+// G(J,t) = H(Jb,t) H(Jb+1,t) ... = I - V T V^T (forward compact WY).
+// G(J,t) only has to follow G(J,t-1) and G(J+1,t), so all groups with the same
+// t + (nJ - 1 - J) are applied by one launch.
+
+__global__ void __launch_bounds__(256)
+bt2_tfactor_kernel(const double *refl, const double *rtau, int N, int b, int Tmax, int nJ, double *T2)
+{
+    extern __shared__ double sh[];
+    double *V = sh;              // [2b][b]
+    double *gram = V + 2 * b * b; // [b][b]
+    double *Tm = gram + b * b;   // [b][b]
+    double *tl = Tm + b * b;     // [b]
+    const int J = blockIdx.x / Tmax, t = blockIdx.x - (blockIdx.x / Tmax) * Tmax;
+    if (J >= nJ) return;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < 2 * b * b; idx += 256) {
+        const int r = idx / b, i = idx - (idx / b) * b;
+        const int j = J * b + i;
+        double val = 0.0;
+        if (j < N - 2 && t < bulge_nsteps(N, b, j) && r - i >= 0 && r - i < b)
+            val = refl[((long)j * Tmax + t) * b + (r - i)];
+        V[idx] = val;
+    }
+    for (int i = tid; i < b; i += 256) {
+        const int j = J * b + i;
+        tl[i] = (j < N - 2 && t < bulge_nsteps(N, b, j)) ? rtau[(long)j * Tmax + t] : 0.0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < b * b; idx += 256) {
+        const int i = idx / b, k = idx - (idx / b) * b;
+        double s = 0.0;
+        for (int r = 0; r < 2 * b; ++r) s += V[r * b + i] * V[r * b + k];
+        gram[idx] = s;
+        Tm[idx] = 0.0;
+    }
+    __syncthreads();
+    for (int i = 0; i < b; ++i) {
+        if (tid < i) {
+            double s = 0.0;
+            for (int l = tid; l < i; ++l) s += Tm[tid * b + l] * gram[l * b + i];
+            Tm[tid * b + i] = -tl[i] * s;
+        } else if (tid == i) {
+            Tm[i * b + i] = tl[i];
+        }
+        __syncthreads();
+    }
+    double *dst = T2 + ((long)J * Tmax + t) * b * b;
+    for (int idx = tid; idx < b * b; idx += 256) dst[idx] = Tm[idx];
+}
+
+constexpr int BT2_NC = 32;
+
+__global__ void __launch_bounds__(256)
+bt2_apply_kernel(double *Z, int ldz, int N, int ncols, int b, int Tmax, int nJ, int wave, const double *refl,
+                 const double *T2)
+{
+    extern __shared__ double sh[];
+    double *V = sh;                    // [2b][b]
+    double *Tm = V + 2 * b * b;        // [b][b]
+    double *Zt = Tm + b * b;           // [2b][NC]
+    double *W = Zt + 2 * b * BT2_NC;   // [b][NC]
+    double *W2 = W + b * BT2_NC;       // [b][NC]
+    const int J = blockIdx.x;
+    const int t = wave - (nJ - 1 - J);
+    if (t < 0 || t >= Tmax) return;
+    if (J * b >= N - 2 || t >= bulge_nsteps(N, b, J * b)) return;
+    const int col0 = blockIdx.y * BT2_NC;
+    const int ncol = min(BT2_NC, ncols - col0);
+    if (ncol <= 0) return;
+    const int base = J * b + 1 + t * b;
+    const int nrow = min(2 * b - 1, N - base);
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < 2 * b * b; idx += 256) {
+        const int r = idx / b, i = idx - (idx / b) * b;
+        const int j = J * b + i;
+        double val = 0.0;
+        if (r < nrow && j < N - 2 && t < bulge_nsteps(N, b, j) && r - i >= 0 && r - i < b)
+            val = refl[((long)j * Tmax + t) * b + (r - i)];
+        V[idx] = val;
+    }
+    const double *Ts = T2 + ((long)J * Tmax + t) * b * b;
+    for (int idx = tid; idx < b * b; idx += 256) Tm[idx] = Ts[idx];
+    for (int idx = tid; idx < 2 * b * BT2_NC; idx += 256) {
+        const int r = idx / BT2_NC, c = idx - (idx / BT2_NC) * BT2_NC;
+        Zt[idx] = (r < nrow && c < ncol) ? Z[(long)(base + r) * ldz + col0 + c] : 0.0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < b * BT2_NC; idx += 256) {
+        const int i = idx / BT2_NC, c = idx - (idx / BT2_NC) * BT2_NC;
+        double s = 0.0;
+        for (int r = i; r < i + b && r < 2 * b; ++r) s += V[r * b + i] * Zt[r * BT2_NC + c];
+        W[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < b * BT2_NC; idx += 256) {
+        const int i = idx / BT2_NC, c = idx - (idx / BT2_NC) * BT2_NC;
+        double s = 0.0;
+        for (int k = i; k < b; ++k) s += Tm[i * b + k] * W[k * BT2_NC + c];
+        W2[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 2 * b * BT2_NC; idx += 256) {
+        const int r = idx / BT2_NC, c = idx - (idx / BT2_NC) * BT2_NC;
+        if (r >= nrow || c >= ncol) continue;
+        double s = 0.0;
+        const int ilo = max(0, r - b + 1), ihi = min(b - 1, r);
+        for (int i = ilo; i <= ihi; ++i) s += V[r * b + i] * W2[i * BT2_NC + c];
+        Z[(long)(base + r) * ldz + col0 + c] = Zt[idx] - s;
+    }
+}
+
+// ============================================================================
+// Final copy with sign convention: each eigenvector is negated if its first
+// entry of largest magnitude is negative.
+// ============================================================================
+__global__ void __launch_bounds__(256)
+sign_fix_copy_kernel(const double *Z, int ldz, int N, int me, double *U, int ldu)
+{
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (j >= me) {
+        for (int i = tid; i < N; i += 256) U[(long)i * ldu + j] = 0.0;
+        return;
+    }
+    double best = -1.0;
+    int bi = 0;
+    for (int i = tid; i < N; i += 256) {
+        const double a = fabs(Z[(long)i * ldz + j]);
+        if (a > best) { best = a; bi = i; }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            const double a = sv[tid + s];
+            const int ai = si[tid + s];
+            if (a > sv[tid] || (a == sv[tid] && ai < si[tid])) { sv[tid] = a; si[tid] = ai; }
+        }
+        __syncthreads();
+    }
+    const double sg = (Z[(long)si[0] * ldz + j] < 0.0) ? -1.0 : 1.0;
+    for (int i = tid; i < N; i += 256) U[(long)i * ldu + j] = sg * Z[(long)i * ldz + j];
+}
+
+// ============================================================================
+// Host drivers
+// ============================================================================
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t eig_bytes(int Nmax, int kmax, int b)
+{
+    const int np = num_panels(Nmax, b);
+    const int Tmax = max_steps(Nmax, b) + 1;
+    const int nJ = (Nmax + b - 1) / b;
+    const int G = (Nmax + pqr_rows(b) - 1) / pqr_rows(b) + 1;
+    size_t s = 0;
+    s += align_up(sizeof(double) * (size_t)panel_v_offset(Nmax, b, np) + 8);
+    s += align_up(sizeof(double) * (size_t)np * b * b + 8);
+    s += align_up(sizeof(double) * (size_t)np * b + 8);
+    s += 2 * align_up(sizeof(double) * (size_t)Nmax * 2 * b);
+    s += 2 * align_up(sizeof(double) * (size_t)Nmax * b);
+    s += align_up(sizeof(double) * 4 * b * b);
+    s += align_up(sizeof(double) * ((size_t)G * (2 * b + b * b) + 2 * b + 64));
+    s += align_up(sizeof(double) * (size_t)std::max<size_t>((size_t)64 * Nmax * std::max(b, 64), (size_t)64 * kmax * kmax + 64 * 64 * 64));
+    s += align_up(sizeof(double) * (size_t)Nmax * 2 * b);
+    s += align_up(sizeof(double) * (size_t)Nmax * Tmax * b);
+    s += align_up(sizeof(double) * (size_t)Nmax * Tmax);
+    s += align_up(sizeof(unsigned) * (size_t)Nmax);
+    s += align_up(sizeof(double) * (size_t)nJ * Tmax * b * b);
+    s += 4 * align_up(sizeof(double) * (size_t)Nmax);
+    s += 2 * align_up(sizeof(double) * (size_t)Nmax * kmax);
+    s += align_up(sizeof(double) * (size_t)kmax * kmax);
+    const size_t kpad = ((size_t)kmax + 63) / 64 * 64;
+    s += align_up(sizeof(double) * 4 * (size_t)Nmax * kpad);
+    s += align_up(sizeof(int) * (size_t)Nmax * kpad);
+    s += 2 * align_up(sizeof(int) * (size_t)(kmax + 2));
+    s += align_up(sizeof(double) * 8) + 2 * align_up(64);
+    return s;
+}
+
+hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
+{
+    w.Nmax = Nmax;
+    w.kmax = kmax;
+    w.b = b;
+    w.Tmax = max_steps(Nmax, b) + 1;
+    w.nJmax = (Nmax + b - 1) / b;
+    const int np = num_panels(Nmax, b);
+    const int G = (Nmax + pqr_rows(b) - 1) / pqr_rows(b) + 1;
+    const size_t kpad = ((size_t)kmax + 63) / 64 * 64;  // threads of invit_kernel
+    w.splitk_elems = std::max<size_t>((size_t)64 * Nmax * std::max(b, 64), (size_t)64 * kmax * kmax + 64 * 64 * 64);
+    struct Req { void **p; size_t bytes; };
+    double *bounds_unused = nullptr;
+    (void)bounds_unused;
+    std::vector<Req> reqs = {
+        {(void **)&w.Vx, sizeof(double) * (size_t)panel_v_offset(Nmax, b, np) + 8},
+        {(void **)&w.Tp, sizeof(double) * (size_t)np * b * b + 8},
+        {(void **)&w.tau1, sizeof(double) * (size_t)np * b + 8},
+        {(void **)&w.VW, sizeof(double) * (size_t)Nmax * 2 * b},
+        {(void **)&w.WV, sizeof(double) * (size_t)Nmax * 2 * b},
+        {(void **)&w.Y, sizeof(double) * (size_t)Nmax * b},
+        {(void **)&w.X, sizeof(double) * (size_t)Nmax * b},
+        {(void **)&w.sm, sizeof(double) * 4 * b * b},
+        {(void **)&w.part, sizeof(double) * ((size_t)G * (2 * b + b * b) + 2 * b + 64)},
+        {(void **)&w.splitk, sizeof(double) * w.splitk_elems},
+        {(void **)&w.band, sizeof(double) * (size_t)Nmax * 2 * b},
+        {(void **)&w.refl, sizeof(double) * (size_t)Nmax * w.Tmax * b},
+        {(void **)&w.rtau, sizeof(double) * (size_t)Nmax * w.Tmax},
+        {(void **)&w.progress, sizeof(unsigned) * (size_t)Nmax},
+        {(void **)&w.T2, sizeof(double) * (size_t)w.nJmax * w.Tmax * b * b},
+        {(void **)&w.d, sizeof(double) * (size_t)Nmax},
+        {(void **)&w.e, sizeof(double) * (size_t)Nmax},
+        {(void **)&w.e2, sizeof(double) * (size_t)Nmax},
+        {(void **)&w.evals, sizeof(double) * (size_t)Nmax},
+        {(void **)&w.ZT, sizeof(double) * (size_t)Nmax * kmax},
+        {(void **)&w.Ztmp, sizeof(double) * (size_t)Nmax * kmax},
+        {(void **)&w.G, sizeof(double) * (size_t)kmax * kmax},
+        {(void **)&w.lu, sizeof(double) * 4 * (size_t)Nmax * kpad},
+        {(void **)&w.ipiv, sizeof(int) * (size_t)Nmax * kpad},
+        {(void **)&w.clist, sizeof(int) * (size_t)(kmax + 2) * 2},
+        {(void **)&w.cstart, sizeof(int) * (size_t)(kmax + 2)},
+        {(void **)&w.bar, 64},
+        {(void **)&w.err, 64},
+    };
+    for (auto &r : reqs) {
+        hipError_t e = hipMalloc(r.p, r.bytes);
+        if (e != hipSuccess) {
+            eig_free(w);
+            return e;
+        }
+    }
+    (void)hipMemset(w.bar, 0, 64);
+    (void)hipMemset(w.err, 0, 64);
+    return hipSuccess;
+}
+
+void eig_free(EigWork &w)
+{
+    void *ptrs[] = {w.Vx, w.Tp, w.tau1, w.VW, w.WV, w.Y, w.X, w.sm, w.part, w.splitk, w.band, w.refl, w.rtau,
+                    w.progress, w.T2, w.d, w.e, w.e2, w.evals, w.ZT, w.Ztmp, w.G, w.lu, w.ipiv, w.clist,
+                    w.cstart, w.bar, w.err};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    w = EigWork();
+}
+
+unsigned eig_take_errors(EigWork &w)
+{
+    unsigned e = 0;
+    (void)hipMemcpy(&e, w.err, sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e) (void)hipMemset(w.err, 0, sizeof(unsigned));
+    return e;
+}
+
+static int splits_for(long tiles, long K, int kmin)
+{
+    long s = 1;
+    while (tiles * s < 512 && K / (s * 2) >= kmin) s *= 2;
+    return (int)s;
+}
+
+static hipError_t launch_coop(const void *fn, dim3 grid, dim3 block, void **args, size_t smem, hipStream_t s)
+{
+    return hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)smem, s);
+}
+
+static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
+{
+    const int b = w.b;
+    const int np = num_panels(N, b);
+    const int rows = pqr_rows(b);
+    const size_t smem = pqr_smem(b);
+    hipError_t e;
+    for (int pi = 0; pi < np; ++pi) {
+        const int p = pi * b, r0 = p + b, n = N - r0;
+        double *Vp = w.Vx + panel_v_offset(N, b, pi);
+        double *Tp = w.Tp + (long)pi * b * b;
+        double *taup = w.tau1 + (long)pi * b;
+        int G = (n + rows - 1) / rows;
+        void *args[] = {&A, &lda, (void *)&r0, (void *)&p, (void *)&n, (void *)&b, &Vp, &taup, &Tp, &w.part, &w.bar, &w.err};
+        e = launch_coop((const void *)panel_qr_kernel, dim3(G), dim3(256), args, smem, s);
+        if (e != hipSuccess) return e;
+        double *A22 = A + (long)r0 * lda + r0;
+        // Y = A22 V
+        {
+            const long tiles = ceil_div(n, 64);
+            const int sp = splits_for(tiles, n, 256);
+            e = gemm_f64_splitk(A_RM{A22, lda}, B_RM{Vp, b}, EpiStore{w.Y, b, 1.0}, n, b, n, sp, w.splitk, s);
+            if (e != hipSuccess) return e;
+        }
+        // X = Y T
+        e = gemm_f64(GEMM_TALL, A_RM{w.Y, b}, B_RM{Tp, b}, EpiStore{w.X, b, 1.0}, n, b, b, s);
+        if (e != hipSuccess) return e;
+        // M = V^T X
+        {
+            const int sp = splits_for(1, n, 128);
+            e = gemm_f64_splitk(A_T{Vp, b}, B_RM{w.X, b}, EpiStore{w.sm, b, 1.0}, b, b, n, sp, w.splitk, s);
+            if (e != hipSuccess) return e;
+        }
+        // S = T^T M
+        e = gemm_f64(GEMM_SMALL, A_T{Tp, b}, B_RM{w.sm, b}, EpiStore{w.sm + b * b, b, 1.0}, b, b, b, s);
+        if (e != hipSuccess) return e;
+        // W = X - 1/2 V S, and the operands [V|W], [W|V]
+        e = gemm_f64(GEMM_TALL, A_RM{Vp, b}, B_RM{w.sm + b * b, b}, EpiWform{w.X, Vp, w.VW, w.WV, b}, n, b, b, s);
+        if (e != hipSuccess) return e;
+        // A22 -= [V|W] [W|V]^T
+        e = gemm_f64(GEMM_LARGE, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, n, 2 * b, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s)
+{
+    if (N > w.Nmax) return hipErrorInvalidValue;
+    const int b = w.b;
+    hipError_t e = stage1(w, A, lda, N, s);
+    if (e != hipSuccess) return e;
+    mark(w, MK_STAGE1, s);
+    hipLaunchKernelGGL(extract_band_kernel, dim3(std::min(4096, ceil_div((long)N * 2 * b, 256))), dim3(256), 0, s, A,
+                       lda, N, b, w.band);
+    if (N > 2) {
+        e = hipMemsetAsync(w.progress, 0, sizeof(unsigned) * N, s);
+        if (e != hipSuccess) return e;
+        const int Tmax = w.Tmax;
+        double *band = w.band;
+        int G = std::min(N - 2, 256);
+        size_t smem = sizeof(double) * (3 * b * b + 4 * b + 4);
+        void *args[] = {&band, (void *)&N, (void *)&b, &w.refl, &w.rtau, (void *)&Tmax, &w.progress, &w.err};
+        e = launch_coop((const void *)bulge_kernel, dim3(G), dim3(256), args, smem, s);
+        if (e != hipSuccess) return e;
+    }
+    mark(w, MK_BULGE, s);
+    hipLaunchKernelGGL(band_to_tridiag_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, s, w.band, N, b, w.d, w.e, w.e2);
+    double *bounds = w.sm + 3 * b * b;
+    hipLaunchKernelGGL(tridiag_bounds_kernel, dim3(1), dim3(256), 0, s, w.d, w.e, N, bounds);
+    hipLaunchKernelGGL(bisect_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, s, w.d, w.e2, N, bounds, w.evals);
+    mark(w, MK_BISECT, s);
+    return hipGetLastError();
+}
+
+hipError_t eig_post(EigWork &w, int N, int m, double gap_tol, double rank_tol, const double *omega4_prev,
+                    double *omega_new, double *selval, PostOut *out_dev, hipStream_t s)
+{
+    if (m > w.kmax) return hipErrorInvalidValue;
+    int *selpos = w.clist + (w.kmax + 2);
+    hipLaunchKernelGGL(post_eigen_kernel, dim3(1), dim3(256), 0, s, w.evals, N, m, gap_tol, rank_tol, omega4_prev,
+                       omega_new, selval, selpos, w.clist, w.cstart, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const double *selval, int nclusters,
+                       double *U, int ldu, hipStream_t s)
+{
+    const int b = w.b;
+    const int ldz = w.kmax;
+    const double *bounds = w.sm + 3 * b * b;
+    hipError_t e;
+    mark(w, MK_VEC_START, s);
+    hipLaunchKernelGGL(invit_kernel, dim3(ceil_div(nclusters, 64)), dim3(64), 0, s, w.d, w.e, N, selval, w.clist,
+                       w.cstart, nclusters, w.ZT, ldz, w.lu, w.ipiv, bounds, w.err);
+    mark(w, MK_INVIT, s);
+    // Newton-Schulz polar orthonormalization: Z <- Z (3/2 I - 1/2 Z^T Z)
+    double *Z = w.ZT, *Zo = w.Ztmp;
+    for (int it = 0; it < 3; ++it) {
+        const long tiles = (long)ceil_div(me, 64) * ceil_div(me, 64);
+        const int sp = splits_for(tiles, N, 256);
+        e = gemm_f64_splitk(A_T{Z, ldz}, B_RM{Z, ldz}, EpiStore{w.G, me, 1.0}, me, me, N, sp, w.splitk, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(ns_matrix_kernel, dim3(std::max(1, std::min(1024, ceil_div((long)me * me, 256)))), dim3(256), 0,
+                           s, w.G, me);
+        e = gemm_f64(GEMM_LARGE, A_RM{Z, ldz}, B_RM{w.G, me}, EpiStore{Zo, ldz, 1.0}, N, me, me, s);
+        if (e != hipSuccess) return e;
+        std::swap(Z, Zo);
+    }
+    mark(w, MK_NS, s);
+    // stage-2 back-transform
+    if (N > 2) {
+        const int nJ = ceil_div(N - 2, b);
+        const int Tmax = w.Tmax;
+        hipLaunchKernelGGL(bt2_tfactor_kernel, dim3(nJ * Tmax), dim3(256), sizeof(double) * (4 * b * b + b), s, w.refl,
+                           w.rtau, N, b, Tmax, nJ, w.T2);
+        const size_t smem = sizeof(double) * (3 * b * b + 4 * b * BT2_NC);
+        const int nwave = nJ + Tmax - 1;
+        for (int wv = 0; wv < nwave; ++wv) {
+            hipLaunchKernelGGL(bt2_apply_kernel, dim3(nJ, ceil_div(me, BT2_NC)), dim3(256), smem, s, Z, ldz, N, me, b,
+                               Tmax, nJ, wv, w.refl, w.T2);
+        }
+    }
+    mark(w, MK_BT2, s);
+    // stage-1 back-transform, last panel first
+    const int np = num_panels(N, b);
+    for (int pi = np - 1; pi >= 0; --pi) {
+        const int r0 = pi * b + b, n = N - r0;
+        const double *Vp = w.Vx + panel_v_offset(N, b, pi);
+        const double *Tp = w.Tp + (long)pi * b * b;
+        double *Zs = Z + (long)r0 * ldz;
+        const long tiles = ceil_div(me, 64);
+        const int sp = splits_for(tiles, n, 128);
+        e = gemm_f64_splitk(A_T{Vp, b}, B_RM{Zs, ldz}, EpiStore{w.Y, me, 1.0}, b, me, n, sp, w.splitk, s);
+        if (e != hipSuccess) return e;
+        e = gemm_f64(GEMM_SMALL, A_RM{Tp, b}, B_RM{w.Y, me}, EpiStore{w.X, me, 1.0}, b, me, b, s);
+        if (e != hipSuccess) return e;
+        e = gemm_f64(GEMM_LARGE, A_RM{Vp, b}, B_RM{w.X, me}, EpiAxpby{Zs, ldz, -1.0, 1.0}, n, me, b, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(sign_fix_copy_kernel, dim3(ldu), dim3(256), 0, s, Z, ldz, N, me, U, ldu);
+    mark(w, MK_BT1, s);
+    return hipGetLastError();
+}
+
+}  // namespace ctm

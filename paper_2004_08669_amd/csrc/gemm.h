@@ -1,0 +1,214 @@
+// Tiled FP64 / FP32 GEMM on the CDNA matrix cores (gfx950), with operand
+// addressing supplied by small accessor structs.  The CTMRG contractions need
+// operands whose rows and columns are combined (spin, state) indices; the
+// accessors turn the paper's index permutations (its P-Index / P-Index2
+// reorderings) into address arithmetic inside the tile loads and the epilogue
+// stores, so no permuted copy of any matrix is ever written.
+//
+// C(i,j) = sum_k A(i,k) B(k,j), then epi(i, j, value, split).
+//
+// Work decomposition: a workgroup owns a BM x BN output tile and is made of
+// WM x WN waves of 64 lanes; each wave owns (BM/WM) x (BN/WN), a grid of 16x16
+// MFMA blocks.  K is walked in BK slices staged through LDS.  blockIdx.z splits
+// K into chunks (split-K) when the output has too few tiles to fill the chip.
+//
+// MFMA operand layout for v_mfma_f64_16x16x4_f64 (and the f32 16x16x4 form):
+//   A fragment: lane l holds A[l%16][l/16]   (row l%16, k l/16)
+//   B fragment: lane l holds B[l/16][l%16]   (k l/16, column l%16)
+//   D fragment: lane l, register r holds D[l/16 + 4 r][l%16]
+#pragma once
+
+#include "common.h"
+
+namespace ctm {
+
+static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------- accessors
+// kContigK: consecutive k are adjacent in memory (else consecutive m / n are).
+
+// A row-major M x K: A(i,k) = p[i*ld + k]
+struct A_RM {
+    const double *p; long ld;
+    static constexpr bool kContigK = true;
+    __device__ double operator()(int i, int k) const { return p[(long)i * ld + k]; }
+};
+// A stored K x M row-major, used transposed: A(i,k) = p[k*ld + i]
+struct A_T {
+    const double *p; long ld;
+    static constexpr bool kContigK = false;
+    __device__ double operator()(int i, int k) const { return p[(long)k * ld + i]; }
+};
+// B row-major K x N: B(k,j) = p[k*ld + j]
+struct B_RM {
+    const double *p; long ld;
+    static constexpr bool kContigK = false;
+    __device__ double operator()(int k, int j) const { return p[(long)k * ld + j]; }
+};
+// B stored N x K row-major, used transposed: B(k,j) = p[j*ld + k]
+struct B_T {
+    const double *p; long ld;
+    static constexpr bool kContigK = true;
+    __device__ double operator()(int k, int j) const { return p[(long)j * ld + k]; }
+};
+
+// ---------------------------------------------------------------- epilogues
+struct EpiStore {  // C = alpha * acc
+    double *p; long ld; double alpha;
+    __device__ void operator()(int i, int j, double v, int) const { p[(long)i * ld + j] = alpha * v; }
+};
+struct EpiAxpby {  // C = alpha * acc + beta * C
+    double *p; long ld; double alpha, beta;
+    __device__ void operator()(int i, int j, double v, int) const
+    {
+        double *c = p + (long)i * ld + j;
+        *c = alpha * v + beta * (*c);
+    }
+};
+struct EpiPartial {  // split-K partial sums, reduced by reduce_partials
+    double *p; long M, N;
+    __device__ void operator()(int i, int j, double v, int split) const
+    {
+        p[((long)split * M + i) * N + j] = v;
+    }
+};
+
+// ---------------------------------------------------------------- FP64 kernel
+template <int BM, int BN, int BK, int WM, int WN, class LA, class LB, class EPI>
+__global__ void __launch_bounds__(WM * WN * 64)
+gemm_f64_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
+{
+    constexpr int NT = WM * WN * 64;
+    constexpr int TM = BM / WM / 16;
+    constexpr int TN = BN / WN / 16;
+    static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
+    static_assert(BK % 4 == 0, "BK");
+    __shared__ double As[BK][BM + 1];
+    __shared__ double Bs[BK][BN + 1];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave % WM, wn = wave / WM;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+
+    double4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll 4
+        for (int idx = tid; idx < BM * BK; idx += NT) {
+            int mm, kk;
+            if (LA::kContigK) { mm = idx / BK; kk = idx - mm * BK; }
+            else { kk = idx / BM; mm = idx - kk * BM; }
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[kk][mm] = (gm < M && gk < kend) ? la(gm, gk) : 0.0;
+        }
+#pragma unroll 4
+        for (int idx = tid; idx < BN * BK; idx += NT) {
+            int nn, kk;
+            if (LB::kContigK) { nn = idx / BK; kk = idx - nn * BK; }
+            else { kk = idx / BN; nn = idx - kk * BN; }
+            const int gn = n0 + nn, gk = k0 + kk;
+            Bs[kk][nn] = (gn < N && gk < kend) ? lb(gk, gn) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double a[TM], b[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = As[kk + (lane >> 4)][(wm * TM + i) * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b[j] = Bs[kk + (lane >> 4)][(wn * TN + j) * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + (wm * TM + i) * 16 + (lane >> 4) + 4 * r;
+                const int col = n0 + (wn * TN + j) * 16 + (lane & 15);
+                if (row < M && col < N) epi(row, col, acc[i][j][r], blockIdx.z);
+            }
+}
+
+// Sum split-K partials and apply the final epilogue.
+template <class EPI>
+__global__ void reduce_partials_kernel(const double *part, int splits, int M, int N, EPI epi)
+{
+    const long total = (long)M * N;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int z = 0; z < splits; ++z) s += part[(long)z * total + idx];
+        const int i = (int)(idx / N), j = (int)(idx - (long)i * N);
+        epi(i, j, s, 0);
+    }
+}
+
+// Tile configurations.
+enum GemmShape {
+    GEMM_LARGE,   // 128 x 128 tile, 2 x 2 waves
+    GEMM_TALL,    // 128 x 32 tile, 4 x 1 waves (outputs with few columns)
+    GEMM_MIX,     // 80 x 128 tile, 1 x 4 waves (the q^2 = 400 rows of the W-mix)
+    GEMM_SMALL,   // 64 x 64 tile, 2 x 2 waves
+};
+
+template <class LA, class LB, class EPI>
+hipError_t gemm_f64(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K, hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    switch (shape) {
+    case GEMM_LARGE:
+        hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 16, 2, 2, LA, LB, EPI>),
+                           dim3(ceil_div(M, 128), ceil_div(N, 128), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
+        break;
+    case GEMM_TALL:
+        hipLaunchKernelGGL((gemm_f64_kernel<128, 32, 16, 4, 1, LA, LB, EPI>),
+                           dim3(ceil_div(M, 128), ceil_div(N, 32), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
+        break;
+    case GEMM_MIX:
+        hipLaunchKernelGGL((gemm_f64_kernel<80, 128, 16, 1, 4, LA, LB, EPI>),
+                           dim3(ceil_div(M, 80), ceil_div(N, 128), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
+        break;
+    case GEMM_SMALL:
+        hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 16, 2, 2, LA, LB, EPI>),
+                           dim3(ceil_div(M, 64), ceil_div(N, 64), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
+        break;
+    }
+    return hipGetLastError();
+}
+
+// Split-K GEMM: partials go to `work` (splits * M * N doubles), then reduced.
+template <class LA, class LB, class EPI>
+hipError_t gemm_f64_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int splits, double *work,
+                           hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (splits <= 1) return gemm_f64(GEMM_SMALL, la, lb, epi, M, N, K, s);
+    int kchunk = ceil_div(ceil_div(K, splits), 16) * 16;
+    splits = ceil_div(K, kchunk);
+    EpiPartial part{work, M, N};
+    hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 16, 2, 2, LA, LB, EpiPartial>),
+                       dim3(ceil_div(M, 64), ceil_div(N, 64), splits), dim3(256), 0, s, la, lb, part, M, N,
+                       K, kchunk);
+    long total = (long)M * N;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(reduce_partials_kernel<EPI>, dim3(blocks), dim3(256), 0, s, work, splits, M, N, epi);
+    return hipGetLastError();
+}
+
+}  // namespace ctm
