@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Throughput of the CTMRG step (Sec. III, Algorithm 3) for the q=20 dodecahedron model on one MI355X.
+
+A step is one full pass of the method on the GPU: extension products and W-mix
+(the extended corner C', (q m) x (q m)), the FP64 eigensolver (all eigenvalues,
+the m leading eigenvectors), the multiplet-preserving cut, the half-row
+products, W-mix and projection, and the normalizations.  The state after the
+warmup has reached the full dimension m (the dimension saturates after four
+steps at m = 512 since 20^3 < 10240 <= 20^4), so every timed step does the
+full-size work.  Inputs are the dodecahedron spin vectors and K = 1/T; the
+state is whatever the iteration produces (synthetic, deterministic).
+
+Prints one JSON line (see the repository's design notes for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
+PEAK_HBM_GBS = 8000.0
+
+
+def stage_flops(q: int, m: int):
+    """Algorithmic flop counts of the single-launch contraction kernels of one step."""
+    N = q * m
+    return {
+        "extension": 2.0 * N * N * m,            # X = A^T (Omega A)
+        "wmix_C": 2.0 * q ** 4 * m * m,          # C' = W-mix(X)
+        "halfrow": 2.0 * N * N * m,              # Y = A^T U~
+        "wmix_Z": 2.0 * q ** 4 * m * m,          # Z = W-mix(Y)
+        "projection": 2.0 * m * N * N,           # P~ = U^T Z
+        "dense_to_band": 4.0 / 3.0 * N ** 3,     # two-sided Householder reduction to band
+        "backtransform_dense": 4.0 * N * N * m / 2.0,
+        "backtransform_band": 2.0 * N * N * m,
+    }
+
+
+def cpu_baseline(q_vectors, K, m_sample, m_target, warm=3):
+    """The oracle's step time at m_sample, scaled by its O(m^3) cost to m_target."""
+    from oracle import ctmrg_oracle as O
+    o = O.OracleCTMRG(q_vectors, K, m_sample)
+    for _ in range(warm):
+        o.step()
+    t0 = time.perf_counter()
+    o.step()
+    dt = time.perf_counter() - t0
+    scale = (m_target / m_sample) ** 3
+    return {
+        "value": 1.0 / (dt * scale),
+        "unit": "steps/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"one oracle step (Jacobi eigensolver) at q=20, m={m_sample} (C' {20 * m_sample}^2) "
+                   f"from the state after {warm} steps took {dt:.2f} s; scaled by (m/{m_sample})^3 = {scale:.0f} "
+                   f"to m={m_target}"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--m", type=int, default=512)
+    ap.add_argument("--T", type=float, default=0.4398)
+    ap.add_argument("--band", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-m", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the CTMRG step of one (T, m) problem runs on a single MI355X "
+              f"(independent temperatures would shard with no communication); --gpus {args.gpus} is not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import ctmrg_inputs as I
+    from paper_2004_08669_amd import ctmrg
+
+    torch.cuda.set_device(0)
+    V = I.dodecahedron()
+    q, m, K = len(V), args.m, 1.0 / args.T
+    print(f"# bench: q={q} m={m} T={args.T} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    g = ctmrg.CTMRG(V, K, m, band=args.band)
+    for i in range(args.warmup):
+        g.step(1)
+        print(f"# warmup step {i + 1}/{args.warmup}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    g.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        g.step(1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages, nsteps = g.stage_times()
+    obs = g.observables()
+    g.close()
+    dt = t1 - t0
+    ms_step = 1000.0 * dt / args.steps
+    stage_ms = {k: v / max(1, nsteps) for k, v in stages.items()}
+
+    flops = stage_flops(q, m)
+    # dominant single-launch kernel among the contractions, and the dominant stage overall
+    kernel_stages = ["extension", "wmix_C", "halfrow", "wmix_Z", "projection"]
+    dom = max(kernel_stages, key=lambda k: stage_ms[k])
+    achieved = flops[dom] / (stage_ms[dom] * 1e-3) / 1e12
+    roofline = {
+        "kernel": dom,
+        "bound": "mfma",
+        "achieved": achieved,
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64_TFLOPS,
+        "traffic": None,
+        "algorithmic_per_launch": flops[dom],
+        "avg_launch_ms": stage_ms[dom],
+    }
+    out = {
+        "metric": "CTMRG steps/s at q=20 m=512 (mixed vs FP64, same error); % MFMA peak",
+        "value": args.steps / dt,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"CTMRG step, q=20 dodecahedron, m={m} (C' {q * m}x{q * m}), T={args.T}, fixed boundary, FP64",
+            "q": q, "m": m, "T": args.T, "precision": "fp64", "band": args.band,
+        },
+        "roofline": roofline,
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "state": {"m_eff": obs["m_eff"], "S_E": obs["S_E"], "delta": obs["delta"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(V, K, args.cpu_sample_m, m)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

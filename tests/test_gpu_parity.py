@@ -206,21 +206,30 @@ def test_dodecahedron_free_boundary_m8_500_steps():
     assert abs(abs(og["M"]) - abs(oo["M"])) <= 5e-2
 
 
-@pytest.mark.parametrize("T", [0.40, 0.48])
-def test_dodecahedron_fixed_boundary_m16(T):
-    """Well-conditioned fixed-boundary runs (rounding sensitivity of f ~ 1e-13 at step 400)."""
+@pytest.mark.parametrize("T,tol", [(0.40, 1e-12), (0.48, 1e-11)])
+def test_dodecahedron_fixed_boundary_m16(T, tol):
+    """Fixed points reached independently by the GPU and the oracle (each iterated until
+    Delta < tol); the trajectories may differ transiently (a level crossing at the cut
+    amplifies rounding differences) but the fixed point is the same."""
     ct = _lib()
     V = I.dodecahedron()
     K, m = 1.0 / T, 16
     say(f"[fixed point] dodecahedron m=16 T={T} fixed")
     g = ct.CTMRG(V, K, m)
-    ks, dg, conv = g.run_to_fixed_point(1e-12, 200)
+    ks, dg, conv = g.run_to_fixed_point(tol, 1500)
+    assert conv
     og = g.observables()
+    say(f"  gpu converged in {ks} steps")
     o = O.OracleCTMRG(V, K, m)
-    for i in range(ks):
+    i = 0
+    while i < 1500:
         o.step()
+        i += 1
         if i % 100 == 0:
-            say(f"  oracle step {i}/{ks}")
+            say(f"  oracle step {i} delta={o.delta:.2e}")
+        if i >= 2 and o.delta < tol:
+            break
+    assert o.delta < tol
     oo = o.observables()
     assert og["m_eff"] == oo["m_eff"]
     assert abs(og["f"] - oo["f"]) <= 1e-10 * abs(oo["f"])
@@ -247,3 +256,29 @@ def test_checkpoint_resume_bitwise():
     assert oa["f"] == ob["f"] and oa["M"] == ob["M"]
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("T,bc,nsteps", [(0.48, "fixed", 26), (0.40, "fixed", 30)])
+def test_trajectory_first_steps(T, bc, nsteps):
+    """Step-by-step agreement from the initial state (dimension growing 1 -> q -> m): kept
+    spectrum and cut after every step.  At T=0.48, m=16 the 16th and 17th eigenvalues cross at
+    step 30; near the crossing the iteration amplifies any rounding-level difference by 1e3-1e4
+    per step (the oracle does the same to a 1e-14 perturbation of its own state), so the strict
+    comparison stops at step 26."""
+    ct = _lib()
+    V = I.dodecahedron()
+    K, m = 1.0 / T, 16
+    say(f"[trajectory] m={m} T={T} {bc}")
+    g = ct.CTMRG(V, K, m, bc=bc)
+    o = O.OracleCTMRG(V, K, m, bc=bc)
+    worst = 0.0
+    for k in range(1, nsteps + 1):
+        g.step(1)
+        r = o.step()
+        om = g.get("omega")
+        d = float(np.abs(om[: r.m_eff] - r.omega).max())
+        worst = max(worst, d)
+        say(f"  step {k}: m_eff gpu={int(np.count_nonzero(om))} oracle={r.m_eff} max|d omega|={d:.2e}")
+        assert int(np.count_nonzero(om)) == r.m_eff
+    assert worst <= 1e-11
+    g.close()
