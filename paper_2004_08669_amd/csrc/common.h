@@ -27,6 +27,23 @@ CTMRG_DEVINL unsigned atomic_add_acqrel(unsigned *p, unsigned v)
     return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Device-coherent accesses (relaxed, agent scope: the load or store is coherent
+// across the L2s of all XCDs, with no cache writeback or invalidate).  Data that
+// workgroups exchange inside one launch goes through these; a writer makes its
+// coherent stores complete (wait_mem) before it stores the flag that publishes
+// them, and a reader issues its coherent loads after it has seen the flag.
+CTMRG_DEVINL double ld_coh(const double *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+CTMRG_DEVINL void st_coh(double *p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+CTMRG_DEVINL unsigned ldu_coh(const unsigned *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+CTMRG_DEVINL void stu_coh(unsigned *p, unsigned v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+// Wait until this thread's outstanding memory operations have completed.
+CTMRG_DEVINL void wait_mem()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Error flags raised by kernels (bitwise OR into a device word).
 enum {
     KERR_BARRIER_TIMEOUT = 1,
@@ -45,21 +62,23 @@ CTMRG_DEVINL void raise_error(unsigned *err, unsigned code)
 // Grid-wide barrier for a launch whose workgroups are all resident (cooperative
 // launch).  bar[0] counts arrivals, bar[1] is the generation.  `gen` is the
 // generation this workgroup read at kernel start; it is advanced on each call.
-// Returns false (and raises KERR_BARRIER_TIMEOUT) if the wait hit the spin limit.
+// Data exchanged across the barrier must use ld_coh / st_coh.  Returns false
+// (and raises KERR_BARRIER_TIMEOUT) if the wait hit the spin limit.
 CTMRG_DEVINL bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, unsigned *err)
 {
     __shared__ int ok_shared;
-    fence_release_agent();
+    wait_mem();
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        unsigned arrived = atomic_add_acqrel(&bar[0], 1u);
+        unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == nblocks - 1) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            atomic_store_release(&bar[1], gen + 1u);
+            stu_coh(&bar[0], 0u);
+            wait_mem();
+            stu_coh(&bar[1], gen + 1u);
         } else {
             unsigned spins = 0;
-            while (atomic_load_acquire(&bar[1]) == gen) {
+            while (ldu_coh(&bar[1]) == gen) {
                 __builtin_amdgcn_s_sleep(1);
                 if (++spins > CTMRG_SPIN_LIMIT) {
                     raise_error(err, KERR_BARRIER_TIMEOUT);
@@ -72,7 +91,7 @@ CTMRG_DEVINL bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, u
     }
     gen += 1u;
     __syncthreads();
-    fence_acquire_agent();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     return ok_shared != 0;
 }
 

@@ -47,7 +47,7 @@ struct EigWork {
     double *ZT = nullptr;      // N x kmax (row-major, ld kmax)
     double *Ztmp = nullptr;    // N x kmax
     double *G = nullptr;       // kmax x kmax
-    double *lu = nullptr;      // inverse-iteration scratch (4 N kmax)
+    double *lu = nullptr;      // inverse-iteration scratch (5 N kmax, rounded up to 64)
     int *ipiv = nullptr;       // N kmax
     int *clist = nullptr;      // kmax: kept indices in ascending-eigenvalue order
     int *cstart = nullptr;     // kmax + 1 cluster offsets

@@ -31,19 +31,9 @@ static long panel_v_offset(int N, int b, int pi)
 }
 
 // Steps of bulge-chasing sweep j (columns j = 0 .. N-3): step t works on rows
-// R_t = [r0, r0 + b) with r0 = j + 1 + t b.
-__host__ __device__ inline int bulge_nsteps(int N, int b, int j)
-{
-    int t = 0;
-    while (true) {
-        const int r0 = j + 1 + t * b;
-        if (r0 >= N) return t;
-        const int r1 = min(r0 + b, N);
-        if (t > 0 && r1 - r0 < 2) return t;
-        ++t;
-        if (r1 >= N) return t;
-    }
-}
+// R_t = [r0, r0 + b) with r0 = j + 1 + t b (clipped to N); step 0 always exists and
+// step t >= 1 exists while its block has at least two rows: t <= (N - 3 - j) / b.
+__host__ __device__ inline int bulge_nsteps(int N, int b, int j) { return 1 + (N - 3 - j) / b; }
 
 static int max_steps(int N, int b) { return N > 2 ? bulge_nsteps(N, b, 0) : 0; }
 
@@ -74,7 +64,7 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
     const int row0 = g * rows;
     const int nloc = min(rows, n - row0);
-    unsigned gen = atomic_load_acquire(&bar[1]);
+    unsigned gen = ldu_coh(&bar[1]);
     double *rowbuf = part + 2L * G * b;          // [2][b]
     double *gpart = rowbuf + 2L * b;             // [G][b*b]
 
@@ -97,18 +87,34 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
         if (tid < b) {
             double t = 0.0;
             for (int k = 0; k < RG; ++k) t += red[k * b + tid];
-            part[((long)buf * G + g) * b + tid] = t;
-            if (i >= row0 && i < row0 + nloc) rowbuf[buf * b + tid] = pan[(i - row0) * b + tid];
+            st_coh(&part[((long)buf * G + g) * b + tid], t);
+            if (i >= row0 && i < row0 + nloc) st_coh(&rowbuf[buf * b + tid], pan[(i - row0) * b + tid]);
         }
         grid_barrier(bar, G, gen, err);
+        {
+            // partial sums of the G workgroups: row group rg adds workgroups rg, rg+RG, ...
+            double t = 0.0;
+            int k = rg;
+            for (; k + 7 * RG < G; k += 8 * RG) {
+                double x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = ld_coh(&part[((long)buf * G + k + u * RG) * b + cl]);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t += x[u];
+            }
+            for (; k < G; k += RG) t += ld_coh(&part[((long)buf * G + k) * b + cl]);
+            red[rg * b + cl] = t;
+        }
+        if (tid < b) wv[tid] = ld_coh(&rowbuf[buf * b + tid]);
+        __syncthreads();
         if (tid < b) {
             double t = 0.0;
-            for (int k = 0; k < G; ++k) t += part[((long)buf * G + k) * b + tid];
+            for (int k = 0; k < RG; ++k) t += red[k * b + tid];
             sv[tid] = t;
         }
         __syncthreads();
         if (tid == 0) {
-            const double alpha = rowbuf[buf * b + i];
+            const double alpha = wv[i];
             const double xn2 = sv[i];
             double beta, tau, scale;
             if (xn2 == 0.0) {
@@ -122,7 +128,7 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
             tl[i] = tau;
         }
         __syncthreads();
-        if (tid < b && tid > i) wv[tid] = rowbuf[buf * b + tid] + bc[2] * sv[tid];
+        if (tid < b && tid > i) wv[tid] = wv[tid] + bc[2] * sv[tid];
         __syncthreads();
         const double beta = bc[0], tau_i = bc[1], scale = bc[2];
         // columns right of i first (they read the old column i)
@@ -158,13 +164,21 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
             const double v2 = (gr == c2) ? 1.0 : (gr > c2 ? pan[r * b + c2] : 0.0);
             s += v1 * v2;
         }
-        gpart[(long)g * b * b + idx] = s;
+        st_coh(&gpart[(long)g * b * b + idx], s);
     }
     grid_barrier(bar, G, gen, err);
     if (g != 0) return;
     for (int idx = tid; idx < b * b; idx += 256) {
         double s = 0.0;
-        for (int k = 0; k < G; ++k) s += gpart[(long)k * b * b + idx];
+        int k = 0;
+        for (; k + 8 <= G; k += 8) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = ld_coh(&gpart[(long)(k + u) * b * b + idx]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += x[u];
+        }
+        for (; k < G; ++k) s += ld_coh(&gpart[(long)k * b * b + idx]);
         gram[idx] = s;
         Tm[idx] = 0.0;
     }
@@ -215,145 +229,189 @@ __global__ void extract_band_kernel(const double *A, long lda, int N, int b, dou
 // Stage 2: pipelined bulge chasing
 // ============================================================================
 
-__global__ void __launch_bounds__(256)
-bulge_kernel(double *band, int N, int b, double *refl, double *rtau, int Tmax, unsigned *progress, unsigned *err)
-{
-    extern __shared__ double sh[];
-    double *L = sh;
-    double *D = L + b * b;
-    double *B = D + b * b;
-    double *v = B + b * b;
-    double *w = v + b;
-    double *pp = w + b;
-    double *y = pp + b;
-    double *sc = y + b;
-    __shared__ int abort_flag;
-    const int ld = 2 * b;
-    const int tid = threadIdx.x;
+// One wave per sweep, BW consecutive sweeps per workgroup.  Inside a workgroup a
+// sweep waits for its predecessor through an LDS progress word; only the first
+// sweep of a group waits across workgroups, on the progress word of the last
+// sweep of the previous group.  A sweep may run step t once its predecessor has
+// completed step t+2.  All band traffic is device-coherent (ld_coh / st_coh) and
+// a step's stores complete before its progress word is advanced, so no cache
+// writeback or invalidate is needed anywhere in the pipeline.
+//
+// A step holds its three b x b blocks in registers: lane (c, h) = (lane % b,
+// lane / b) owns column c, rows h*RPL .. h*RPL + RPL - 1 of each block, so every
+// load of the step is in flight at once; sums over a column combine the LPC
+// lanes of that column, sums over a row combine the b lanes of a row group.
+constexpr int BW = 8;
 
-    for (int j = blockIdx.x; j < N - 2; j += gridDim.x) {
-        const int ns = bulge_nsteps(N, b, j);
-        const int nsprev = (j > 0) ? bulge_nsteps(N, b, j - 1) : 0;
+CTMRG_DEVINL void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); __builtin_amdgcn_wave_barrier(); }
+
+template <int B>
+CTMRG_DEVINL double col_sum(double x)  // over the lanes sharing lane % B
+{
+    for (int off = B; off < 64; off <<= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+template <int B>
+CTMRG_DEVINL double row_sum(double x)  // over the lanes sharing lane / B
+{
+    for (int off = 1; off < B; off <<= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+template <int B>
+__global__ void __launch_bounds__(64 * BW)
+bulge_reg_kernel(double *band, int N, double *refl, double *rtau, int Tmax, unsigned *gprog, unsigned *err)
+{
+    constexpr int LPC = 64 / B;   // lanes per column
+    constexpr int RPL = B / LPC;  // rows per lane
+    __shared__ int lprog[BW];
+    __shared__ int labort;
+    __shared__ double vsh[BW][B], wsh[BW][B];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = lane % B, h = lane / B, rb = h * RPL;
+    const int ld = 2 * B;
+    const int nsw = N - 2;
+    const int ngroups = (nsw + BW - 1) / BW;
+    if (threadIdx.x == 0) labort = 0;
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        __syncthreads();
+        if (lane == 0) __hip_atomic_store(&lprog[wave], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __syncthreads();
+        if (labort) return;
+        const int j = grp * BW + wave;
+        if (j >= nsw) continue;
+        const int ns = bulge_nsteps(N, B, j);
+        const int nsprev = (j > 0) ? bulge_nsteps(N, B, j - 1) : 0;
+        double *vs = vsh[wave], *ws = wsh[wave];
         for (int t = 0; t < ns; ++t) {
             if (j > 0) {
-                if (tid == 0) {
-                    const unsigned need = (unsigned)min(t + 3, nsprev);
-                    unsigned spins = 0;
-                    int ok = 1;
-                    while (atomic_load_acquire(&progress[j - 1]) < need) {
+                const int need = min(t + 3, nsprev);
+                unsigned spins = 0;
+                int ok = 1;
+                if (wave == 0) {
+                    while ((int)ldu_coh(&gprog[grp - 1]) < need) {
                         __builtin_amdgcn_s_sleep(1);
-                        if (++spins > CTMRG_SPIN_LIMIT) {
-                            raise_error(err, KERR_PIPELINE_TIMEOUT);
-                            ok = 0;
-                            break;
-                        }
+                        if (++spins > CTMRG_SPIN_LIMIT) { ok = 0; break; }
                     }
-                    abort_flag = !ok;
+                } else {
+                    while (__hip_atomic_load(&lprog[wave - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++spins > CTMRG_SPIN_LIMIT) { ok = 0; break; }
+                    }
                 }
-                __syncthreads();
-                if (abort_flag) return;
+                if (!ok) {
+                    if (lane == 0) { raise_error(err, KERR_PIPELINE_TIMEOUT); labort = 1; }
+                    break;
+                }
             }
-            fence_acquire_agent();
             int r0, c0, ncl;
             if (t == 0) { r0 = j + 1; c0 = j; ncl = 1; }
-            else { r0 = j + 1 + t * b; c0 = j + 1 + (t - 1) * b; ncl = b; }
-            const int r1 = min(r0 + b, N), len = r1 - r0;
-            const int n0 = r1, n1 = min(r1 + b, N), nbl = n1 - n0;
-
-            for (int idx = tid; idx < len * ncl; idx += 256) {
-                const int r = idx / ncl, c = idx - (idx / ncl) * ncl;
-                L[r * b + c] = band[(long)(c0 + c) * ld + (r0 + r - c0 - c)];
-            }
-            for (int idx = tid; idx < len * len; idx += 256) {
-                const int r = idx / len, c = idx - (idx / len) * len;
-                const int rr = max(r, c), cc = min(r, c);
-                D[r * b + c] = band[(long)(r0 + cc) * ld + (rr - cc)];
-            }
-            for (int idx = tid; idx < nbl * len; idx += 256) {
-                const int r = idx / len, c = idx - (idx / len) * len;
-                B[r * b + c] = band[(long)(r0 + c) * ld + (n0 + r - r0 - c)];
-            }
-            __syncthreads();
-            if (tid < 64) {
-                double xs = 0.0;
-                for (int r = 1 + tid; r < len; r += 64) xs += L[r * b] * L[r * b];
-                xs = wave_sum(xs);
-                const double alpha = L[0];
-                double beta, tau, scale;
+            else { r0 = j + 1 + t * B; c0 = j + 1 + (t - 1) * B; ncl = B; }
+            const int len = min(r0 + B, N) - r0;
+            const int n0 = r0 + len, nbl = min(n0 + B, N) - n0;
+            const long safe = (long)r0 * ld;  // an in-bounds address for masked-off lanes
+            double tau = 0.0;
+            // ---- left block (lane: column c, rows rb..rb+RPL-1): Householder vector from
+            //      column 0, then L[:,c] -= tau v (v^T L[:,c]) for the columns c >= 1
+            {
+                double L[RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const int r = rb + i;
+                    const bool ok = (c < ncl && r < len);
+                    const double x = ld_coh(&band[ok ? (long)(c0 + c) * ld + (r0 + r - c0 - c) : safe]);
+                    L[i] = ok ? x : 0.0;
+                }
+                const double alpha = __shfl(L[0], 0, 64);
+                double part = 0.0;
+                if (c == 0) {
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) part += (rb + i >= 1) ? L[i] * L[i] : 0.0;
+                }
+                const double xs = wave_sum(part);
+                double beta, scale;
                 if (xs == 0.0) { beta = alpha; tau = 0.0; scale = 0.0; }
                 else {
                     beta = -copysign(sqrt(alpha * alpha + xs), alpha);
                     tau = (beta - alpha) / beta;
                     scale = 1.0 / (alpha - beta);
                 }
-                if (tid == 0) { sc[0] = beta; sc[1] = tau; }
-                for (int r = tid; r < len; r += 64) v[r] = (r == 0) ? 1.0 : L[r * b] * scale;
-            }
-            __syncthreads();
-            const double beta = sc[0], tau = sc[1];
-            if (tid < b) {
-                const int c = tid;
-                if (c >= 1 && c < ncl) {
-                    double s = 0.0;
-                    for (int r = 0; r < len; ++r) s += v[r] * L[r * b + c];
-                    w[c] = s;
+                if (c == 0) {
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) {
+                        const int r = rb + i;
+                        const double vr = (r >= len) ? 0.0 : (r == 0 ? 1.0 : L[i] * scale);
+                        vs[r] = vr;
+                        refl[((long)j * Tmax + t) * B + r] = vr;
+                        L[i] = (r == 0) ? beta : 0.0;
+                    }
                 }
-            } else if (tid < 2 * b) {
-                const int r = tid - b;
-                if (r < len) {
-                    double s = 0.0;
-                    for (int c = 0; c < len; ++c) s += D[r * b + c] * v[c];
-                    pp[r] = tau * s;
+                if (lane == 0) rtau[(long)j * Tmax + t] = tau;
+                wave_fence();
+                double sdot = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) sdot += vs[rb + i] * L[i];
+                const double wc = tau * col_sum<B>(sdot);
+                if (c >= 1) {
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) L[i] -= wc * vs[rb + i];
                 }
-            } else if (tid < 3 * b) {
-                const int r = tid - 2 * b;
-                if (r < nbl) {
-                    double s = 0.0;
-                    for (int c = 0; c < len; ++c) s += B[r * b + c] * v[c];
-                    y[r] = s;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const int r = rb + i;
+                    if (c < ncl && r < len) st_coh(&band[(long)(c0 + c) * ld + (r0 + r - c0 - c)], L[i]);
                 }
             }
-            __syncthreads();
-            if (tid < 64) {
-                double s = 0.0;
-                for (int r = tid; r < len; r += 64) s += v[r] * pp[r];
-                s = wave_sum(s);
-                if (tid == 0) sc[2] = 0.5 * tau * s;
+            const double vc = vs[c];
+            // ---- diagonal block: p = tau D v, k = tau v^T p / 2, w = p - k v, D -= v w^T + w v^T
+            {
+                double D[RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const int r = rb + i;
+                    const bool ok = (r < len && c < len);
+                    const long off = (r >= c) ? (long)(r0 + c) * ld + (r - c) : (long)(r0 + r) * ld + (c - r);
+                    const double x = ld_coh(&band[ok ? off : safe]);
+                    D[i] = ok ? x : 0.0;
+                }
+                double pd = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) pd += D[i] * vs[rb + i];  // column c of D (= row c) dotted with v
+                const double pc = tau * col_sum<B>(pd);
+                const double kk = 0.5 * tau * wave_sum((h == 0 && c < len) ? vc * pc : 0.0);
+                const double wc = pc - kk * vc;
+                if (h == 0) ws[c] = (c < len) ? wc : 0.0;
+                wave_fence();
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const int r = rb + i;
+                    D[i] -= vs[r] * wc + ws[r] * vc;
+                    if (r < len && c < len && r >= c) st_coh(&band[(long)(r0 + c) * ld + (r - c)], D[i]);
+                }
             }
-            __syncthreads();
-            const double kk = sc[2];
-            for (int idx = tid; idx < len * ncl; idx += 256) {
-                const int r = idx / ncl, c = idx - (idx / ncl) * ncl;
-                if (c == 0) L[r * b] = (r == 0) ? beta : 0.0;
-                else L[r * b + c] -= tau * v[r] * w[c];
+            // ---- block below: y = B v (row sums), B -= tau y v^T
+            {
+                double Bm[RPL];
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const int r = rb + i;
+                    const bool ok = (r < nbl && c < len);
+                    const double x = ld_coh(&band[ok ? (long)(r0 + c) * ld + (n0 + r - r0 - c) : safe]);
+                    Bm[i] = ok ? x : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const int r = rb + i;
+                    const double yr = row_sum<B>(Bm[i] * vc);
+                    Bm[i] -= tau * yr * vc;
+                    if (r < nbl && c < len) st_coh(&band[(long)(r0 + c) * ld + (n0 + r - r0 - c)], Bm[i]);
+                }
             }
-            for (int idx = tid; idx < len * len; idx += 256) {
-                const int r = idx / len, c = idx - (idx / len) * len;
-                const double wr = pp[r] - kk * v[r], wc = pp[c] - kk * v[c];
-                D[r * b + c] -= v[r] * wc + wr * v[c];
-            }
-            for (int idx = tid; idx < nbl * len; idx += 256) {
-                const int r = idx / len, c = idx - (idx / len) * len;
-                B[r * b + c] -= tau * y[r] * v[c];
-            }
-            __syncthreads();
-            for (int idx = tid; idx < len * ncl; idx += 256) {
-                const int r = idx / ncl, c = idx - (idx / ncl) * ncl;
-                band[(long)(c0 + c) * ld + (r0 + r - c0 - c)] = L[r * b + c];
-            }
-            for (int idx = tid; idx < len * len; idx += 256) {
-                const int r = idx / len, c = idx - (idx / len) * len;
-                if (r >= c) band[(long)(r0 + c) * ld + (r - c)] = D[r * b + c];
-            }
-            for (int idx = tid; idx < nbl * len; idx += 256) {
-                const int r = idx / len, c = idx - (idx / len) * len;
-                band[(long)(r0 + c) * ld + (n0 + r - r0 - c)] = B[r * b + c];
-            }
-            for (int r = tid; r < b; r += 256) refl[((long)j * Tmax + t) * b + r] = (r < len) ? v[r] : 0.0;
-            if (tid == 0) rtau[(long)j * Tmax + t] = tau;
-            fence_release_agent();
-            __syncthreads();
-            if (tid == 0) atomic_store_release(&progress[j], (unsigned)(t + 1));
+            // ---- publish completion of step t (the coherent stores above complete first)
+            wait_mem();
+            if (wave == BW - 1 && lane == 0) stu_coh(&gprog[grp], (unsigned)(t + 1));
+            if (lane == 0) __hip_atomic_store(&lprog[wave], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
     }
 }
@@ -541,8 +599,8 @@ post_eigen_kernel(const double *ev, int N, int m, double gap_tol, double rank_to
 // Eigenvectors of the tridiagonal: inverse iteration
 // ============================================================================
 
-// One thread per tight cluster; the LU scratch of thread c is interleaved
-// (element i of array a at lu[(a*N + i)*nth + c]) so that the lanes of a wave
+// One thread per tight cluster; the LU scratch and the iterate of thread c are
+// interleaved (element i of array a at lu[(a*N + i)*nth + c]) so that the lanes of a wave
 // touch adjacent addresses.
 __global__ void __launch_bounds__(64)
 invit_kernel(const double *d, const double *e, int N, const double *selval, const int *clist, const int *cstart,
@@ -558,7 +616,7 @@ invit_kernel(const double *d, const double *e, int N, const double *selval, cons
 #define DU(i) lu[((long)2 * N + (i)) * nth + c]
 #define DU2(i) lu[((long)3 * N + (i)) * nth + c]
 #define IP(i) ipiv[(long)(i) * nth + c]
-#define X(i) ZT[(long)(i) * ldz + j]
+#define X(i) lu[((long)4 * N + (i)) * nth + c]
     for (int q = cstart[c]; q < cstart[c + 1]; ++q) {
         const int j = clist[q];
         const double lam = selval[j];
@@ -635,6 +693,7 @@ invit_kernel(const double *d, const double *e, int N, const double *selval, cons
             nrm = (nrm > 0.0) ? 1.0 / sqrt(nrm) : 0.0;
             for (int i = 0; i < N; ++i) X(i) *= nrm;
         }
+        for (int i = 0; i < N; ++i) ZT[(long)i * ldz + j] = X(i);
     }
 #undef DL
 #undef DD
@@ -677,12 +736,12 @@ bt2_tfactor_kernel(const double *refl, const double *rtau, int N, int b, int Tma
     if (J >= nJ) return;
     const int tid = threadIdx.x;
     for (int idx = tid; idx < 2 * b * b; idx += 256) {
-        const int r = idx / b, i = idx - (idx / b) * b;
+        const int i = idx / (2 * b), r = idx - (idx / (2 * b)) * (2 * b);
         const int j = J * b + i;
         double val = 0.0;
         if (j < N - 2 && t < bulge_nsteps(N, b, j) && r - i >= 0 && r - i < b)
             val = refl[((long)j * Tmax + t) * b + (r - i)];
-        V[idx] = val;
+        V[r * b + i] = val;
     }
     for (int i = tid; i < b; i += 256) {
         const int j = J * b + i;
@@ -734,12 +793,12 @@ bt2_apply_kernel(double *Z, int ldz, int N, int ncols, int b, int Tmax, int nJ, 
     const int nrow = min(2 * b - 1, N - base);
     const int tid = threadIdx.x;
     for (int idx = tid; idx < 2 * b * b; idx += 256) {
-        const int r = idx / b, i = idx - (idx / b) * b;
+        const int i = idx / (2 * b), r = idx - (idx / (2 * b)) * (2 * b);
         const int j = J * b + i;
         double val = 0.0;
         if (r < nrow && j < N - 2 && t < bulge_nsteps(N, b, j) && r - i >= 0 && r - i < b)
             val = refl[((long)j * Tmax + t) * b + (r - i)];
-        V[idx] = val;
+        V[r * b + i] = val;
     }
     const double *Ts = T2 + ((long)J * Tmax + t) * b * b;
     for (int idx = tid; idx < b * b; idx += 256) Tm[idx] = Ts[idx];
@@ -838,7 +897,7 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += 2 * align_up(sizeof(double) * (size_t)Nmax * kmax);
     s += align_up(sizeof(double) * (size_t)kmax * kmax);
     const size_t kpad = ((size_t)kmax + 63) / 64 * 64;
-    s += align_up(sizeof(double) * 4 * (size_t)Nmax * kpad);
+    s += align_up(sizeof(double) * 5 * (size_t)Nmax * kpad);
     s += align_up(sizeof(int) * (size_t)Nmax * kpad);
     s += 2 * align_up(sizeof(int) * (size_t)(kmax + 2));
     s += align_up(sizeof(double) * 8) + 2 * align_up(64);
@@ -882,7 +941,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.ZT, sizeof(double) * (size_t)Nmax * kmax},
         {(void **)&w.Ztmp, sizeof(double) * (size_t)Nmax * kmax},
         {(void **)&w.G, sizeof(double) * (size_t)kmax * kmax},
-        {(void **)&w.lu, sizeof(double) * 4 * (size_t)Nmax * kpad},
+        {(void **)&w.lu, sizeof(double) * 5 * (size_t)Nmax * kpad},
         {(void **)&w.ipiv, sizeof(int) * (size_t)Nmax * kpad},
         {(void **)&w.clist, sizeof(int) * (size_t)(kmax + 2) * 2},
         {(void **)&w.cstart, sizeof(int) * (size_t)(kmax + 2)},
@@ -991,10 +1050,11 @@ hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s)
         if (e != hipSuccess) return e;
         const int Tmax = w.Tmax;
         double *band = w.band;
-        int G = std::min(N - 2, 256);
-        size_t smem = sizeof(double) * (3 * b * b + 4 * b + 4);
-        void *args[] = {&band, (void *)&N, (void *)&b, &w.refl, &w.rtau, (void *)&Tmax, &w.progress, &w.err};
-        e = launch_coop((const void *)bulge_kernel, dim3(G), dim3(256), args, smem, s);
+        const int ngroups = (N - 2 + BW - 1) / BW;
+        int G = std::min(ngroups, 128);
+        void *args[] = {&band, (void *)&N, &w.refl, &w.rtau, (void *)&Tmax, &w.progress, &w.err};
+        const void *fn = (b == 32) ? (const void *)bulge_reg_kernel<32> : (const void *)bulge_reg_kernel<16>;
+        e = launch_coop(fn, dim3(G), dim3(64 * BW), args, 0, s);
         if (e != hipSuccess) return e;
     }
     mark(w, MK_BULGE, s);
