@@ -62,8 +62,12 @@ CTMRG_DEVINL void raise_error(unsigned *err, unsigned code)
 // Grid-wide barrier for a launch whose workgroups are all resident (cooperative
 // launch).  bar[0] counts arrivals, bar[1] is the generation.  `gen` is the
 // generation this workgroup read at kernel start; it is advanced on each call.
-// Data exchanged across the barrier must use ld_coh / st_coh.  Returns false
-// (and raises KERR_BARRIER_TIMEOUT) if the wait hit the spin limit.
+// Every thread's stores complete before the workgroup arrives; one thread per
+// workgroup performs the agent-scope release before arriving and the acquire
+// after the wait, so plain loads after the barrier see every workgroup's
+// stores made before it.  Polling uses relaxed loads (an acquire load in the
+// loop would invalidate the cache on every iteration).  Returns false (and
+// raises KERR_BARRIER_TIMEOUT) if the wait hit the spin limit.
 CTMRG_DEVINL bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, unsigned *err)
 {
     __shared__ int ok_shared;
@@ -71,6 +75,7 @@ CTMRG_DEVINL bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, u
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
+        fence_release_agent();
         unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == nblocks - 1) {
             stu_coh(&bar[0], 0u);
@@ -87,11 +92,11 @@ CTMRG_DEVINL bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, u
                 }
             }
         }
+        fence_acquire_agent();
         ok_shared = ok;
     }
     gen += 1u;
     __syncthreads();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     return ok_shared != 0;
 }
 

@@ -87,8 +87,8 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
         if (tid < b) {
             double t = 0.0;
             for (int k = 0; k < RG; ++k) t += red[k * b + tid];
-            st_coh(&part[((long)buf * G + g) * b + tid], t);
-            if (i >= row0 && i < row0 + nloc) st_coh(&rowbuf[buf * b + tid], pan[(i - row0) * b + tid]);
+            part[((long)buf * G + g) * b + tid] = t;
+            if (i >= row0 && i < row0 + nloc) rowbuf[buf * b + tid] = pan[(i - row0) * b + tid];
         }
         grid_barrier(bar, G, gen, err);
         {
@@ -98,14 +98,14 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
             for (; k + 7 * RG < G; k += 8 * RG) {
                 double x[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = ld_coh(&part[((long)buf * G + k + u * RG) * b + cl]);
+                for (int u = 0; u < 8; ++u) x[u] = part[((long)buf * G + k + u * RG) * b + cl];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) t += x[u];
             }
-            for (; k < G; k += RG) t += ld_coh(&part[((long)buf * G + k) * b + cl]);
+            for (; k < G; k += RG) t += part[((long)buf * G + k) * b + cl];
             red[rg * b + cl] = t;
         }
-        if (tid < b) wv[tid] = ld_coh(&rowbuf[buf * b + tid]);
+        if (tid < b) wv[tid] = rowbuf[buf * b + tid];
         __syncthreads();
         if (tid < b) {
             double t = 0.0;
@@ -164,7 +164,7 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
             const double v2 = (gr == c2) ? 1.0 : (gr > c2 ? pan[r * b + c2] : 0.0);
             s += v1 * v2;
         }
-        st_coh(&gpart[(long)g * b * b + idx], s);
+        gpart[(long)g * b * b + idx] = s;
     }
     grid_barrier(bar, G, gen, err);
     if (g != 0) return;
@@ -174,11 +174,11 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
         for (; k + 8 <= G; k += 8) {
             double x[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = ld_coh(&gpart[(long)(k + u) * b * b + idx]);
+            for (int u = 0; u < 8; ++u) x[u] = gpart[(long)(k + u) * b * b + idx];
 #pragma unroll
             for (int u = 0; u < 8; ++u) s += x[u];
         }
-        for (; k < G; ++k) s += ld_coh(&gpart[(long)k * b * b + idx]);
+        for (; k < G; ++k) s += gpart[(long)k * b * b + idx];
         gram[idx] = s;
         Tm[idx] = 0.0;
     }
@@ -229,21 +229,36 @@ __global__ void extract_band_kernel(const double *A, long lda, int N, int b, dou
 // Stage 2: pipelined bulge chasing
 // ============================================================================
 
-// One wave per sweep, BW consecutive sweeps per workgroup.  Inside a workgroup a
-// sweep waits for its predecessor through an LDS progress word; only the first
-// sweep of a group waits across workgroups, on the progress word of the last
-// sweep of the previous group.  A sweep may run step t once its predecessor has
-// completed step t+2.  All band traffic is device-coherent (ld_coh / st_coh) and
-// a step's stores complete before its progress word is advanced, so no cache
-// writeback or invalidate is needed anywhere in the pipeline.
-//
-// A step holds its three b x b blocks in registers: lane (c, h) = (lane % b,
-// lane / b) owns column c, rows h*RPL .. h*RPL + RPL - 1 of each block, so every
-// load of the step is in flight at once; sums over a column combine the LPC
-// lanes of that column, sums over a row combine the b lanes of a row group.
-constexpr int BW = 8;
-
-CTMRG_DEVINL void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); __builtin_amdgcn_wave_barrier(); }
+// ---------------------------------------------------------------------------
+// One bulge-chasing step (sweep j, step t), executed by one wave.  The three
+// b x b blocks of the step (the left block whose first column is annihilated,
+// the symmetric diagonal block, the block below that receives the new bulge)
+// are held in registers: lane (c, h) = (lane % b, lane / b) owns column c,
+// rows h*RPL .. h*RPL + RPL - 1 of each block, so all loads of a block are in
+// flight together; sums over a column combine the LPC lanes of that column,
+// sums over a row combine the b lanes of a row group.  vs and ws are two
+// b-element LDS vectors private to the wave.  COH selects device-coherent
+// band accesses (for kernels in which workgroups exchange band data).
+// ---------------------------------------------------------------------------
+template <bool COH>
+CTMRG_DEVINL double ldb(const double *p)
+{
+    if constexpr (COH) return ld_coh(p);
+    else return *p;
+}
+template <bool COH>
+CTMRG_DEVINL void stb(double *p, double v)
+{
+    if constexpr (COH) st_coh(p, v);
+    else *p = v;
+}
+// Orders this wave's LDS accesses (the LDS unit serves one wave in order).
+CTMRG_DEVINL void lane_sync()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 template <int B>
 CTMRG_DEVINL double col_sum(double x)  // over the lanes sharing lane % B
@@ -258,18 +273,139 @@ CTMRG_DEVINL double row_sum(double x)  // over the lanes sharing lane / B
     return x;
 }
 
-template <int B>
-__global__ void __launch_bounds__(64 * BW)
-bulge_reg_kernel(double *band, int N, double *refl, double *rtau, int Tmax, unsigned *gprog, unsigned *err)
+template <int B, bool COH>
+CTMRG_DEVINL void bulge_step(double *band, int N, int j, int t, double *refl, double *rtau, int Tmax, double *vs,
+                             double *ws)
 {
     constexpr int LPC = 64 / B;   // lanes per column
     constexpr int RPL = B / LPC;  // rows per lane
+    const int lane = threadIdx.x & 63;
+    const int c = lane % B, h = lane / B, rb = h * RPL;
+    const int ld = 2 * B;
+    int r0, c0, ncl;
+    if (t == 0) { r0 = j + 1; c0 = j; ncl = 1; }
+    else { r0 = j + 1 + t * B; c0 = j + 1 + (t - 1) * B; ncl = B; }
+    const int len = min(r0 + B, N) - r0;
+    const int n0 = r0 + len, nbl = min(n0 + B, N) - n0;
+    const long safe = (long)r0 * ld;  // an in-bounds address for masked-off lanes
+    double tau = 0.0;
+    // ---- left block (lane: column c, rows rb..rb+RPL-1): Householder vector from
+    //      column 0, then L[:,c] -= tau v (v^T L[:,c]) for the columns c >= 1
+    {
+        double L[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = rb + i;
+            const bool ok = (c < ncl && r < len);
+            const double x = ldb<COH>(&band[ok ? (long)(c0 + c) * ld + (r0 + r - c0 - c) : safe]);
+            L[i] = ok ? x : 0.0;
+        }
+        const double alpha = __shfl(L[0], 0, 64);
+        double part = 0.0;
+        if (c == 0) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) part += (rb + i >= 1) ? L[i] * L[i] : 0.0;
+        }
+        const double xs = wave_sum(part);
+        double beta, scale;
+        if (xs == 0.0) { beta = alpha; tau = 0.0; scale = 0.0; }
+        else {
+            beta = -copysign(sqrt(alpha * alpha + xs), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        if (c == 0) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int r = rb + i;
+                const double vr = (r >= len) ? 0.0 : (r == 0 ? 1.0 : L[i] * scale);
+                vs[r] = vr;
+                refl[((long)j * Tmax + t) * B + r] = vr;
+                L[i] = (r == 0) ? beta : 0.0;
+            }
+        }
+        if (lane == 0) rtau[(long)j * Tmax + t] = tau;
+        lane_sync();
+        double sdot = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) sdot += vs[rb + i] * L[i];
+        const double wc = tau * col_sum<B>(sdot);
+        if (c >= 1) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) L[i] -= wc * vs[rb + i];
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = rb + i;
+            if (c < ncl && r < len) stb<COH>(&band[(long)(c0 + c) * ld + (r0 + r - c0 - c)], L[i]);
+        }
+    }
+    const double vc = vs[c];
+    // ---- diagonal block: p = tau D v, k = tau v^T p / 2, w = p - k v, D -= v w^T + w v^T
+    {
+        double D[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = rb + i;
+            const bool ok = (r < len && c < len);
+            const long off = (r >= c) ? (long)(r0 + c) * ld + (r - c) : (long)(r0 + r) * ld + (c - r);
+            const double x = ldb<COH>(&band[ok ? off : safe]);
+            D[i] = ok ? x : 0.0;
+        }
+        double pd = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) pd += D[i] * vs[rb + i];  // column c of D (= row c) dotted with v
+        const double pc = tau * col_sum<B>(pd);
+        const double kk = 0.5 * tau * wave_sum((h == 0 && c < len) ? vc * pc : 0.0);
+        const double wc = pc - kk * vc;
+        if (h == 0) ws[c] = (c < len) ? wc : 0.0;
+        lane_sync();
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = rb + i;
+            D[i] -= vs[r] * wc + ws[r] * vc;
+            if (r < len && c < len && r >= c) stb<COH>(&band[(long)(r0 + c) * ld + (r - c)], D[i]);
+        }
+    }
+    // ---- block below: y = B v (row sums), B -= tau y v^T
+    {
+        double Bm[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = rb + i;
+            const bool ok = (r < nbl && c < len);
+            const double x = ldb<COH>(&band[ok ? (long)(r0 + c) * ld + (n0 + r - r0 - c) : safe]);
+            Bm[i] = ok ? x : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = rb + i;
+            const double yr = row_sum<B>(Bm[i] * vc);
+            Bm[i] -= tau * yr * vc;
+            if (r < nbl && c < len) stb<COH>(&band[(long)(r0 + c) * ld + (n0 + r - r0 - c)], Bm[i]);
+        }
+    }
+}
+
+// Pipelined form: one wave per sweep, BW consecutive sweeps per workgroup.  A
+// sweep may run step t once its predecessor has completed step t+2.  Inside a
+// workgroup a sweep waits on an LDS progress word; the first sweep of a group
+// waits across workgroups on the progress word of the last sweep of the
+// previous group (words PSTRIDE apart, one cache line each).  With COH all band
+// traffic is device-coherent and a step's stores complete before its progress
+// word advances; without it, the cross-workgroup handoff uses an agent-scope
+// release by the publisher and an acquire by the waiter.
+constexpr int BW = 8;
+constexpr int PSTRIDE = 32;
+
+template <int B, bool COH>
+__global__ void __launch_bounds__(64 * BW)
+bulge_pipe_kernel(double *band, int N, double *refl, double *rtau, int Tmax, unsigned *gprog, unsigned *err)
+{
     __shared__ int lprog[BW];
     __shared__ int labort;
     __shared__ double vsh[BW][B], wsh[BW][B];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int c = lane % B, h = lane / B, rb = h * RPL;
-    const int ld = 2 * B;
     const int nsw = N - 2;
     const int ngroups = (nsw + BW - 1) / BW;
     if (threadIdx.x == 0) labort = 0;
@@ -282,138 +418,53 @@ bulge_reg_kernel(double *band, int N, double *refl, double *rtau, int Tmax, unsi
         if (j >= nsw) continue;
         const int ns = bulge_nsteps(N, B, j);
         const int nsprev = (j > 0) ? bulge_nsteps(N, B, j - 1) : 0;
-        double *vs = vsh[wave], *ws = wsh[wave];
         for (int t = 0; t < ns; ++t) {
             if (j > 0) {
                 const int need = min(t + 3, nsprev);
                 unsigned spins = 0;
                 int ok = 1;
                 if (wave == 0) {
-                    while ((int)ldu_coh(&gprog[grp - 1]) < need) {
+                    while ((int)ldu_coh(&gprog[(long)(grp - 1) * PSTRIDE]) < need) {
                         __builtin_amdgcn_s_sleep(1);
                         if (++spins > CTMRG_SPIN_LIMIT) { ok = 0; break; }
                     }
+                    if (!COH) fence_acquire_agent();
                 } else {
                     while (__hip_atomic_load(&lprog[wave - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
                         __builtin_amdgcn_s_sleep(1);
                         if (++spins > CTMRG_SPIN_LIMIT) { ok = 0; break; }
                     }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 }
                 if (!ok) {
                     if (lane == 0) { raise_error(err, KERR_PIPELINE_TIMEOUT); labort = 1; }
                     break;
                 }
             }
-            int r0, c0, ncl;
-            if (t == 0) { r0 = j + 1; c0 = j; ncl = 1; }
-            else { r0 = j + 1 + t * B; c0 = j + 1 + (t - 1) * B; ncl = B; }
-            const int len = min(r0 + B, N) - r0;
-            const int n0 = r0 + len, nbl = min(n0 + B, N) - n0;
-            const long safe = (long)r0 * ld;  // an in-bounds address for masked-off lanes
-            double tau = 0.0;
-            // ---- left block (lane: column c, rows rb..rb+RPL-1): Householder vector from
-            //      column 0, then L[:,c] -= tau v (v^T L[:,c]) for the columns c >= 1
-            {
-                double L[RPL];
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    const int r = rb + i;
-                    const bool ok = (c < ncl && r < len);
-                    const double x = ld_coh(&band[ok ? (long)(c0 + c) * ld + (r0 + r - c0 - c) : safe]);
-                    L[i] = ok ? x : 0.0;
-                }
-                const double alpha = __shfl(L[0], 0, 64);
-                double part = 0.0;
-                if (c == 0) {
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) part += (rb + i >= 1) ? L[i] * L[i] : 0.0;
-                }
-                const double xs = wave_sum(part);
-                double beta, scale;
-                if (xs == 0.0) { beta = alpha; tau = 0.0; scale = 0.0; }
-                else {
-                    beta = -copysign(sqrt(alpha * alpha + xs), alpha);
-                    tau = (beta - alpha) / beta;
-                    scale = 1.0 / (alpha - beta);
-                }
-                if (c == 0) {
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) {
-                        const int r = rb + i;
-                        const double vr = (r >= len) ? 0.0 : (r == 0 ? 1.0 : L[i] * scale);
-                        vs[r] = vr;
-                        refl[((long)j * Tmax + t) * B + r] = vr;
-                        L[i] = (r == 0) ? beta : 0.0;
-                    }
-                }
-                if (lane == 0) rtau[(long)j * Tmax + t] = tau;
-                wave_fence();
-                double sdot = 0.0;
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) sdot += vs[rb + i] * L[i];
-                const double wc = tau * col_sum<B>(sdot);
-                if (c >= 1) {
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) L[i] -= wc * vs[rb + i];
-                }
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    const int r = rb + i;
-                    if (c < ncl && r < len) st_coh(&band[(long)(c0 + c) * ld + (r0 + r - c0 - c)], L[i]);
-                }
+            bulge_step<B, COH>(band, N, j, t, refl, rtau, Tmax, vsh[wave], wsh[wave]);
+            if (COH) wait_mem();
+            if (wave == BW - 1) {
+                if (!COH) fence_release_agent();
+                if (lane == 0) stu_coh(&gprog[(long)grp * PSTRIDE], (unsigned)(t + 1));
             }
-            const double vc = vs[c];
-            // ---- diagonal block: p = tau D v, k = tau v^T p / 2, w = p - k v, D -= v w^T + w v^T
-            {
-                double D[RPL];
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    const int r = rb + i;
-                    const bool ok = (r < len && c < len);
-                    const long off = (r >= c) ? (long)(r0 + c) * ld + (r - c) : (long)(r0 + r) * ld + (c - r);
-                    const double x = ld_coh(&band[ok ? off : safe]);
-                    D[i] = ok ? x : 0.0;
-                }
-                double pd = 0.0;
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) pd += D[i] * vs[rb + i];  // column c of D (= row c) dotted with v
-                const double pc = tau * col_sum<B>(pd);
-                const double kk = 0.5 * tau * wave_sum((h == 0 && c < len) ? vc * pc : 0.0);
-                const double wc = pc - kk * vc;
-                if (h == 0) ws[c] = (c < len) ? wc : 0.0;
-                wave_fence();
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    const int r = rb + i;
-                    D[i] -= vs[r] * wc + ws[r] * vc;
-                    if (r < len && c < len && r >= c) st_coh(&band[(long)(r0 + c) * ld + (r - c)], D[i]);
-                }
-            }
-            // ---- block below: y = B v (row sums), B -= tau y v^T
-            {
-                double Bm[RPL];
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    const int r = rb + i;
-                    const bool ok = (r < nbl && c < len);
-                    const double x = ld_coh(&band[ok ? (long)(r0 + c) * ld + (n0 + r - r0 - c) : safe]);
-                    Bm[i] = ok ? x : 0.0;
-                }
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) {
-                    const int r = rb + i;
-                    const double yr = row_sum<B>(Bm[i] * vc);
-                    Bm[i] -= tau * yr * vc;
-                    if (r < nbl && c < len) st_coh(&band[(long)(r0 + c) * ld + (n0 + r - r0 - c)], Bm[i]);
-                }
-            }
-            // ---- publish completion of step t (the coherent stores above complete first)
-            wait_mem();
-            if (wave == BW - 1 && lane == 0) stu_coh(&gprog[grp], (unsigned)(t + 1));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0) __hip_atomic_store(&lprog[wave], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
     }
+}
+
+// Wavefront form: the steps (j, t) with 3 j + t = tau are mutually independent
+// (a sweep trails its predecessor by three steps), so one launch per tau runs
+// them all, one wave per step; kernel boundaries order the launches.
+template <int B>
+__global__ void __launch_bounds__(64)
+bulge_front_kernel(double *band, int N, int tau, int jlo, double *refl, double *rtau, int Tmax)
+{
+    __shared__ double vsh[B], wsh[B];
+    const int j = jlo + blockIdx.x;
+    const int t = tau - 3 * j;
+    if (j > N - 3 || t < 0 || t >= bulge_nsteps(N, B, j)) return;
+    bulge_step<B, false>(band, N, j, t, refl, rtau, Tmax, vsh, wsh);
 }
 
 __global__ void band_to_tridiag_kernel(const double *band, int N, int b, double *d, double *e, double *e2)
@@ -891,7 +942,7 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += align_up(sizeof(double) * (size_t)Nmax * 2 * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax);
-    s += align_up(sizeof(unsigned) * (size_t)Nmax);
+    s += align_up(sizeof(unsigned) * (size_t)Nmax * PSTRIDE);
     s += align_up(sizeof(double) * (size_t)nJ * Tmax * b * b);
     s += 4 * align_up(sizeof(double) * (size_t)Nmax);
     s += 2 * align_up(sizeof(double) * (size_t)Nmax * kmax);
@@ -932,7 +983,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.band, sizeof(double) * (size_t)Nmax * 2 * b},
         {(void **)&w.refl, sizeof(double) * (size_t)Nmax * w.Tmax * b},
         {(void **)&w.rtau, sizeof(double) * (size_t)Nmax * w.Tmax},
-        {(void **)&w.progress, sizeof(unsigned) * (size_t)Nmax},
+        {(void **)&w.progress, sizeof(unsigned) * (size_t)Nmax * PSTRIDE},
         {(void **)&w.T2, sizeof(double) * (size_t)w.nJmax * w.Tmax * b * b},
         {(void **)&w.d, sizeof(double) * (size_t)Nmax},
         {(void **)&w.e, sizeof(double) * (size_t)Nmax},
@@ -1046,15 +1097,21 @@ hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s)
     hipLaunchKernelGGL(extract_band_kernel, dim3(std::min(4096, ceil_div((long)N * 2 * b, 256))), dim3(256), 0, s, A,
                        lda, N, b, w.band);
     if (N > 2) {
-        e = hipMemsetAsync(w.progress, 0, sizeof(unsigned) * N, s);
-        if (e != hipSuccess) return e;
+        // one launch per wavefront tau = 3 j + t of independent steps
         const int Tmax = w.Tmax;
-        double *band = w.band;
-        const int ngroups = (N - 2 + BW - 1) / BW;
-        int G = std::min(ngroups, 128);
-        void *args[] = {&band, (void *)&N, &w.refl, &w.rtau, (void *)&Tmax, &w.progress, &w.err};
-        const void *fn = (b == 32) ? (const void *)bulge_reg_kernel<32> : (const void *)bulge_reg_kernel<16>;
-        e = launch_coop(fn, dim3(G), dim3(64 * BW), args, 0, s);
+        const int taumax = 3 * (N - 3) + bulge_nsteps(N, b, N - 3);
+        for (int tau = 0; tau < taumax; ++tau) {
+            const int jhi = std::min(tau / 3, N - 3);
+            const int jlo = std::max(0, (tau - (Tmax - 1)) / 3);
+            if (jhi < jlo) continue;
+            if (b == 32)
+                hipLaunchKernelGGL(bulge_front_kernel<32>, dim3(jhi - jlo + 1), dim3(64), 0, s, w.band, N, tau, jlo,
+                                   w.refl, w.rtau, Tmax);
+            else
+                hipLaunchKernelGGL(bulge_front_kernel<16>, dim3(jhi - jlo + 1), dim3(64), 0, s, w.band, N, tau, jlo,
+                                   w.refl, w.rtau, Tmax);
+        }
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     mark(w, MK_BULGE, s);
