@@ -387,6 +387,103 @@ CTMRG_DEVINL void bulge_step(double *band, int N, int j, int t, double *refl, do
     }
 }
 
+// The same step with all three blocks loaded at the start, so that a step costs
+// one memory round trip (used where a wave has the register budget to itself).
+template <int B>
+CTMRG_DEVINL void bulge_step_pre(double *band, int N, int j, int t, double *refl, double *rtau, int Tmax, double *vs,
+                                 double *ws)
+{
+    constexpr int LPC = 64 / B;
+    constexpr int RPL = B / LPC;
+    const int lane = threadIdx.x & 63;
+    const int c = lane % B, h = lane / B, rb = h * RPL;
+    const int ld = 2 * B;
+    int r0, c0, ncl;
+    if (t == 0) { r0 = j + 1; c0 = j; ncl = 1; }
+    else { r0 = j + 1 + t * B; c0 = j + 1 + (t - 1) * B; ncl = B; }
+    const int len = min(r0 + B, N) - r0;
+    const int n0 = r0 + len, nbl = min(n0 + B, N) - n0;
+    const long safe = (long)r0 * ld;  // an in-bounds address for masked-off lanes
+    double L[RPL], D[RPL], Bm[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int r = rb + i;
+        const bool okl = (c < ncl && r < len);
+        const bool okd = (r < len && c < len);
+        const bool okb = (r < nbl && c < len);
+        const long offd = (r >= c) ? (long)(r0 + c) * ld + (r - c) : (long)(r0 + r) * ld + (c - r);
+        const double xl = band[okl ? (long)(c0 + c) * ld + (r0 + r - c0 - c) : safe];
+        const double xd = band[okd ? offd : safe];
+        const double xb = band[okb ? (long)(r0 + c) * ld + (n0 + r - r0 - c) : safe];
+        L[i] = okl ? xl : 0.0;
+        D[i] = okd ? xd : 0.0;
+        Bm[i] = okb ? xb : 0.0;
+    }
+    // Householder vector from column 0 of the left block
+    const double alpha = __shfl(L[0], 0, 64);
+    double part = 0.0;
+    if (c == 0) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) part += (rb + i >= 1) ? L[i] * L[i] : 0.0;
+    }
+    const double xs = wave_sum(part);
+    double beta, tau, scale;
+    if (xs == 0.0) { beta = alpha; tau = 0.0; scale = 0.0; }
+    else {
+        beta = -copysign(sqrt(alpha * alpha + xs), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+    }
+    if (c == 0) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = rb + i;
+            const double vr = (r >= len) ? 0.0 : (r == 0 ? 1.0 : L[i] * scale);
+            vs[r] = vr;
+            refl[((long)j * Tmax + t) * B + r] = vr;
+            L[i] = (r == 0) ? beta : 0.0;
+        }
+    }
+    if (lane == 0) rtau[(long)j * Tmax + t] = tau;
+    lane_sync();
+    const double vc = vs[c];
+    // left block, columns >= 1: L[:,c] -= tau v (v^T L[:,c])
+    {
+        double sdot = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) sdot += vs[rb + i] * L[i];
+        const double wc = tau * col_sum<B>(sdot);
+        if (c >= 1) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) L[i] -= wc * vs[rb + i];
+        }
+    }
+    // diagonal block: p = tau D v, k = tau v^T p / 2, w = p - k v, D -= v w^T + w v^T
+    double pd = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) pd += D[i] * vs[rb + i];
+    const double pc = tau * col_sum<B>(pd);
+    const double kk = 0.5 * tau * wave_sum((h == 0 && c < len) ? vc * pc : 0.0);
+    const double wc = pc - kk * vc;
+    if (h == 0) ws[c] = (c < len) ? wc : 0.0;
+    lane_sync();
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) D[i] -= vs[rb + i] * wc + ws[rb + i] * vc;
+    // block below: y = B v (row sums), B -= tau y v^T
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const double yr = row_sum<B>(Bm[i] * vc);
+        Bm[i] -= tau * yr * vc;
+    }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int r = rb + i;
+        if (c < ncl && r < len) band[(long)(c0 + c) * ld + (r0 + r - c0 - c)] = L[i];
+        if (r < len && c < len && r >= c) band[(long)(r0 + c) * ld + (r - c)] = D[i];
+        if (r < nbl && c < len) band[(long)(r0 + c) * ld + (n0 + r - r0 - c)] = Bm[i];
+    }
+}
+
 // Pipelined form: one wave per sweep, BW consecutive sweeps per workgroup.  A
 // sweep may run step t once its predecessor has completed step t+2.  Inside a
 // workgroup a sweep waits on an LDS progress word; the first sweep of a group
@@ -464,7 +561,7 @@ bulge_front_kernel(double *band, int N, int tau, int jlo, double *refl, double *
     const int j = jlo + blockIdx.x;
     const int t = tau - 3 * j;
     if (j > N - 3 || t < 0 || t >= bulge_nsteps(N, B, j)) return;
-    bulge_step<B, false>(band, N, j, t, refl, rtau, Tmax, vsh, wsh);
+    bulge_step_pre<B>(band, N, j, t, refl, rtau, Tmax, vsh, wsh);
 }
 
 __global__ void band_to_tridiag_kernel(const double *band, int N, int b, double *d, double *e, double *e2)
@@ -520,6 +617,9 @@ __device__ inline int sturm_count(const double *d, const double *e2, int N, doub
     return cnt;
 }
 
+// Four-shift multisection: each iteration evaluates four independent Sturm
+// counts at the quintisection points of the bracket (their recurrences
+// interleave in one thread), gaining log2(5) bits per pass over T.
 __global__ void __launch_bounds__(256) bisect_kernel(const double *d, const double *e2, int N, const double *bounds, double *evals)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -527,12 +627,59 @@ __global__ void __launch_bounds__(256) bisect_kernel(const double *d, const doub
     double lo = bounds[0], hi = bounds[1];
     const double pivmin = bounds[2], tn = bounds[3];
     const double abstol = DBL_EPSILON * tn;
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;
+    for (int it = 0; it < 120; ++it) {
         if (hi - lo <= fmax(abstol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
-        if (sturm_count(d, e2, N, mid, pivmin) <= k) lo = mid;
-        else hi = mid;
+        const double w = (hi - lo) * 0.2;
+        double x[4], q[4];
+        int cnt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            x[u] = lo + (u + 1) * w;
+            q[u] = d[0] - x[u];
+            cnt[u] = q[u] < 0.0 ? 1 : 0;
+        }
+        if (!(x[0] > lo) || !(x[3] < hi)) {  // bracket too narrow to split in five
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (sturm_count(d, e2, N, mid, pivmin) <= k) lo = mid;
+            else hi = mid;
+            continue;
+        }
+        for (int i0 = 1; i0 < N; i0 += 16) {
+            const int nI = min(16, N - i0);
+            double dv[16], ev[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int i = (u < nI) ? i0 + u : i0;
+                dv[u] = d[i];
+                ev[u] = e2[i - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                if (u < nI) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        double qq = q[v];
+                        if (fabs(qq) < pivmin) qq = -pivmin;
+                        qq = dv[u] - x[v] - ev[u] / qq;
+                        cnt[v] += qq < 0.0 ? 1 : 0;
+                        q[v] = qq;
+                    }
+                }
+            }
+        }
+        // the eigenvalue k lies in [x_u, x_{u+1}) for the first u with count(x_{u+1}) > k
+        double nlo = lo, nhi = hi;
+#pragma unroll
+        for (int u = 3; u >= 0; --u) {
+            if (cnt[u] <= k) { nlo = x[u]; break; }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (cnt[u] > k) { nhi = x[u]; break; }
+        }
+        lo = nlo;
+        hi = nhi;
     }
     evals[k] = 0.5 * (lo + hi);
 }
@@ -651,8 +798,14 @@ post_eigen_kernel(const double *ev, int N, int m, double gap_tol, double rank_to
 // ============================================================================
 
 // One thread per tight cluster; the LU scratch and the iterate of thread c are
-// interleaved (element i of array a at lu[(a*N + i)*nth + c]) so that the lanes of a wave
-// touch adjacent addresses.
+// interleaved (element i of array a at lu[(a*N + i)*nth + c]) so that the lanes
+// of a wave touch adjacent addresses.  The factorization of T - lambda I with
+// partial pivoting carries its recurrence in registers and reads only d and e;
+// the triangular solves work in chunks of IV_CH rows whose loads are all issued
+// before the chunk's recurrence runs.  The normalization of an iterate is
+// folded into the next pass that reads it.
+constexpr int IV_CH = 16;
+
 __global__ void __launch_bounds__(64)
 invit_kernel(const double *d, const double *e, int N, const double *selval, const int *clist, const int *cstart,
              int ncl, double *ZT, int ldz, double *lu, int *ipiv, const double *bounds, unsigned *err)
@@ -666,85 +819,117 @@ invit_kernel(const double *d, const double *e, int N, const double *selval, cons
 #define DD(i) lu[((long)1 * N + (i)) * nth + c]
 #define DU(i) lu[((long)2 * N + (i)) * nth + c]
 #define DU2(i) lu[((long)3 * N + (i)) * nth + c]
-#define IP(i) ipiv[(long)(i) * nth + c]
 #define X(i) lu[((long)4 * N + (i)) * nth + c]
+#define IP(i) ipiv[(long)(i) * nth + c]
     for (int q = cstart[c]; q < cstart[c + 1]; ++q) {
         const int j = clist[q];
         const double lam = selval[j];
-        // LU with partial pivoting of T - lam I
-        for (int i = 0; i < N; ++i) {
-            DD(i) = d[i] - lam;
-            if (i < N - 1) { DL(i) = e[i]; DU(i) = e[i]; }
-            DU2(i) = 0.0;
-        }
+        // ---- LU with partial pivoting of T - lam I (rows i, i+1 swapped when |e_i| > |pivot|)
+        double ddi = d[0] - lam, dui = (N > 1) ? e[0] : 0.0;
         for (int i = 0; i < N - 1; ++i) {
-            const double di = DD(i), li = DL(i);
-            if (fabs(di) >= fabs(li)) {
-                const double piv = (fabs(di) < pivmin) ? (di < 0.0 ? -pivmin : pivmin) : di;
-                DD(i) = piv;
+            const double li = e[i];
+            const double dn = d[i + 1] - lam;
+            const double dun = (i < N - 2) ? e[i + 1] : 0.0;
+            if (fabs(ddi) >= fabs(li)) {
+                const double piv = (fabs(ddi) < pivmin) ? (ddi < 0.0 ? -pivmin : pivmin) : ddi;
                 const double f = li / piv;
-                DL(i) = f;
-                DD(i + 1) = DD(i + 1) - f * DU(i);
-                IP(i) = 0;
+                DD(i) = piv; DL(i) = f; DU(i) = dui; DU2(i) = 0.0; IP(i) = 0;
+                ddi = dn - f * dui;
+                dui = dun;
             } else {
-                const double f = di / li;
-                DD(i) = li;
-                DL(i) = f;
-                const double tmp = DU(i);
-                DU(i) = DD(i + 1);
-                DD(i + 1) = tmp - f * DD(i + 1);
-                if (i < N - 2) {
-                    DU2(i) = DU(i + 1);
-                    DU(i + 1) = -f * DU(i + 1);
-                }
-                IP(i) = 1;
+                const double f = ddi / li;
+                DD(i) = li; DL(i) = f; DU(i) = dn; DU2(i) = dun; IP(i) = 1;
+                ddi = dui - f * dn;
+                dui = -f * dun;
             }
         }
-        if (fabs(DD(N - 1)) < pivmin) DD(N - 1) = (DD(N - 1) < 0.0 ? -pivmin : pivmin);
-        // start vector
-        double nrm = 0.0;
+        if (fabs(ddi) < pivmin) ddi = (ddi < 0.0 ? -pivmin : pivmin);
+        DD(N - 1) = ddi;
+        // ---- start vector (counter-based random numbers)
+        double nrm2 = 0.0;
         for (int i = 0; i < N; ++i) {
             const double x = hash_uniform(((uint64_t)(j + 1) << 32) ^ (uint64_t)i);
             X(i) = x;
-            nrm += x * x;
+            nrm2 += x * x;
         }
-        nrm = 1.0 / sqrt(nrm);
-        for (int i = 0; i < N; ++i) X(i) *= nrm;
+        double sc = 1.0 / sqrt(nrm2);  // pending scale of the stored iterate
         for (int it = 0; it < 3; ++it) {
-            // forward: L with row interchanges
-            for (int i = 0; i < N - 1; ++i) {
-                if (IP(i) == 0) {
-                    X(i + 1) = X(i + 1) - DL(i) * X(i);
-                } else {
-                    const double t = X(i);
-                    X(i) = X(i + 1);
-                    X(i + 1) = t - DL(i) * X(i);
-                }
+            // forward: unit lower factor with row interchanges, applied to sc * X
+            double xi = X(0) * sc;
+            for (int i0 = 0; i0 < N - 1; i0 += IV_CH) {
+                const int nI = min(IV_CH, N - 1 - i0);
+                double xn[IV_CH], dl[IV_CH], out[IV_CH];
+                int ip[IV_CH];
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) { xn[u] = X(i0 + u + 1) * sc; dl[u] = DL(i0 + u); ip[u] = IP(i0 + u); }
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) {
+                        if (ip[u] == 0) { out[u] = xi; xi = xn[u] - dl[u] * xi; }
+                        else { out[u] = xn[u]; xi = xi - dl[u] * xn[u]; }
+                    }
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) X(i0 + u) = out[u];
             }
-            // backward: U with two superdiagonals
-            X(N - 1) = X(N - 1) / DD(N - 1);
-            if (N > 1) X(N - 2) = (X(N - 2) - DU(N - 2) * X(N - 1)) / DD(N - 2);
-            for (int i = N - 3; i >= 0; --i) X(i) = (X(i) - DU(i) * X(i + 1) - DU2(i) * X(i + 2)) / DD(i);
-            // scale down, then orthogonalize against the earlier members of the cluster
-            double mx = 0.0;
-            for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(X(i)));
-            if (!(mx > 0.0) || !isfinite(mx)) {
+            X(N - 1) = xi;
+            // backward: upper factor with two superdiagonals; accumulate the norm
+            double x1 = X(N - 1) / DD(N - 1);
+            X(N - 1) = x1;
+            nrm2 = x1 * x1;
+            double x2 = 0.0;
+            if (N > 1) {
+                const double x0 = (X(N - 2) - DU(N - 2) * x1) / DD(N - 2);
+                X(N - 2) = x0;
+                nrm2 += x0 * x0;
+                x2 = x1;
+                x1 = x0;
+            }
+            for (int i0 = N - 3; i0 >= 0; i0 -= IV_CH) {
+                const int nI = min(IV_CH, i0 + 1);
+                double xv[IV_CH], du[IV_CH], du2[IV_CH], dd[IV_CH];
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) { xv[u] = X(i0 - u); du[u] = DU(i0 - u); du2[u] = DU2(i0 - u); dd[u] = DD(i0 - u); }
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) {
+                        const double xnew = (xv[u] - du[u] * x1 - du2[u] * x2) / dd[u];
+                        x2 = x1;
+                        x1 = xnew;
+                        xv[u] = xnew;
+                        nrm2 += xnew * xnew;
+                    }
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) X(i0 - u) = xv[u];
+            }
+            if (!(nrm2 > 0.0) || !isfinite(nrm2)) {
                 raise_error(err, KERR_NONFINITE);
-                mx = 1.0;
+                nrm2 = 1.0;
             }
-            for (int i = 0; i < N; ++i) X(i) /= mx;
-            for (int qq = cstart[c]; qq < q; ++qq) {
-                const int jp = clist[qq];
-                double dot = 0.0;
-                for (int i = 0; i < N; ++i) dot += ZT[(long)i * ldz + jp] * X(i);
-                for (int i = 0; i < N; ++i) X(i) -= dot * ZT[(long)i * ldz + jp];
+            sc = 1.0 / sqrt(nrm2);
+            if (q > cstart[c]) {
+                // orthogonalize against the earlier members of the cluster (in ZT), renormalize
+#pragma unroll 16
+                for (int i = 0; i < N; ++i) X(i) *= sc;
+                for (int qq = cstart[c]; qq < q; ++qq) {
+                    const int jp = clist[qq];
+                    double dot = 0.0;
+#pragma unroll 16
+                    for (int i = 0; i < N; ++i) dot += ZT[(long)i * ldz + jp] * X(i);
+#pragma unroll 16
+                    for (int i = 0; i < N; ++i) X(i) -= dot * ZT[(long)i * ldz + jp];
+                }
+                nrm2 = 0.0;
+#pragma unroll 16
+                for (int i = 0; i < N; ++i) nrm2 += X(i) * X(i);
+                sc = (nrm2 > 0.0) ? 1.0 / sqrt(nrm2) : 0.0;
             }
-            nrm = 0.0;
-            for (int i = 0; i < N; ++i) nrm += X(i) * X(i);
-            nrm = (nrm > 0.0) ? 1.0 / sqrt(nrm) : 0.0;
-            for (int i = 0; i < N; ++i) X(i) *= nrm;
         }
-        for (int i = 0; i < N; ++i) ZT[(long)i * ldz + j] = X(i);
+#pragma unroll 16
+        for (int i = 0; i < N; ++i) ZT[(long)i * ldz + j] = X(i) * sc;
     }
 #undef DL
 #undef DD
@@ -1060,9 +1245,9 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
         double *A22 = A + (long)r0 * lda + r0;
         // Y = A22 V
         {
-            const long tiles = ceil_div(n, 64);
+            const long tiles = (long)ceil_div(n, 128) * ceil_div(b, 32);
             const int sp = splits_for(tiles, n, 256);
-            e = gemm_f64_splitk(A_RM{A22, lda}, B_RM{Vp, b}, EpiStore{w.Y, b, 1.0}, n, b, n, sp, w.splitk, s);
+            e = gemm_f64_splitk(A_RM{A22, lda}, B_RM{Vp, b}, EpiStore{w.Y, b, 1.0}, n, b, n, sp, w.splitk, s, GEMM_TALL);
             if (e != hipSuccess) return e;
         }
         // X = Y T
@@ -1081,7 +1266,7 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
         e = gemm_f64(GEMM_TALL, A_RM{Vp, b}, B_RM{w.sm + b * b, b}, EpiWform{w.X, Vp, w.VW, w.WV, b}, n, b, b, s);
         if (e != hipSuccess) return e;
         // A22 -= [V|W] [W|V]^T
-        e = gemm_f64(GEMM_LARGE, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, n, 2 * b, s);
+        e = gemm_f64(GEMM_SMALL, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, n, 2 * b, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

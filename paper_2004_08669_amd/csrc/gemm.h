@@ -192,18 +192,24 @@ hipError_t gemm_f64(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K,
 }
 
 // Split-K GEMM: partials go to `work` (splits * M * N doubles), then reduced.
+// shape GEMM_SMALL (64 x 64 tiles) or GEMM_TALL (128 x 32 tiles, narrow outputs).
 template <class LA, class LB, class EPI>
-hipError_t gemm_f64_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int splits, double *work,
-                           hipStream_t s)
+hipError_t gemm_f64_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int splits, double *work, hipStream_t s,
+                           GemmShape shape = GEMM_SMALL)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    if (splits <= 1) return gemm_f64(GEMM_SMALL, la, lb, epi, M, N, K, s);
+    if (splits <= 1) return gemm_f64(shape, la, lb, epi, M, N, K, s);
     int kchunk = ceil_div(ceil_div(K, splits), 16) * 16;
     splits = ceil_div(K, kchunk);
     EpiPartial part{work, M, N};
-    hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 16, 2, 2, LA, LB, EpiPartial>),
-                       dim3(ceil_div(M, 64), ceil_div(N, 64), splits), dim3(256), 0, s, la, lb, part, M, N,
-                       K, kchunk);
+    if (shape == GEMM_TALL)
+        hipLaunchKernelGGL((gemm_f64_kernel<128, 32, 16, 4, 1, LA, LB, EpiPartial>),
+                           dim3(ceil_div(M, 128), ceil_div(N, 32), splits), dim3(256), 0, s, la, lb, part, M, N, K,
+                           kchunk);
+    else
+        hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 16, 2, 2, LA, LB, EpiPartial>),
+                           dim3(ceil_div(M, 64), ceil_div(N, 64), splits), dim3(256), 0, s, la, lb, part, M, N, K,
+                           kchunk);
     long total = (long)M * N;
     int blocks = (int)((total + 255) / 256);
     if (blocks > 4096) blocks = 4096;
