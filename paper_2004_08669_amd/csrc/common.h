@@ -47,7 +47,6 @@ CTMRG_DEVINL void wait_mem()
 // Error flags raised by kernels (bitwise OR into a device word).
 enum {
     KERR_BARRIER_TIMEOUT = 1,
-    KERR_PIPELINE_TIMEOUT = 2,
     KERR_NONFINITE = 4,
     KERR_NO_CONVERGENCE = 8,
 };

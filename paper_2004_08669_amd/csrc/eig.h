@@ -39,7 +39,6 @@ struct EigWork {
     double *band = nullptr;    // N x 2b column-major band
     double *refl = nullptr;    // (N * Tmax * b) reflectors
     double *rtau = nullptr;    // (N * Tmax)
-    unsigned *progress = nullptr;  // N
     double *T2 = nullptr;      // nJ * Tmax * b * b
     // tridiagonal
     double *d = nullptr, *e = nullptr, *e2 = nullptr;  // N

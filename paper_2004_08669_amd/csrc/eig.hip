@@ -226,32 +226,8 @@ __global__ void extract_band_kernel(const double *A, long lda, int N, int b, dou
 }
 
 // ============================================================================
-// Stage 2: pipelined bulge chasing
+// Stage 2: bulge chasing (band to tridiagonal)
 // ============================================================================
-
-// ---------------------------------------------------------------------------
-// One bulge-chasing step (sweep j, step t), executed by one wave.  The three
-// b x b blocks of the step (the left block whose first column is annihilated,
-// the symmetric diagonal block, the block below that receives the new bulge)
-// are held in registers: lane (c, h) = (lane % b, lane / b) owns column c,
-// rows h*RPL .. h*RPL + RPL - 1 of each block, so all loads of a block are in
-// flight together; sums over a column combine the LPC lanes of that column,
-// sums over a row combine the b lanes of a row group.  vs and ws are two
-// b-element LDS vectors private to the wave.  COH selects device-coherent
-// band accesses (for kernels in which workgroups exchange band data).
-// ---------------------------------------------------------------------------
-template <bool COH>
-CTMRG_DEVINL double ldb(const double *p)
-{
-    if constexpr (COH) return ld_coh(p);
-    else return *p;
-}
-template <bool COH>
-CTMRG_DEVINL void stb(double *p, double v)
-{
-    if constexpr (COH) st_coh(p, v);
-    else *p = v;
-}
 // Orders this wave's LDS accesses (the LDS unit serves one wave in order).
 CTMRG_DEVINL void lane_sync()
 {
@@ -266,129 +242,18 @@ CTMRG_DEVINL double col_sum(double x)  // over the lanes sharing lane % B
     for (int off = B; off < 64; off <<= 1) x += __shfl_xor(x, off, 64);
     return x;
 }
-template <int B>
-CTMRG_DEVINL double row_sum(double x)  // over the lanes sharing lane / B
-{
-    for (int off = 1; off < B; off <<= 1) x += __shfl_xor(x, off, 64);
-    return x;
-}
 
-template <int B, bool COH>
-CTMRG_DEVINL void bulge_step(double *band, int N, int j, int t, double *refl, double *rtau, int Tmax, double *vs,
-                             double *ws)
-{
-    constexpr int LPC = 64 / B;   // lanes per column
-    constexpr int RPL = B / LPC;  // rows per lane
-    const int lane = threadIdx.x & 63;
-    const int c = lane % B, h = lane / B, rb = h * RPL;
-    const int ld = 2 * B;
-    int r0, c0, ncl;
-    if (t == 0) { r0 = j + 1; c0 = j; ncl = 1; }
-    else { r0 = j + 1 + t * B; c0 = j + 1 + (t - 1) * B; ncl = B; }
-    const int len = min(r0 + B, N) - r0;
-    const int n0 = r0 + len, nbl = min(n0 + B, N) - n0;
-    const long safe = (long)r0 * ld;  // an in-bounds address for masked-off lanes
-    double tau = 0.0;
-    // ---- left block (lane: column c, rows rb..rb+RPL-1): Householder vector from
-    //      column 0, then L[:,c] -= tau v (v^T L[:,c]) for the columns c >= 1
-    {
-        double L[RPL];
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int r = rb + i;
-            const bool ok = (c < ncl && r < len);
-            const double x = ldb<COH>(&band[ok ? (long)(c0 + c) * ld + (r0 + r - c0 - c) : safe]);
-            L[i] = ok ? x : 0.0;
-        }
-        const double alpha = __shfl(L[0], 0, 64);
-        double part = 0.0;
-        if (c == 0) {
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) part += (rb + i >= 1) ? L[i] * L[i] : 0.0;
-        }
-        const double xs = wave_sum(part);
-        double beta, scale;
-        if (xs == 0.0) { beta = alpha; tau = 0.0; scale = 0.0; }
-        else {
-            beta = -copysign(sqrt(alpha * alpha + xs), alpha);
-            tau = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        if (c == 0) {
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const int r = rb + i;
-                const double vr = (r >= len) ? 0.0 : (r == 0 ? 1.0 : L[i] * scale);
-                vs[r] = vr;
-                refl[((long)j * Tmax + t) * B + r] = vr;
-                L[i] = (r == 0) ? beta : 0.0;
-            }
-        }
-        if (lane == 0) rtau[(long)j * Tmax + t] = tau;
-        lane_sync();
-        double sdot = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) sdot += vs[rb + i] * L[i];
-        const double wc = tau * col_sum<B>(sdot);
-        if (c >= 1) {
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) L[i] -= wc * vs[rb + i];
-        }
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int r = rb + i;
-            if (c < ncl && r < len) stb<COH>(&band[(long)(c0 + c) * ld + (r0 + r - c0 - c)], L[i]);
-        }
-    }
-    const double vc = vs[c];
-    // ---- diagonal block: p = tau D v, k = tau v^T p / 2, w = p - k v, D -= v w^T + w v^T
-    {
-        double D[RPL];
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int r = rb + i;
-            const bool ok = (r < len && c < len);
-            const long off = (r >= c) ? (long)(r0 + c) * ld + (r - c) : (long)(r0 + r) * ld + (c - r);
-            const double x = ldb<COH>(&band[ok ? off : safe]);
-            D[i] = ok ? x : 0.0;
-        }
-        double pd = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) pd += D[i] * vs[rb + i];  // column c of D (= row c) dotted with v
-        const double pc = tau * col_sum<B>(pd);
-        const double kk = 0.5 * tau * wave_sum((h == 0 && c < len) ? vc * pc : 0.0);
-        const double wc = pc - kk * vc;
-        if (h == 0) ws[c] = (c < len) ? wc : 0.0;
-        lane_sync();
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int r = rb + i;
-            D[i] -= vs[r] * wc + ws[r] * vc;
-            if (r < len && c < len && r >= c) stb<COH>(&band[(long)(r0 + c) * ld + (r - c)], D[i]);
-        }
-    }
-    // ---- block below: y = B v (row sums), B -= tau y v^T
-    {
-        double Bm[RPL];
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int r = rb + i;
-            const bool ok = (r < nbl && c < len);
-            const double x = ldb<COH>(&band[ok ? (long)(r0 + c) * ld + (n0 + r - r0 - c) : safe]);
-            Bm[i] = ok ? x : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int r = rb + i;
-            const double yr = row_sum<B>(Bm[i] * vc);
-            Bm[i] -= tau * yr * vc;
-            if (r < nbl && c < len) stb<COH>(&band[(long)(r0 + c) * ld + (n0 + r - r0 - c)], Bm[i]);
-        }
-    }
-}
-
-// The same step with all three blocks loaded at the start, so that a step costs
-// one memory round trip (used where a wave has the register budget to itself).
+// ---------------------------------------------------------------------------
+// One bulge-chasing step (sweep j, step t), executed by one wave.  The three
+// b x b blocks of the step (the left block whose first column is annihilated,
+// the symmetric diagonal block, the block below that receives the new bulge)
+// are held in registers and all loaded at the start, so a step costs one
+// memory round trip: lane (c, h) = (lane % b, lane / b) owns column c, rows
+// h*RPL .. h*RPL + RPL - 1 of the left and diagonal blocks, and row c, columns
+// h*RPL .. h*RPL + RPL - 1 of the block below, so that every product with the
+// reflector sums within a lane and then over the LPC lanes sharing c.
+// vs and ws are two b-element LDS vectors private to the wave.
+// ---------------------------------------------------------------------------
 template <int B>
 CTMRG_DEVINL void bulge_step_pre(double *band, int N, int j, int t, double *refl, double *rtau, int Tmax, double *vs,
                                  double *ws)
@@ -410,11 +275,11 @@ CTMRG_DEVINL void bulge_step_pre(double *band, int N, int j, int t, double *refl
         const int r = rb + i;
         const bool okl = (c < ncl && r < len);
         const bool okd = (r < len && c < len);
-        const bool okb = (r < nbl && c < len);
+        const bool okb = (c < nbl && r < len);
         const long offd = (r >= c) ? (long)(r0 + c) * ld + (r - c) : (long)(r0 + r) * ld + (c - r);
         const double xl = band[okl ? (long)(c0 + c) * ld + (r0 + r - c0 - c) : safe];
         const double xd = band[okd ? offd : safe];
-        const double xb = band[okb ? (long)(r0 + c) * ld + (n0 + r - r0 - c) : safe];
+        const double xb = band[okb ? (long)(r0 + r) * ld + (n0 + c - r0 - r) : safe];
         L[i] = okl ? xl : 0.0;
         D[i] = okd ? xd : 0.0;
         Bm[i] = okb ? xb : 0.0;
@@ -469,84 +334,22 @@ CTMRG_DEVINL void bulge_step_pre(double *band, int N, int j, int t, double *refl
     lane_sync();
 #pragma unroll
     for (int i = 0; i < RPL; ++i) D[i] -= vs[rb + i] * wc + ws[rb + i] * vc;
-    // block below: y = B v (row sums), B -= tau y v^T
+    // block below, held transposed (lane (c, h) has row c, columns rb..rb+RPL-1):
+    // y = B v, B -= tau y v^T
+    {
+        double yp = 0.0;
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-        const double yr = row_sum<B>(Bm[i] * vc);
-        Bm[i] -= tau * yr * vc;
+        for (int i = 0; i < RPL; ++i) yp += Bm[i] * vs[rb + i];
+        const double ty = tau * col_sum<B>(yp);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) Bm[i] -= ty * vs[rb + i];
     }
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
         const int r = rb + i;
         if (c < ncl && r < len) band[(long)(c0 + c) * ld + (r0 + r - c0 - c)] = L[i];
         if (r < len && c < len && r >= c) band[(long)(r0 + c) * ld + (r - c)] = D[i];
-        if (r < nbl && c < len) band[(long)(r0 + c) * ld + (n0 + r - r0 - c)] = Bm[i];
-    }
-}
-
-// Pipelined form: one wave per sweep, BW consecutive sweeps per workgroup.  A
-// sweep may run step t once its predecessor has completed step t+2.  Inside a
-// workgroup a sweep waits on an LDS progress word; the first sweep of a group
-// waits across workgroups on the progress word of the last sweep of the
-// previous group (words PSTRIDE apart, one cache line each).  With COH all band
-// traffic is device-coherent and a step's stores complete before its progress
-// word advances; without it, the cross-workgroup handoff uses an agent-scope
-// release by the publisher and an acquire by the waiter.
-constexpr int BW = 8;
-constexpr int PSTRIDE = 32;
-
-template <int B, bool COH>
-__global__ void __launch_bounds__(64 * BW)
-bulge_pipe_kernel(double *band, int N, double *refl, double *rtau, int Tmax, unsigned *gprog, unsigned *err)
-{
-    __shared__ int lprog[BW];
-    __shared__ int labort;
-    __shared__ double vsh[BW][B], wsh[BW][B];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nsw = N - 2;
-    const int ngroups = (nsw + BW - 1) / BW;
-    if (threadIdx.x == 0) labort = 0;
-    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-        __syncthreads();
-        if (lane == 0) __hip_atomic_store(&lprog[wave], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __syncthreads();
-        if (labort) return;
-        const int j = grp * BW + wave;
-        if (j >= nsw) continue;
-        const int ns = bulge_nsteps(N, B, j);
-        const int nsprev = (j > 0) ? bulge_nsteps(N, B, j - 1) : 0;
-        for (int t = 0; t < ns; ++t) {
-            if (j > 0) {
-                const int need = min(t + 3, nsprev);
-                unsigned spins = 0;
-                int ok = 1;
-                if (wave == 0) {
-                    while ((int)ldu_coh(&gprog[(long)(grp - 1) * PSTRIDE]) < need) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (++spins > CTMRG_SPIN_LIMIT) { ok = 0; break; }
-                    }
-                    if (!COH) fence_acquire_agent();
-                } else {
-                    while (__hip_atomic_load(&lprog[wave - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (++spins > CTMRG_SPIN_LIMIT) { ok = 0; break; }
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                }
-                if (!ok) {
-                    if (lane == 0) { raise_error(err, KERR_PIPELINE_TIMEOUT); labort = 1; }
-                    break;
-                }
-            }
-            bulge_step<B, COH>(band, N, j, t, refl, rtau, Tmax, vsh[wave], wsh[wave]);
-            if (COH) wait_mem();
-            if (wave == BW - 1) {
-                if (!COH) fence_release_agent();
-                if (lane == 0) stu_coh(&gprog[(long)grp * PSTRIDE], (unsigned)(t + 1));
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (lane == 0) __hip_atomic_store(&lprog[wave], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
+        if (c < nbl && r < len) band[(long)(r0 + r) * ld + (n0 + c - r0 - r)] = Bm[i];
     }
 }
 
@@ -1127,7 +930,6 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += align_up(sizeof(double) * (size_t)Nmax * 2 * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax);
-    s += align_up(sizeof(unsigned) * (size_t)Nmax * PSTRIDE);
     s += align_up(sizeof(double) * (size_t)nJ * Tmax * b * b);
     s += 4 * align_up(sizeof(double) * (size_t)Nmax);
     s += 2 * align_up(sizeof(double) * (size_t)Nmax * kmax);
@@ -1168,7 +970,6 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.band, sizeof(double) * (size_t)Nmax * 2 * b},
         {(void **)&w.refl, sizeof(double) * (size_t)Nmax * w.Tmax * b},
         {(void **)&w.rtau, sizeof(double) * (size_t)Nmax * w.Tmax},
-        {(void **)&w.progress, sizeof(unsigned) * (size_t)Nmax * PSTRIDE},
         {(void **)&w.T2, sizeof(double) * (size_t)w.nJmax * w.Tmax * b * b},
         {(void **)&w.d, sizeof(double) * (size_t)Nmax},
         {(void **)&w.e, sizeof(double) * (size_t)Nmax},
@@ -1199,7 +1000,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
 void eig_free(EigWork &w)
 {
     void *ptrs[] = {w.Vx, w.Tp, w.tau1, w.VW, w.WV, w.Y, w.X, w.sm, w.part, w.splitk, w.band, w.refl, w.rtau,
-                    w.progress, w.T2, w.d, w.e, w.e2, w.evals, w.ZT, w.Ztmp, w.G, w.lu, w.ipiv, w.clist,
+                    w.T2, w.d, w.e, w.e2, w.evals, w.ZT, w.Ztmp, w.G, w.lu, w.ipiv, w.clist,
                     w.cstart, w.bar, w.err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1282,8 +1083,8 @@ hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s)
     hipLaunchKernelGGL(extract_band_kernel, dim3(std::min(4096, ceil_div((long)N * 2 * b, 256))), dim3(256), 0, s, A,
                        lda, N, b, w.band);
     if (N > 2) {
-        // one launch per wavefront tau = 3 j + t of independent steps
         const int Tmax = w.Tmax;
+        // one launch per wavefront tau = 3 j + t of independent steps
         const int taumax = 3 * (N - 3) + bulge_nsteps(N, b, N - 3);
         for (int tau = 0; tau < taumax; ++tau) {
             const int jhi = std::min(tau / 3, N - 3);
