@@ -6,8 +6,9 @@
 //            b-column panel below the band (one cooperative kernel per panel,
 //            one grid barrier per column) and a two-sided compact-WY update of
 //            the trailing matrix with GEMMs on the matrix cores;
-//   stage 2  band -> tridiagonal: pipelined bulge chasing, one workgroup per
-//            sweep, a sweep trailing its predecessor by three steps;
+//   stage 2  band -> tridiagonal: bulge chasing, one wave per step, one
+//            launch per wavefront of independent steps (a sweep trails its
+//            predecessor by three steps);
 //   values   all N eigenvalues by Sturm-count bisection;
 //   vectors  inverse iteration on the tridiagonal for the kept eigenvalues,
 //            re-orthogonalization inside tight clusters, then a Newton-Schulz
