@@ -1,16 +1,24 @@
 #!/usr/bin/env python3
-"""Throughput of the CTMRG step (Sec. III, Algorithm 3) for the q=20 dodecahedron model on one MI355X.
+"""Throughput of the CTMRG step (Sec. 3, Algorithm 3) for the q=20 dodecahedron model on one MI355X.
 
 A step is one full pass of the method on the GPU: extension products and W-mix
 (the extended corner C', (q m) x (q m)), the FP64 eigensolver (all eigenvalues,
 the m leading eigenvectors), the multiplet-preserving cut, the half-row
-products, W-mix and projection, and the normalizations.  The state after the
-warmup has reached the full dimension m (the dimension saturates after four
-steps at m = 512 since 20^3 < 10240 <= 20^4), so every timed step does the
+products, W-mix and projection, and the normalizations.  Every step works on
+the full padded size N = q m, so the timed steps after the warmup all do the
 full-size work.  Inputs are the dodecahedron spin vectors and K = 1/T; the
-state is whatever the iteration produces (synthetic, deterministic).
+state is whatever the iteration produces from the fixed boundary (synthetic,
+deterministic).
 
-Prints one JSON line (see the repository's design notes for the fields).
+By default two paths are timed one after the other from the same initial
+state: the mixed path (FP32 contractions on the matrix cores, FP64 eigensolver
+and state), whose steps/s is the headline `value`, and the FP64 path
+(`fp64`, `mixed_over_fp64`); `mixed_vs_fp64_after_run` gives how far their
+observables are apart after the same steps.  `roofline` is the dominant kernel
+(the wavefront bulge-chasing kernel, whose time per launch is its stage's
+HIP-event time over its launches), `contraction_roofline` the largest
+contraction kernel, and `cpu_baseline` the oracle's step time on the host.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -24,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0
 
 
@@ -89,6 +98,35 @@ def cpu_baseline(q_vectors, K, m_sample, m_target, warm=3):
     }
 
 
+def run_path(V, K, m, band, precision, gap_tol, warmup, steps):
+    """Warm up, then time `steps` CTMRG steps of one context; per-stage HIP-event times."""
+    import torch
+    from paper_2004_08669_amd import ctmrg
+    g = ctmrg.CTMRG(V, K, m, band=band, precision=precision, gap_tol=gap_tol)
+    for i in range(warmup):
+        g.step(1)
+        print(f"# {precision} warmup step {i + 1}/{warmup}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    g.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        g.step(1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"# {precision}: {steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
+    stages, nsteps = g.stage_times()
+    obs = g.observables()
+    g.close()
+    dt = t1 - t0
+    return {
+        "steps_per_s": steps / dt,
+        "ms_per_step": 1000.0 * dt / steps,
+        "stage_ms": {k: v / max(1, nsteps) for k, v in stages.items()},
+        "obs": obs,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +135,10 @@ def main():
     ap.add_argument("--m", type=int, default=512)
     ap.add_argument("--T", type=float, default=0.4398)
     ap.add_argument("--band", type=int, default=32)
+    ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both",
+                    help="both: time the mixed path (the headline value) and the FP64 path")
+    ap.add_argument("--gap-tol", type=float, default=1e-6,
+                    help="multiplet gap of the cut, the same on both paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=64)
     args = ap.parse_args()
@@ -108,30 +150,19 @@ def main():
 
     import torch
     import ctmrg_inputs as I
-    from paper_2004_08669_amd import ctmrg
 
     torch.cuda.set_device(0)
     V = I.dodecahedron()
     q, m, K = len(V), args.m, 1.0 / args.T
     print(f"# bench: q={q} m={m} T={args.T} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
-    g = ctmrg.CTMRG(V, K, m, band=args.band)
-    for i in range(args.warmup):
-        g.step(1)
-        print(f"# warmup step {i + 1}/{args.warmup}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    g.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        g.step(1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages, nsteps = g.stage_times()
-    obs = g.observables()
-    g.close()
-    dt = t1 - t0
-    ms_step = 1000.0 * dt / args.steps
-    stage_ms = {k: v / max(1, nsteps) for k, v in stages.items()}
+    runs = {}
+    order = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
+    for prec in order:
+        runs[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps)
+    head_prec = order[0]
+    head = runs[head_prec]
+    stage_ms = head["stage_ms"]
+    obs = head["obs"]
 
     flops = stage_flops(q, m)
     # Dominant kernel of the step: the wavefront bulge-chasing kernel (band -> tridiagonal).
@@ -154,42 +185,62 @@ def main():
         "launches_per_step": launches,
         "avg_launch_us": avg_launch_s * 1e6,
     }
-    # The largest contraction kernel, against the FP64 matrix-core peak.
+    # The largest contraction kernel, against the matrix-core peak of its precision.
     kernel_stages = ["extension", "wmix_C", "halfrow", "wmix_Z", "projection"]
     dom = max(kernel_stages, key=lambda k: stage_ms[k])
     c_ach = flops[dom] / (stage_ms[dom] * 1e-3) / 1e12
+    c_peak = PEAK_FP32_TFLOPS if head_prec == "fp32" else PEAK_FP64_TFLOPS
     contraction_roofline = {
         "kernel": dom,
         "bound": "mfma",
         "achieved": c_ach,
-        "peak": PEAK_FP64_TFLOPS,
+        "peak": c_peak,
         "unit": "TFLOP/s",
-        "frac": c_ach / PEAK_FP64_TFLOPS,
+        "frac": c_ach / c_peak,
         "algorithmic_flops_per_launch": flops[dom],
         "avg_launch_ms": stage_ms[dom],
     }
+    desc = {"fp32": "mixed (FP32 contractions, FP64 eigensolver and state)", "fp64": "FP64"}
     out = {
         "metric": "CTMRG steps/s at q=20 m=512 (mixed vs FP64, same error); % MFMA peak",
-        "value": args.steps / dt,
+        "value": head["steps_per_s"],
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if head_prec == "fp32" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"CTMRG step, q=20 dodecahedron, m={m} (C' {q * m}x{q * m}), T={args.T}, fixed boundary, FP64",
-            "q": q, "m": m, "T": args.T, "precision": "fp64", "band": args.band,
+            "workload": (f"CTMRG step, q=20 dodecahedron, m={m} (C' {q * m}x{q * m}), T={args.T}, fixed boundary, "
+                         f"{desc[head_prec]}"),
+            "q": q, "m": m, "T": args.T, "precision": head_prec, "band": args.band, "gap_tol": args.gap_tol,
         },
         "roofline": roofline,
         "contraction_roofline": contraction_roofline,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "state": {"m_eff": obs["m_eff"], "S_E": obs["S_E"], "delta": obs["delta"]},
     }
+    if "fp64" in runs and head_prec != "fp64":
+        r64 = runs["fp64"]
+        o64 = r64["obs"]
+        out["fp64"] = {
+            "steps_per_s": r64["steps_per_s"],
+            "ms_per_step": r64["ms_per_step"],
+            "stages_ms": {k: round(v, 4) for k, v in r64["stage_ms"].items()},
+        }
+        out["mixed_over_fp64"] = head["steps_per_s"] / r64["steps_per_s"]
+        # both paths ran the same steps from the same initial state
+        out["mixed_vs_fp64_after_run"] = {
+            "f_rel": abs(obs["f"] - o64["f"]) / abs(o64["f"]),
+            "E_abs": abs(obs["E"] - o64["E"]),
+            "M_abs": abs(obs["M"] - o64["M"]),
+            "S_E_abs": abs(obs["S_E"] - o64["S_E"]),
+            "m_eff": [obs["m_eff"], o64["m_eff"]],
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V, K, args.cpu_sample_m, m)
     print(json.dumps(out), flush=True)

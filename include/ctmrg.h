@@ -57,6 +57,15 @@ typedef enum {
     CTMRG_E_UNSUPPORTED = 7    /* option not available in this build */
 } ctmrg_status;
 
+/* Precision of the contractions (steps 1, 2 and 5 above).
+ *   CTMRG_FP64: FP64 operands on the FP64 matrix cores.
+ *   CTMRG_FP32: the mixed path.  P, Omega, U and W are rounded to FP32 operands
+ *     (W scaled by e^{-4K} first, so no weight overflows), products run on the
+ *     FP32 matrix cores with FP32 accumulation, and C' and P~ are produced in
+ *     FP64 with the factor restored.  The state, the eigensolver, the cut, all
+ *     normalizations, the log bookkeeping and the observables stay FP64.  The
+ *     contraction error is ~1e-7 relative to max|C'|, which also splits
+ *     multiplets of C' by that much: use gap_tol >= 1e-6 on this path. */
 typedef enum { CTMRG_FP64 = 0, CTMRG_FP32 = 1 } ctmrg_precision;
 typedef enum { CTMRG_BC_FIXED = 0, CTMRG_BC_FREE = 1 } ctmrg_bc;
 
@@ -65,7 +74,7 @@ typedef struct {
     int bc;               /* ctmrg_bc: fixed (all boundary spins = boundary_spin) or free      */
     int boundary_spin;    /* vertex index of the fixed boundary spin (the paper's s = 1)       */
     int band;             /* eigensolver half-bandwidth: 16 or 32 (default)                    */
-    double gap_tol;       /* multiplet gap, relative to |lambda_1| (default 1e-10)             */
+    double gap_tol;       /* multiplet gap, relative to |lambda_1| (default 1e-10; >= 1e-6 for FP32) */
     double rank_tol;      /* eigenvalues with |l| <= rank_tol |l_1| are never kept (1e-13)     */
     void *hip_stream;     /* hipStream_t to run on; NULL = a stream owned by the context       */
 } ctmrg_options;

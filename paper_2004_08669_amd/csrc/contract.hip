@@ -11,38 +11,50 @@ namespace ctm {
 
 // ---------------------------------------------------------------- accessors
 // W-mix operand: B(k = (s,sg), n = (a,b)) = X[(s m + a) N + sg m + b]
-struct B_Mix {
-    const double *X; int q, m; long Nc;
+template <class T>
+struct B_Mix_ {
+    using value_type = T;
+    const T *X; int q, m; long Nc;
     static constexpr bool kContigK = false;
-    __device__ double operator()(int k, int n) const
+    __device__ T operator()(int k, int n) const
     {
         const int s = k / q, sg = k - s * q;
         const int a = n / m, b = n - a * m;
         return X[(long)(s * m + a) * Nc + sg * m + b];
     }
 };
-// W-mix store: out(i = (s',sg'), n = (a,b)) -> C[(s' m + a) N + sg' m + b]
-struct EpiMix {
-    double *C; int q, m; long Nc;
+using B_Mix = B_Mix_<double>;
+using B_Mixf = B_Mix_<float>;
+// W-mix store: out(i = (s',sg'), n = (a,b)) -> C[(s' m + a) N + sg' m + b] = acc (times alpha if SCALED;
+// the factor is a template switch because a multiply in this epilogue costs the FP64 kernel occupancy)
+template <class TO, bool SCALED>
+struct EpiMix_ {
+    TO *C; int q, m; long Nc; double alpha;
     __device__ void operator()(int i, int n, double v, int) const
     {
         const int sp = i / q, sgp = i - sp * q;
         const int a = n / m, b = n - a * m;
-        C[(long)(sp * m + a) * Nc + sgp * m + b] = v;
+        if constexpr (SCALED) C[(long)(sp * m + a) * Nc + sgp * m + b] = (TO)(alpha * v);
+        else C[(long)(sp * m + a) * Nc + sgp * m + b] = (TO)v;
     }
 };
 // Half-row operand: B(k = gamma, n = (sg, j)) = U[(sg m + gamma) m + j]  (U is N x m)
-struct B_Ublk {
-    const double *U; int m;
+template <class T>
+struct B_Ublk_ {
+    using value_type = T;
+    const T *U; int m;
     static constexpr bool kContigK = false;
-    __device__ double operator()(int k, int n) const
+    __device__ T operator()(int k, int n) const
     {
         const int sg = n / m, j = n - sg * m;
         return U[(long)(sg * m + k) * m + j];
     }
 };
+using B_Ublk = B_Ublk_<double>;
+using B_Ublkf = B_Ublk_<float>;
 // Gram of the extension blocks: A(k1 = (s,sg), n = (i,j)) = w_i w_j X[(s m + i) N + sg m + j]
 struct A_MixW {
+    using value_type = double;
     const double *X; const double *om; int q, m; long Nc;
     static constexpr bool kContigK = true;
     __device__ double operator()(int k1, int n) const
@@ -54,6 +66,7 @@ struct A_MixW {
 };
 // B(n = (i,j), k2 = (s',sg')) = X[(s' m + i) N + sg' m + j]
 struct B_MixT {
+    using value_type = double;
     const double *X; int q, m; long Nc;
     static constexpr bool kContigK = true;
     __device__ double operator()(int n, int k2) const
@@ -227,6 +240,25 @@ env_scalars_kernel(const double *A, const double *omega, const double *W, const 
     }
 }
 
+// FP32 operands of the mixed-precision contractions: A32 = A, OA32 = diag(omega) A (rounded once).
+__global__ void rows_to_f32_kernel(const double *A, const double *omega, float *A32, float *OA32, int m, long N)
+{
+    const long total = (long)m * N;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int g = (int)(idx / N);
+        const double a = A[idx];
+        A32[idx] = (float)a;
+        OA32[idx] = (float)(omega[g] * a);
+    }
+}
+
+// dst = scale * src, rounded to FP32.
+__global__ void to_f32_kernel(const double *src, float *dst, long n, double scale)
+{
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x)
+        dst[idx] = (float)(scale * src[idx]);
+}
+
 // ---------------------------------------------------------------- launchers
 
 static int grid_for(long total) { return (int)std::max<long>(1, std::min<long>(4096, (total + 255) / 256)); }
@@ -250,7 +282,7 @@ hipError_t extension_products(const double *A, const double *omega, double *OA, 
 {
     const long N = (long)q * m;
     hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(m * N)), dim3(256), 0, s, A, omega, OA, m, N);
-    return gemm_f64(GEMM_LARGE, A_T{A, N}, B_RM{OA, N}, EpiStore{X, N, 1.0}, (int)N, (int)N, m, s);
+    return gemm_mfma(GEMM_LARGE, A_T{A, N}, B_RM{OA, N}, EpiStore{X, N, 1.0}, (int)N, (int)N, m, s);
 }
 
 hipError_t weight_mix(const double *W, const double *Xin, double *Cout, int q, int m, hipStream_t s)
@@ -258,19 +290,80 @@ hipError_t weight_mix(const double *W, const double *Xin, double *Cout, int q, i
     const long N = (long)q * m;
     const int q2 = q * q;
     // W is symmetric: W^T(i,k) = W[k q2 + i]
-    return gemm_f64(GEMM_MIX, A_T{W, q2}, B_Mix{Xin, q, m, N}, EpiMix{Cout, q, m, N}, q2, m * m, q2, s);
+    return gemm_mfma(GEMM_MIX, A_T{W, q2}, B_Mix{Xin, q, m, N}, EpiMix_<double, false>{Cout, q, m, N, 1.0}, q2,
+                     m * m, q2, s);
 }
 
 hipError_t halfrow_products(const double *A, const double *U, double *Y, int q, int m, hipStream_t s)
 {
     const long N = (long)q * m;
-    return gemm_f64(GEMM_LARGE, A_T{A, N}, B_Ublk{U, m}, EpiStore{Y, N, 1.0}, (int)N, (int)N, m, s);
+    return gemm_mfma(GEMM_LARGE, A_T{A, N}, B_Ublk{U, m}, EpiStore{Y, N, 1.0}, (int)N, (int)N, m, s);
 }
 
 hipError_t projection(const double *U, const double *Z, double *Pt, int q, int m, hipStream_t s)
 {
     const long N = (long)q * m;
-    return gemm_f64(GEMM_LARGE, A_T{U, m}, B_RM{Z, N}, EpiStore{Pt, N, 1.0}, m, (int)N, (int)N, s);
+    return gemm_mfma(GEMM_LARGE, A_T{U, m}, B_RM{Z, N}, EpiStore{Pt, N, 1.0}, m, (int)N, (int)N, s);
+}
+
+// ---- mixed precision: FP32 operands on the FP32 matrix cores, FP32 accumulation.
+// W32 holds W / wscale (wscale = e^{4K} >= max W, so that no weight overflows FP32);
+// the factor is restored in FP64 in the epilogues that produce C' and P~.
+
+hipError_t weight_to_f32(const double *W, float *W32, int q, double wscale, hipStream_t s)
+{
+    const long n = (long)q * q * q * q;
+    hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, W, W32, n, 1.0 / wscale);
+    return hipGetLastError();
+}
+
+hipError_t state_to_f32(const double *A, const double *omega, float *A32, float *OA32, int q, int m, hipStream_t s)
+{
+    const long N = (long)q * m;
+    hipLaunchKernelGGL(rows_to_f32_kernel, dim3(grid_for((long)m * N)), dim3(256), 0, s, A, omega, A32, OA32, m, N);
+    return hipGetLastError();
+}
+
+hipError_t vectors_to_f32(const double *U, float *U32, int q, int m, hipStream_t s)
+{
+    const long n = (long)q * m * m;
+    hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, U, U32, n, 1.0);
+    return hipGetLastError();
+}
+
+hipError_t extension_products_f32(const float *A32, const float *OA32, float *X32, int q, int m, hipStream_t s)
+{
+    const long N = (long)q * m;
+    return gemm_mfma(GEMM_LARGE, A_Tf{A32, N}, B_RMf{OA32, N}, EpiStoreF{X32, N, 1.0}, (int)N, (int)N, m, s);
+}
+
+hipError_t weight_mix_f32_to_f64(const float *W32, const float *X32, double *Cout, int q, int m, double wscale,
+                                 hipStream_t s)
+{
+    const long N = (long)q * m;
+    const int q2 = q * q;
+    return gemm_mfma(GEMM_MIX, A_Tf{W32, q2}, B_Mixf{X32, q, m, N}, EpiMix_<double, true>{Cout, q, m, N, wscale}, q2,
+                     m * m, q2, s);
+}
+
+hipError_t halfrow_products_f32(const float *A32, const float *U32, float *Y32, int q, int m, hipStream_t s)
+{
+    const long N = (long)q * m;
+    return gemm_mfma(GEMM_LARGE, A_Tf{A32, N}, B_Ublkf{U32, m}, EpiStoreF{Y32, N, 1.0}, (int)N, (int)N, m, s);
+}
+
+hipError_t weight_mix_f32(const float *W32, const float *Y32, float *Z32, int q, int m, hipStream_t s)
+{
+    const long N = (long)q * m;
+    const int q2 = q * q;
+    return gemm_mfma(GEMM_MIX, A_Tf{W32, q2}, B_Mixf{Y32, q, m, N}, EpiMix_<float, false>{Z32, q, m, N, 1.0}, q2, m * m,
+                     q2, s);
+}
+
+hipError_t projection_f32(const float *U32, const float *Z32, double *Pt, int q, int m, double wscale, hipStream_t s)
+{
+    const long N = (long)q * m;
+    return gemm_mfma(GEMM_LARGE, A_Tf{U32, m}, B_RMf{Z32, N}, EpiStore{Pt, N, wscale}, m, (int)N, (int)N, s);
 }
 
 hipError_t normalize_and_book(const double *Pt, double *A, int q, int m, double *partials, Book *book,
@@ -297,7 +390,7 @@ hipError_t observables(const double *A, const double *omega, const double *U, co
     const long tiles = (long)ceil_div(q2, 64) * ceil_div(q2, 64);
     int sp = 1;
     while (tiles * sp < 512 && K / (sp * 2) >= 256 && (size_t)(sp * 2) * q2 * q2 <= work_elems) sp *= 2;
-    e = gemm_f64_splitk(A_MixW{X, omega, q, m, N}, B_MixT{X, q, m, N}, EpiStore{H, q2, 1.0}, q2, q2, (int)K, sp, work,
+    e = gemm_mfma_splitk(A_MixW{X, omega, q, m, N}, B_MixT{X, q, m, N}, EpiStore{H, q2, 1.0}, q2, q2, (int)K, sp, work,
                         s);
     if (e != hipSuccess) return e;
     double *prob = out + 8;

@@ -29,6 +29,9 @@ struct ctmrg_ctx {
     double *dX = nullptr, *dC = nullptr, *dU = nullptr;
     double *dPart = nullptr, *dObs = nullptr, *dH = nullptr, *dWork = nullptr;
     size_t work_elems = 0;
+    // mixed precision (FP32 contractions): W / wscale, A, diag(omega) A and U in FP32
+    float *dW32 = nullptr, *dA32 = nullptr, *dOA32 = nullptr, *dU32 = nullptr;
+    double wscale = 1.0;
     Book *dBook = nullptr;
     PostOut *dPost = nullptr;
     PostOut *hPost = nullptr;
@@ -98,6 +101,9 @@ void free_all(ctmrg_ctx *c)
                       c->dX, c->dC, c->dU, c->dPart, c->dObs, c->dH, c->dWork};
     for (double *p : bufs)
         if (p) (void)hipFree(p);
+    float *fbufs[] = {c->dW32, c->dA32, c->dOA32, c->dU32};
+    for (float *p : fbufs)
+        if (p) (void)hipFree(p);
     if (c->dBook) (void)hipFree(c->dBook);
     if (c->dPost) (void)hipFree(c->dPost);
     if (c->hPost) (void)hipHostFree(c->hPost);
@@ -107,7 +113,7 @@ void free_all(ctmrg_ctx *c)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
 }
 
-size_t context_bytes(int q, int m, int band)
+size_t context_bytes(int q, int m, int band, int precision)
 {
     const size_t N = (size_t)q * m;
     const size_t q4 = (size_t)q * q * q * q;
@@ -120,6 +126,7 @@ size_t context_bytes(int q, int m, int band)
     s += sizeof(double) * (4096 + 64 + q + q4 + 64 * q4);
     s += sizeof(Book) + sizeof(PostOut);
     s += eig_bytes((int)N, m, band);
+    if (precision == CTMRG_FP32) s += sizeof(float) * (q4 + 3 * (size_t)m * N);
     return s;
 }
 
@@ -146,6 +153,36 @@ ctmrg_status check_kernel_errors(ctmrg_ctx *c)
     return CTMRG_OK;
 }
 
+// C' = W-mix(A^T Omega A) into dC, in the context's precision (marks MK_EXT between the two products).
+hipError_t extend_corner(ctmrg_ctx *c)
+{
+    const int q = c->q, m = c->m;
+    hipStream_t s = c->stream;
+    hipError_t e;
+    if (c->opt.precision == CTMRG_FP32) {
+        float *X32 = reinterpret_cast<float *>(c->dX);
+        e = state_to_f32(c->dA, c->dOmega, c->dA32, c->dOA32, q, m, s);
+        if (e == hipSuccess) e = extension_products_f32(c->dA32, c->dOA32, X32, q, m, s);
+        mark(c->eig, MK_EXT, s);
+        if (e == hipSuccess) e = weight_mix_f32_to_f64(c->dW32, X32, c->dC, q, m, c->wscale, s);
+    } else {
+        e = extension_products(c->dA, c->dOmega, c->dOA, c->dX, q, m, s);
+        mark(c->eig, MK_EXT, s);
+        if (e == hipSuccess) e = weight_mix(c->dW, c->dX, c->dC, q, m, s);
+    }
+    return e;
+}
+
+// W (FP64, and its scaled FP32 copy on the mixed path) for the context's K.
+hipError_t make_weight(ctmrg_ctx *c)
+{
+    hipError_t e = build_weight(c->dV, c->q, c->dim, c->K, c->dW, c->dWH, c->stream);
+    if (e != hipSuccess || c->opt.precision != CTMRG_FP32) return e;
+    // every plaquette sum of four dot products of unit vectors is at most 4
+    c->wscale = exp(4.0 * c->K);
+    return weight_to_f32(c->dW, c->dW32, c->q, c->wscale, c->stream);
+}
+
 ctmrg_status one_step(ctmrg_ctx *c)
 {
     const int q = c->q, m = c->m, N = c->N;
@@ -153,9 +190,7 @@ ctmrg_status one_step(ctmrg_ctx *c)
     c->eig.marks = c->profile ? c->ev : nullptr;
     mark(c->eig, MK_START, s);
     // extension: X = A^T Omega A, C' = W-mix(X)
-    HIPCHK(c, extension_products(c->dA, c->dOmega, c->dOA, c->dX, q, m, s));
-    mark(c->eig, MK_EXT, s);
-    HIPCHK(c, weight_mix(c->dW, c->dX, c->dC, q, m, s));
+    HIPCHK(c, extend_corner(c));
     mark(c->eig, MK_WMIX1, s);
     c->cext_valid = false;
     // eigenvalues, selection, normalization, entropy, convergence
@@ -172,11 +207,21 @@ ctmrg_status one_step(ctmrg_ctx *c)
     // eigenvectors of the kept states
     HIPCHK(c, eig_vectors(c->eig, nullptr, 0, N, po.m_eff, c->dSel, po.nclusters, c->dU, m, s));
     // half-row: Y = A^T U~, Z = W-mix(Y), P~ = U^T Z
-    HIPCHK(c, halfrow_products(c->dA, c->dU, c->dX, q, m, s));
-    mark(c->eig, MK_HALF, s);
-    HIPCHK(c, weight_mix(c->dW, c->dX, c->dC, q, m, s));
-    mark(c->eig, MK_WMIX2, s);
-    HIPCHK(c, projection(c->dU, c->dC, c->dPt, q, m, s));
+    if (c->opt.precision == CTMRG_FP32) {
+        float *Y32 = reinterpret_cast<float *>(c->dX), *Z32 = reinterpret_cast<float *>(c->dC);
+        HIPCHK(c, vectors_to_f32(c->dU, c->dU32, q, m, s));
+        HIPCHK(c, halfrow_products_f32(c->dA32, c->dU32, Y32, q, m, s));
+        mark(c->eig, MK_HALF, s);
+        HIPCHK(c, weight_mix_f32(c->dW32, Y32, Z32, q, m, s));
+        mark(c->eig, MK_WMIX2, s);
+        HIPCHK(c, projection_f32(c->dU32, Z32, c->dPt, q, m, c->wscale, s));
+    } else {
+        HIPCHK(c, halfrow_products(c->dA, c->dU, c->dX, q, m, s));
+        mark(c->eig, MK_HALF, s);
+        HIPCHK(c, weight_mix(c->dW, c->dX, c->dC, q, m, s));
+        mark(c->eig, MK_WMIX2, s);
+        HIPCHK(c, projection(c->dU, c->dC, c->dPt, q, m, s));
+    }
     mark(c->eig, MK_PROJ, s);
     HIPCHK(c, normalize_and_book(c->dPt, c->dA, q, m, c->dPart, c->dBook, &c->dPost->n_C, &c->dPost->S_E, s));
     HIPCHK(c, hipMemcpyAsync(c->dOmega, c->dOmNew, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
@@ -232,7 +277,8 @@ ctmrg_status ctmrg_workspace_size(int q, int m, const ctmrg_options *opt, size_t
     ctmrg_default_options(&o);
     if (opt) o = *opt;
     if (!valid_band(o.band)) return CTMRG_E_INVALID_ARG;
-    *bytes = context_bytes(q, m, o.band);
+    if (o.precision != CTMRG_FP64 && o.precision != CTMRG_FP32) return CTMRG_E_INVALID_ARG;
+    *bytes = context_bytes(q, m, o.band, o.precision);
     return CTMRG_OK;
 }
 
@@ -253,7 +299,7 @@ ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, 
     if (opt) o = *opt;
     if (!valid_band(o.band) || o.boundary_spin < 0 || o.boundary_spin >= q || (o.bc != 0 && o.bc != 1))
         return CTMRG_E_INVALID_ARG;
-    if (o.precision != CTMRG_FP64) return CTMRG_E_UNSUPPORTED;
+    if (o.precision != CTMRG_FP64 && o.precision != CTMRG_FP32) return CTMRG_E_INVALID_ARG;
     const long N = (long)q * m;
     if (N > 65536) return CTMRG_E_INVALID_ARG;
 
@@ -286,6 +332,14 @@ ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, 
         hipError_t e = hipMalloc((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
         if (e != hipSuccess) { *out = c; return hip_fail(c, e, "hipMalloc"); }
     }
+    if (o.precision == CTMRG_FP32) {
+        struct ReqF { float **p; size_t n; };
+        ReqF fr[] = {{&c->dW32, q4}, {&c->dA32, (size_t)m * N}, {&c->dOA32, (size_t)m * N}, {&c->dU32, (size_t)N * m}};
+        for (auto &r : fr) {
+            hipError_t e = hipMalloc((void **)r.p, sizeof(float) * std::max<size_t>(r.n, 1));
+            if (e != hipSuccess) { *out = c; return hip_fail(c, e, "hipMalloc"); }
+        }
+    }
     hipError_t e = hipMalloc((void **)&c->dBook, sizeof(Book));
     if (e == hipSuccess) e = hipMalloc((void **)&c->dPost, sizeof(PostOut));
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->hPost, sizeof(PostOut), hipHostMallocDefault);
@@ -293,7 +347,7 @@ ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, 
     if (e != hipSuccess) { *out = c; return hip_fail(c, e, "allocation"); }
     e = hipMemcpy(c->dV, c->V.data(), sizeof(double) * q * dim, hipMemcpyHostToDevice);
     if (e != hipSuccess) { *out = c; return hip_fail(c, e, "hipMemcpy"); }
-    e = build_weight(c->dV, q, dim, K, c->dW, c->dWH, c->stream);
+    e = make_weight(c);
     if (e != hipSuccess) { *out = c; return hip_fail(c, e, "build_weight"); }
     st = reset_state(c);
     *out = c;
@@ -305,7 +359,7 @@ ctmrg_status ctmrg_set_K(ctmrg_ctx *c, double K)
     if (!c) return CTMRG_E_INVALID_ARG;
     if (!(K > 0.0) || !std::isfinite(K)) return fail(c, CTMRG_E_INVALID_ARG, "K must be positive");
     c->K = K;
-    HIPCHK(c, build_weight(c->dV, c->q, c->dim, K, c->dW, c->dWH, c->stream));
+    HIPCHK(c, make_weight(c));
     return reset_state(c);
 }
 
@@ -433,8 +487,7 @@ ctmrg_status ctmrg_set_state(ctmrg_ctx *c, int d, const double *P, const double 
 ctmrg_status ctmrg_extend(ctmrg_ctx *c)
 {
     if (!c) return CTMRG_E_INVALID_ARG;
-    HIPCHK(c, extension_products(c->dA, c->dOmega, c->dOA, c->dX, c->q, c->m, c->stream));
-    HIPCHK(c, weight_mix(c->dW, c->dX, c->dC, c->q, c->m, c->stream));
+    HIPCHK(c, extend_corner(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cext_valid = true;
     return CTMRG_OK;

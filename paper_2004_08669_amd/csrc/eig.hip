@@ -1048,26 +1048,26 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
         {
             const long tiles = (long)ceil_div(n, 128) * ceil_div(b, 32);
             const int sp = splits_for(tiles, n, 256);
-            e = gemm_f64_splitk(A_RM{A22, lda}, B_RM{Vp, b}, EpiStore{w.Y, b, 1.0}, n, b, n, sp, w.splitk, s, GEMM_TALL);
+            e = gemm_mfma_splitk(A_RM{A22, lda}, B_RM{Vp, b}, EpiStore{w.Y, b, 1.0}, n, b, n, sp, w.splitk, s, GEMM_TALL);
             if (e != hipSuccess) return e;
         }
         // X = Y T
-        e = gemm_f64(GEMM_TALL, A_RM{w.Y, b}, B_RM{Tp, b}, EpiStore{w.X, b, 1.0}, n, b, b, s);
+        e = gemm_mfma(GEMM_TALL, A_RM{w.Y, b}, B_RM{Tp, b}, EpiStore{w.X, b, 1.0}, n, b, b, s);
         if (e != hipSuccess) return e;
         // M = V^T X
         {
             const int sp = splits_for(1, n, 128);
-            e = gemm_f64_splitk(A_T{Vp, b}, B_RM{w.X, b}, EpiStore{w.sm, b, 1.0}, b, b, n, sp, w.splitk, s);
+            e = gemm_mfma_splitk(A_T{Vp, b}, B_RM{w.X, b}, EpiStore{w.sm, b, 1.0}, b, b, n, sp, w.splitk, s);
             if (e != hipSuccess) return e;
         }
         // S = T^T M
-        e = gemm_f64(GEMM_SMALL, A_T{Tp, b}, B_RM{w.sm, b}, EpiStore{w.sm + b * b, b, 1.0}, b, b, b, s);
+        e = gemm_mfma(GEMM_SMALL, A_T{Tp, b}, B_RM{w.sm, b}, EpiStore{w.sm + b * b, b, 1.0}, b, b, b, s);
         if (e != hipSuccess) return e;
         // W = X - 1/2 V S, and the operands [V|W], [W|V]
-        e = gemm_f64(GEMM_TALL, A_RM{Vp, b}, B_RM{w.sm + b * b, b}, EpiWform{w.X, Vp, w.VW, w.WV, b}, n, b, b, s);
+        e = gemm_mfma(GEMM_TALL, A_RM{Vp, b}, B_RM{w.sm + b * b, b}, EpiWform{w.X, Vp, w.VW, w.WV, b}, n, b, b, s);
         if (e != hipSuccess) return e;
         // A22 -= [V|W] [W|V]^T
-        e = gemm_f64(GEMM_SMALL, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, n, 2 * b, s);
+        e = gemm_mfma(GEMM_SMALL, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, n, 2 * b, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1135,11 +1135,11 @@ hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const do
     for (int it = 0; it < 3; ++it) {
         const long tiles = (long)ceil_div(me, 64) * ceil_div(me, 64);
         const int sp = splits_for(tiles, N, 256);
-        e = gemm_f64_splitk(A_T{Z, ldz}, B_RM{Z, ldz}, EpiStore{w.G, me, 1.0}, me, me, N, sp, w.splitk, s);
+        e = gemm_mfma_splitk(A_T{Z, ldz}, B_RM{Z, ldz}, EpiStore{w.G, me, 1.0}, me, me, N, sp, w.splitk, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(ns_matrix_kernel, dim3(std::max(1, std::min(1024, ceil_div((long)me * me, 256)))), dim3(256), 0,
                            s, w.G, me);
-        e = gemm_f64(GEMM_LARGE, A_RM{Z, ldz}, B_RM{w.G, me}, EpiStore{Zo, ldz, 1.0}, N, me, me, s);
+        e = gemm_mfma(GEMM_LARGE, A_RM{Z, ldz}, B_RM{w.G, me}, EpiStore{Zo, ldz, 1.0}, N, me, me, s);
         if (e != hipSuccess) return e;
         std::swap(Z, Zo);
     }
@@ -1167,11 +1167,11 @@ hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const do
         double *Zs = Z + (long)r0 * ldz;
         const long tiles = ceil_div(me, 64);
         const int sp = splits_for(tiles, n, 128);
-        e = gemm_f64_splitk(A_T{Vp, b}, B_RM{Zs, ldz}, EpiStore{w.Y, me, 1.0}, b, me, n, sp, w.splitk, s);
+        e = gemm_mfma_splitk(A_T{Vp, b}, B_RM{Zs, ldz}, EpiStore{w.Y, me, 1.0}, b, me, n, sp, w.splitk, s);
         if (e != hipSuccess) return e;
-        e = gemm_f64(GEMM_SMALL, A_RM{Tp, b}, B_RM{w.Y, me}, EpiStore{w.X, me, 1.0}, b, me, b, s);
+        e = gemm_mfma(GEMM_SMALL, A_RM{Tp, b}, B_RM{w.Y, me}, EpiStore{w.X, me, 1.0}, b, me, b, s);
         if (e != hipSuccess) return e;
-        e = gemm_f64(GEMM_LARGE, A_RM{Vp, b}, B_RM{w.X, me}, EpiAxpby{Zs, ldz, -1.0, 1.0}, n, me, b, s);
+        e = gemm_mfma(GEMM_LARGE, A_RM{Vp, b}, B_RM{w.X, me}, EpiAxpby{Zs, ldz, -1.0, 1.0}, n, me, b, s);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(sign_fix_copy_kernel, dim3(ldu), dim3(256), 0, s, Z, ldz, N, me, U, ldu);

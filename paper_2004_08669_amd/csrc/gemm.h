@@ -12,11 +12,17 @@
 // MFMA blocks.  K is walked in BK slices staged through LDS.  blockIdx.z splits
 // K into chunks (split-K) when the output has too few tiles to fill the chip.
 //
-// MFMA operand layout for v_mfma_f64_16x16x4_f64 (and the f32 16x16x4 form):
+// MFMA operand layout of v_mfma_f64_16x16x4_f64 and v_mfma_f32_16x16x4_f32:
 //   A fragment: lane l holds A[l%16][l/16]   (row l%16, k l/16)
 //   B fragment: lane l holds B[l/16][l%16]   (k l/16, column l%16)
-//   D fragment: lane l, register r holds D[l/16 + 4 r][l%16]
+//   D fragment: lane l, register r holds D[row][l%16] with
+//               row = l/16 + 4 r    (f64)
+//               row = 4 (l/16) + r  (f32)
+// The element type of a GEMM is the value type of its accessors: double runs
+// on the FP64 matrix cores, float on the FP32 ones with FP32 accumulation.
 #pragma once
+
+#include <type_traits>
 
 #include "common.h"
 
@@ -28,29 +34,43 @@ static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 // kContigK: consecutive k are adjacent in memory (else consecutive m / n are).
 
 // A row-major M x K: A(i,k) = p[i*ld + k]
-struct A_RM {
-    const double *p; long ld;
+template <class T>
+struct A_RM_ {
+    using value_type = T;
+    const T *p; long ld;
     static constexpr bool kContigK = true;
-    __device__ double operator()(int i, int k) const { return p[(long)i * ld + k]; }
+    __device__ T operator()(int i, int k) const { return p[(long)i * ld + k]; }
 };
 // A stored K x M row-major, used transposed: A(i,k) = p[k*ld + i]
-struct A_T {
-    const double *p; long ld;
+template <class T>
+struct A_T_ {
+    using value_type = T;
+    const T *p; long ld;
     static constexpr bool kContigK = false;
-    __device__ double operator()(int i, int k) const { return p[(long)k * ld + i]; }
+    __device__ T operator()(int i, int k) const { return p[(long)k * ld + i]; }
 };
 // B row-major K x N: B(k,j) = p[k*ld + j]
-struct B_RM {
-    const double *p; long ld;
+template <class T>
+struct B_RM_ {
+    using value_type = T;
+    const T *p; long ld;
     static constexpr bool kContigK = false;
-    __device__ double operator()(int k, int j) const { return p[(long)k * ld + j]; }
+    __device__ T operator()(int k, int j) const { return p[(long)k * ld + j]; }
 };
 // B stored N x K row-major, used transposed: B(k,j) = p[j*ld + k]
-struct B_T {
-    const double *p; long ld;
+template <class T>
+struct B_T_ {
+    using value_type = T;
+    const T *p; long ld;
     static constexpr bool kContigK = true;
-    __device__ double operator()(int k, int j) const { return p[(long)j * ld + k]; }
+    __device__ T operator()(int k, int j) const { return p[(long)j * ld + k]; }
 };
+using A_RM = A_RM_<double>;
+using A_T = A_T_<double>;
+using B_RM = B_RM_<double>;
+using B_T = B_T_<double>;
+using A_Tf = A_T_<float>;
+using B_RMf = B_RM_<float>;
 
 // ---------------------------------------------------------------- epilogues
 struct EpiStore {  // C = alpha * acc
@@ -65,6 +85,10 @@ struct EpiAxpby {  // C = alpha * acc + beta * C
         *c = alpha * v + beta * (*c);
     }
 };
+struct EpiStoreF {  // C = alpha * acc, rounded to FP32
+    float *p; long ld; double alpha;
+    __device__ void operator()(int i, int j, double v, int) const { p[(long)i * ld + j] = (float)(alpha * v); }
+};
 struct EpiPartial {  // split-K partial sums, reduced by reduce_partials
     double *p; long M, N;
     __device__ void operator()(int i, int j, double v, int split) const
@@ -73,18 +97,36 @@ struct EpiPartial {  // split-K partial sums, reduced by reduce_partials
     }
 };
 
-// ---------------------------------------------------------------- FP64 kernel
+// ---------------------------------------------------------------- MFMA step per element type
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+    using acc_t = double4_t;
+    static __device__ acc_t zero() { return (acc_t){0.0, 0.0, 0.0, 0.0}; }
+    static __device__ acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+    using acc_t = float4_t;
+    static __device__ acc_t zero() { return (acc_t){0.f, 0.f, 0.f, 0.f}; }
+    static __device__ acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// ---------------------------------------------------------------- kernel
 template <int BM, int BN, int BK, int WM, int WN, class LA, class LB, class EPI>
 __global__ void __launch_bounds__(WM * WN * 64)
-gemm_f64_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
+gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
 {
+    using T = typename LA::value_type;
+    static_assert(std::is_same<T, typename LB::value_type>::value, "operand types");
+    using MF = Mfma<T>;
     constexpr int NT = WM * WN * 64;
     constexpr int TM = BM / WM / 16;
     constexpr int TN = BN / WN / 16;
     static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
     static_assert(BK % 4 == 0, "BK");
-    __shared__ double As[BK][BM + 1];
-    __shared__ double Bs[BK][BN + 1];
+    __shared__ T As[BK][BM + 1];
+    __shared__ T Bs[BK][BN + 1];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -93,11 +135,11 @@ gemm_f64_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
 
-    double4_t acc[TM][TN];
+    typename MF::acc_t acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::zero();
 
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll 4
@@ -106,7 +148,7 @@ gemm_f64_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
             if (LA::kContigK) { mm = idx / BK; kk = idx - mm * BK; }
             else { kk = idx / BM; mm = idx - kk * BM; }
             const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < M && gk < kend) ? la(gm, gk) : 0.0;
+            As[kk][mm] = (gm < M && gk < kend) ? la(gm, gk) : T(0);
         }
 #pragma unroll 4
         for (int idx = tid; idx < BN * BK; idx += NT) {
@@ -114,12 +156,12 @@ gemm_f64_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
             if (LB::kContigK) { nn = idx / BK; kk = idx - nn * BK; }
             else { kk = idx / BN; nn = idx - kk * BN; }
             const int gn = n0 + nn, gk = k0 + kk;
-            Bs[kk][nn] = (gn < N && gk < kend) ? lb(gk, gn) : 0.0;
+            Bs[kk][nn] = (gn < N && gk < kend) ? lb(gk, gn) : T(0);
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            double a[TM], b[TN];
+            T a[TM], b[TN];
 #pragma unroll
             for (int i = 0; i < TM; ++i) a[i] = As[kk + (lane >> 4)][(wm * TM + i) * 16 + (lane & 15)];
 #pragma unroll
@@ -127,8 +169,7 @@ gemm_f64_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(a[i], b[j], acc[i][j]);
         }
         __syncthreads();
     }
@@ -138,9 +179,9 @@ gemm_f64_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
         for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + (wm * TM + i) * 16 + (lane >> 4) + 4 * r;
+                const int row = m0 + (wm * TM + i) * 16 + MF::row(lane, r);
                 const int col = n0 + (wn * TN + j) * 16 + (lane & 15);
-                if (row < M && col < N) epi(row, col, acc[i][j][r], blockIdx.z);
+                if (row < M && col < N) epi(row, col, (double)acc[i][j][r], blockIdx.z);
             }
 }
 
@@ -167,24 +208,24 @@ enum GemmShape {
 };
 
 template <class LA, class LB, class EPI>
-hipError_t gemm_f64(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K, hipStream_t s)
+hipError_t gemm_mfma(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K, hipStream_t s)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     switch (shape) {
     case GEMM_LARGE:
-        hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 16, 2, 2, LA, LB, EPI>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EPI>),
                            dim3(ceil_div(M, 128), ceil_div(N, 128), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_TALL:
-        hipLaunchKernelGGL((gemm_f64_kernel<128, 32, 16, 4, 1, LA, LB, EPI>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EPI>),
                            dim3(ceil_div(M, 128), ceil_div(N, 32), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_MIX:
-        hipLaunchKernelGGL((gemm_f64_kernel<80, 128, 16, 1, 4, LA, LB, EPI>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<80, 128, 16, 1, 4, LA, LB, EPI>),
                            dim3(ceil_div(M, 80), ceil_div(N, 128), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_SMALL:
-        hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 16, 2, 2, LA, LB, EPI>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<64, 64, 16, 2, 2, LA, LB, EPI>),
                            dim3(ceil_div(M, 64), ceil_div(N, 64), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     }
@@ -194,20 +235,20 @@ hipError_t gemm_f64(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K,
 // Split-K GEMM: partials go to `work` (splits * M * N doubles), then reduced.
 // shape GEMM_SMALL (64 x 64 tiles) or GEMM_TALL (128 x 32 tiles, narrow outputs).
 template <class LA, class LB, class EPI>
-hipError_t gemm_f64_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int splits, double *work, hipStream_t s,
+hipError_t gemm_mfma_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int splits, double *work, hipStream_t s,
                            GemmShape shape = GEMM_SMALL)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    if (splits <= 1) return gemm_f64(shape, la, lb, epi, M, N, K, s);
+    if (splits <= 1) return gemm_mfma(shape, la, lb, epi, M, N, K, s);
     int kchunk = ceil_div(ceil_div(K, splits), 16) * 16;
     splits = ceil_div(K, kchunk);
     EpiPartial part{work, M, N};
     if (shape == GEMM_TALL)
-        hipLaunchKernelGGL((gemm_f64_kernel<128, 32, 16, 4, 1, LA, LB, EpiPartial>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EpiPartial>),
                            dim3(ceil_div(M, 128), ceil_div(N, 32), splits), dim3(256), 0, s, la, lb, part, M, N, K,
                            kchunk);
     else
-        hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 16, 2, 2, LA, LB, EpiPartial>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<64, 64, 16, 2, 2, LA, LB, EpiPartial>),
                            dim3(ceil_div(M, 64), ceil_div(N, 64), splits), dim3(256), 0, s, la, lb, part, M, N, K,
                            kchunk);
     long total = (long)M * N;

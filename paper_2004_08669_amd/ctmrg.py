@@ -153,7 +153,7 @@ class CTMRG:
     """A CTMRG context on the current GPU (see include/ctmrg.h)."""
 
     def __init__(self, V, K: float, m: int, bc: str = "fixed", boundary_spin: int = 0, band: int = 32,
-                 gap_tol: float = 1e-10, rank_tol: float = 1e-13, precision: str = "fp64", stream=None):
+                 gap_tol: float | None = None, rank_tol: float = 1e-13, precision: str = "fp64", stream=None):
         lib = load()
         self._lib = lib
         self.V = _f64(V)
@@ -164,7 +164,8 @@ class CTMRG:
         o.bc = {"fixed": 0, "free": 1}[bc]
         o.boundary_spin = boundary_spin
         o.band = band
-        o.gap_tol = gap_tol
+        # multiplets of C' are split by the contraction rounding: ~1e-16 (FP64), ~1e-7 (FP32)
+        o.gap_tol = gap_tol if gap_tol is not None else (1e-10 if precision == "fp64" else 1e-6)
         o.rank_tol = rank_tol
         o.precision = {"fp64": 0, "fp32": 1}[precision]
         o.hip_stream = stream

@@ -50,3 +50,25 @@ def test_invalid_arguments_fail_without_a_gpu_call():
     n = ctypes.c_size_t(0)
     assert lib.ctmrg_workspace_size(20, 512, None, ctypes.byref(n)) == 0
     assert n.value > 8 * (20 * 512) ** 2
+
+
+def test_precision_option_is_validated_without_a_gpu_call():
+    from paper_2004_08669_amd import ctmrg
+    if not os.path.exists(ctmrg.LIB_PATH):
+        pytest.skip("libctmrg.so not built")
+    lib = ctmrg.load()
+    o = ctmrg.default_options()
+    assert o.precision == 0 and o.gap_tol == 1e-10
+    n64, n32 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.ctmrg_workspace_size(20, 512, ctypes.byref(o), ctypes.byref(n64)) == 0
+    o.precision = 1
+    assert lib.ctmrg_workspace_size(20, 512, ctypes.byref(o), ctypes.byref(n32)) == 0
+    # the mixed path adds FP32 copies of W, P, diag(omega) P and U
+    N = 20 * 512
+    assert n32.value - n64.value == 4 * (20 ** 4 + 3 * 512 * N)
+    o.precision = 7
+    assert lib.ctmrg_workspace_size(20, 512, ctypes.byref(o), ctypes.byref(n32)) == 1
+    import numpy as np
+    V = np.array([[1.0], [-1.0]])
+    h = ctypes.c_void_p()
+    assert lib.ctmrg_init(2, 1, ctmrg._p(V), 1.0, 4, ctypes.byref(o), ctypes.byref(h)) == 1

@@ -1,0 +1,188 @@
+"""The mixed-precision path (FP32 contractions on the matrix cores, FP64 eigensolver and state)
+through the C ABI, against the FP64 oracle and against the FP64 GPU path.
+
+Tolerances are derived from FP32 rounding (u = 2^-24):
+  * every C' entry is a sum of products W * P * omega * P.  With the operands rounded
+    to FP32 (four roundings, the scaled weight included), FP32 accumulation over the m
+    states and then the q^2 spin pairs, and the rounding of X to FP32 in between, the
+    error of an entry is at most (m + q^2 + 8) u times the sum of the absolute values of
+    its terms, which the oracle computes from |P| and |omega|;
+  * eigenvalues move by at most ||dC'||_2 <= ||dC'||_F (Weyl);
+  * observables at the fixed point: f within 1e-6 relative, M within 1e-5 absolute,
+    E within 1e-5 absolute (the accuracy the mixed path is specified to reach).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import ctmrg_inputs as I
+import exact as E
+from oracle import ctmrg_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _lib():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_08669_amd import ctmrg
+    ctmrg.load()
+    return ctmrg
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("m,seed", [(8, 0), (37, 2), (64, 3)])
+def test_extension_fp32_within_rounding_bound(m, seed):
+    ct = _lib()
+    V = I.dodecahedron()
+    q = len(V)
+    K = 1.0 / 0.4398
+    P, om = I.random_state(seed, q, m)
+    say(f"[mixed extension] q=20 m={m} seed={seed}")
+    g = ct.CTMRG(V, K, m, precision="fp32")
+    g.set_state(P, om)
+    g.extend()
+    C = g.get("cext")
+    g.close()
+    W = O.weight(V, K)
+    ref = O.extend(W, P, om)
+    absum = O.extend(W, np.abs(P), np.abs(om))
+    bound = (m + q * q + 8) * U32 * absum
+    err = np.abs(C - ref)
+    say(f"  max err {err.max():.3e}, max err / bound {np.max(err / np.maximum(bound, 1e-300)):.3f}")
+    assert np.all(err <= bound)
+    # and the rounding is really FP32 (not FP64) so the bound is meaningful
+    assert err.max() > 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("m,T,steps", [(16, 0.5, 3), (40, 0.44, 3)])
+def test_mixed_one_step_spectrum(m, T, steps):
+    """From an oracle state, one mixed GPU step: the whole spectrum of C' within the
+    Weyl bound of the FP32 contraction error, and the kept dimension equal to the
+    oracle's at the same gap tolerance."""
+    ct = _lib()
+    V = I.dodecahedron()
+    q = len(V)
+    K = 1.0 / T
+    gap = 1e-6
+    o = O.OracleCTMRG(V, K, m, tau=gap)
+    for _ in range(steps):
+        o.step()
+    P, om = o.P.copy(), o.omega.copy()
+    say(f"[mixed one step] m={m} T={T} after {steps} oracle steps")
+    r = O.step(o.W, P, om, m, tau=gap)
+    absum = O.extend(o.W, np.abs(P), np.abs(om))
+    weyl = (m + q * q + 8) * U32 * np.linalg.norm(absum)
+    g = ct.CTMRG(V, K, m, precision="fp32", gap_tol=gap)
+    g.set_state(P, om)
+    g.step(1)
+    spec = g.get("spectrum")
+    me_g = int(np.count_nonzero(g.get("omega")))
+    g.close()
+    nz = spec[np.argsort(-np.abs(spec))][: len(r.lam)]
+    d = np.abs(np.sort(nz) - np.sort(r.lam)).max()
+    say(f"  spectrum err {d:.3e}, Weyl bound {weyl:.3e}, m_eff gpu {me_g} oracle {r.m_eff}")
+    assert d <= weyl
+    assert me_g == r.m_eff
+
+
+@pytest.mark.parametrize("T,m", [(2.0, 16), (1.5, 12)])
+def test_mixed_ising_fixed_point(T, m):
+    """q = 2 with FP32 contractions against Onsager's free energy and Yang's magnetization."""
+    ct = _lib()
+    K = 1.0 / T
+    say(f"[mixed ising] T={T} m={m}")
+    g = ct.CTMRG(I.ising(), K, m, precision="fp32")
+    ks, d, conv = g.run_to_fixed_point(1e-9, 2000)
+    ob = g.observables()
+    g.close()
+    ref_f = -T * E.ising_minus_beta_f(K)
+    say(f"  steps {ks} delta {d:.2e} f {ob['f']:.12f} ref {ref_f:.12f} M {ob['M']:.9f}")
+    assert abs(ob["f"] - ref_f) <= 1e-6 * abs(ref_f)
+    assert abs(ob["E"] - E.ising_energy(K)) <= 1e-5
+    assert abs(ob["M"] - E.ising_magnetization(K)) <= 1e-5
+
+
+def _oracle_fixed_point(V, K, m, tol, max_steps, tau):
+    o = O.OracleCTMRG(V, K, m, tau=tau)
+    for i in range(max_steps):
+        o.step()
+        if i >= 2 and o.delta < tol:
+            break
+        if i % 100 == 99:
+            say(f"  oracle step {i + 1} delta {o.delta:.2e}")
+    return o
+
+
+@pytest.mark.parametrize("T", [0.40])
+def test_mixed_dodecahedron_fixed_point_m16(T):
+    """q = 20, m = 16: the mixed path's fixed point against the FP64 oracle's, both with the
+    same multiplet gap tolerance.  The oracle iterates until its spectrum changes by less
+    than 1e-12; the mixed path until it changes by less than 1e-6 (its steps carry FP32
+    noise of about 1e-7 in w^4, so the change stalls there)."""
+    ct = _lib()
+    V = I.dodecahedron()
+    K = 1.0 / T
+    m, gap = 16, 1e-6
+    say(f"[mixed fixed point] q=20 m={m} T={T}")
+    g = ct.CTMRG(V, K, m, precision="fp32", gap_tol=gap)
+    ks, d, conv = g.run_to_fixed_point(1e-6, 1500)
+    og = g.observables()
+    g.close()
+    say(f"  gpu: steps {ks} delta {d:.2e} m_eff {og['m_eff']}")
+    assert conv
+    o = _oracle_fixed_point(V, K, m, 1e-12, 1500, gap)
+    assert o.delta < 1e-12
+    oo = o.observables()
+    say(f"  oracle: steps {len(o.nC)} m_eff {oo['m_eff']}")
+    say(f"  f {og['f']:.12f} vs {oo['f']:.12f}; E {og['E']:.9f} vs {oo['E']:.9f}; M {og['M']:.9f} vs {oo['M']:.9f}")
+    assert og["m_eff"] == oo["m_eff"]
+    assert abs(og["f"] - oo["f"]) <= 1e-6 * abs(oo["f"])
+    assert abs(og["E"] - oo["E"]) <= 1e-5
+    assert abs(og["M"] - oo["M"]) <= 1e-5
+
+
+def test_mixed_vs_fp64_one_step_m512():
+    """At q = 20, m = 512 (C' 10240 x 10240, the size the bench times): from the same FP64
+    state, one mixed step and one FP64 step give the same kept spectrum and normalization
+    to the accuracy of the FP32 contractions."""
+    ct = _lib()
+    V = I.dodecahedron()
+    K = 1.0 / 0.4398
+    m = 512
+    gap = 1e-6  # the same cut rule on both paths
+    say("[mixed vs fp64] q=20 m=512: 5 FP64 steps")
+    a = ct.CTMRG(V, K, m, gap_tol=gap)
+    a.step(5)
+    st = a.export_state()
+    say("  one FP64 step")
+    a.step(1)
+    oa = a.observables()
+    wa = oa["kept_spectrum"]
+    Pa = a.P_slices()
+    a.close()
+    say("  one mixed step from the same state")
+    b = ct.CTMRG(V, K, m, precision="fp32", gap_tol=gap)
+    b.import_state(st)
+    b.step(1)
+    ob = b.observables()
+    wb = ob["kept_spectrum"]
+    Pb = b.P_slices()
+    b.close()
+    me = min(oa["m_eff"], ob["m_eff"])
+    dw = np.abs(wa[:me] ** 4 - wb[:me] ** 4).max()
+    say(f"  m_eff {oa['m_eff']} / {ob['m_eff']}; max |w^4 diff| {dw:.3e}; S_E {oa['S_E']:.10f} / {ob['S_E']:.10f}")
+    assert oa["m_eff"] == ob["m_eff"]
+    assert dw <= 1e-5
+    assert abs(oa["S_E"] - ob["S_E"]) <= 1e-5
+    # the projected P slices have the same spectra (independent of the eigenvector gauge)
+    ea = np.sort(np.linalg.eigvalsh(Pa[0][:me, :me]))
+    eb = np.sort(np.linalg.eigvalsh(Pb[0][:me, :me]))
+    assert np.abs(ea - eb).max() <= 1e-3
