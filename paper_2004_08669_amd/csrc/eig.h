@@ -5,7 +5,10 @@
 //   stage 1  dense -> band (half-bandwidth b): blocked Householder QR of each
 //            b-column panel below the band (one cooperative kernel per panel,
 //            one grid barrier per column) and a two-sided compact-WY update of
-//            the trailing matrix with GEMMs on the matrix cores;
+//            the trailing matrix with GEMMs on the matrix cores; the matrix is
+//            held in its lower triangle (products with it read the lower
+//            triangle twice, once transposed; the update writes only tiles on
+//            or below the diagonal);
 //   stage 2  band -> tridiagonal: bulge chasing, one wave per step, one
 //            launch per wavefront of independent steps (a sweep trails its
 //            predecessor by three steps);
@@ -54,6 +57,9 @@ struct EigWork {
     unsigned *bar = nullptr;   // grid barrier words (2)
     unsigned *err = nullptr;   // kernel error flags
     hipEvent_t *marks = nullptr;  // optional stage-boundary events (see MarkId)
+    // look-ahead: the next panel's QR runs on s2 while the trailing update runs on the caller's stream
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_cols = nullptr, ev_panel = nullptr;
 };
 
 // Stage boundaries recorded when EigWork::marks is set (indices into marks).

@@ -407,46 +407,37 @@ __global__ void __launch_bounds__(256) tridiag_bounds_kernel(const double *d, co
     }
 }
 
-__device__ inline int sturm_count(const double *d, const double *e2, int N, double x, double pivmin)
+// Multisection by groups of lanes: LPE lanes work on one eigenvalue index k and
+// each evaluates S Sturm counts per pass (their recurrences interleave), so one
+// pass over T splits the bracket at LPE*S points and gains log2(LPE*S + 1) bits.
+// The group then keeps the sub-interval [largest point with count <= k,
+// smallest point with count > k).  All lanes of a wave read the same d[i],
+// e2[i] (one broadcast load per wave).
+template <int LPE, int S>
+__global__ void __launch_bounds__(256) bisect_kernel(const double *d, const double *e2, int N, const double *bounds,
+                                                     double *evals)
 {
-    int cnt = 0;
-    double q = d[0] - x;
-    if (q < 0.0) ++cnt;
-    for (int i = 1; i < N; ++i) {
-        if (fabs(q) < pivmin) q = -pivmin;
-        q = d[i] - x - e2[i - 1] / q;
-        if (q < 0.0) ++cnt;
-    }
-    return cnt;
-}
-
-// Four-shift multisection: each iteration evaluates four independent Sturm
-// counts at the quintisection points of the bracket (their recurrences
-// interleave in one thread), gaining log2(5) bits per pass over T.
-__global__ void __launch_bounds__(256) bisect_kernel(const double *d, const double *e2, int N, const double *bounds, double *evals)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
+    constexpr int P = LPE * S;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane % LPE;
+    const int k = (int)((blockIdx.x * (long)blockDim.x + threadIdx.x) / LPE);
+    const bool active = k < N;
     double lo = bounds[0], hi = bounds[1];
     const double pivmin = bounds[2], tn = bounds[3];
     const double abstol = DBL_EPSILON * tn;
-    for (int it = 0; it < 120; ++it) {
-        if (hi - lo <= fmax(abstol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
-        const double w = (hi - lo) * 0.2;
-        double x[4], q[4];
-        int cnt[4];
+    bool done = !active;
+    for (int it = 0; it < 64; ++it) {
+        if (!done && hi - lo <= fmax(abstol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) done = true;
+        // the whole wave stops when every group has
+        if (__all(done)) break;
+        const double w = (hi - lo) / (double)(P + 1);
+        double x[S], q[S];
+        int cnt[S];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            x[u] = lo + (u + 1) * w;
+        for (int u = 0; u < S; ++u) {
+            x[u] = fmin(hi, lo + (double)(sub * S + u + 1) * w);
             q[u] = d[0] - x[u];
             cnt[u] = q[u] < 0.0 ? 1 : 0;
-        }
-        if (!(x[0] > lo) || !(x[3] < hi)) {  // bracket too narrow to split in five
-            const double mid = 0.5 * (lo + hi);
-            if (mid <= lo || mid >= hi) break;
-            if (sturm_count(d, e2, N, mid, pivmin) <= k) lo = mid;
-            else hi = mid;
-            continue;
         }
         for (int i0 = 1; i0 < N; i0 += 16) {
             const int nI = min(16, N - i0);
@@ -461,7 +452,7 @@ __global__ void __launch_bounds__(256) bisect_kernel(const double *d, const doub
             for (int u = 0; u < 16; ++u) {
                 if (u < nI) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
+                    for (int v = 0; v < S; ++v) {
                         double qq = q[v];
                         if (fabs(qq) < pivmin) qq = -pivmin;
                         qq = dv[u] - x[v] - ev[u] / qq;
@@ -471,20 +462,25 @@ __global__ void __launch_bounds__(256) bisect_kernel(const double *d, const doub
                 }
             }
         }
-        // the eigenvalue k lies in [x_u, x_{u+1}) for the first u with count(x_{u+1}) > k
+        // eigenvalue k lies in [x_a, x_b) with x_a the largest point of count <= k, x_b the smallest of count > k
         double nlo = lo, nhi = hi;
 #pragma unroll
-        for (int u = 3; u >= 0; --u) {
-            if (cnt[u] <= k) { nlo = x[u]; break; }
+        for (int u = 0; u < S; ++u) {
+            if (cnt[u] <= k) nlo = fmax(nlo, x[u]);
+            else nhi = fmin(nhi, x[u]);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (cnt[u] > k) { nhi = x[u]; break; }
+        for (int off = 1; off < LPE; off <<= 1) {
+            nlo = fmax(nlo, __shfl_xor(nlo, off, 64));
+            nhi = fmin(nhi, __shfl_xor(nhi, off, 64));
         }
-        lo = nlo;
-        hi = nhi;
+        if (!done) {
+            if (nlo == lo && nhi == hi) done = true;  // no representable point splits the bracket
+            lo = nlo;
+            hi = nhi;
+        }
     }
-    evals[k] = 0.5 * (lo + hi);
+    if (active && sub == 0) evals[k] = 0.5 * (lo + hi);
 }
 
 // ============================================================================
@@ -994,6 +990,13 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
     }
     (void)hipMemset(w.bar, 0, 64);
     (void)hipMemset(w.err, 0, 64);
+    hipError_t e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_cols, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_panel, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        eig_free(w);
+        return e;
+    }
     return hipSuccess;
 }
 
@@ -1004,6 +1007,9 @@ void eig_free(EigWork &w)
                     w.cstart, w.bar, w.err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (w.ev_cols) (void)hipEventDestroy(w.ev_cols);
+    if (w.ev_panel) (void)hipEventDestroy(w.ev_panel);
+    if (w.s2) (void)hipStreamDestroy(w.s2);
     w = EigWork();
 }
 
@@ -1027,28 +1033,43 @@ static hipError_t launch_coop(const void *fn, dim3 grid, dim3 block, void **args
     return hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)smem, s);
 }
 
+static hipError_t panel_qr(EigWork &w, double *A, long lda, int N, int pi, hipStream_t s)
+{
+    const int b = w.b;
+    const int p = pi * b, r0 = p + b, n = N - r0;
+    const int rows = pqr_rows(b);
+    double *Vp = w.Vx + panel_v_offset(N, b, pi);
+    double *Tp = w.Tp + (long)pi * b * b;
+    double *taup = w.tau1 + (long)pi * b;
+    int G = (n + rows - 1) / rows;
+    void *args[] = {&A, &lda, (void *)&r0, (void *)&p, (void *)&n, (void *)&b, &Vp, &taup, &Tp, &w.part, &w.bar, &w.err};
+    return launch_coop((const void *)panel_qr_kernel, dim3(G), dim3(256), args, pqr_smem(b), s);
+}
+
+// Dense -> band.  Look-ahead: once the next panel's b columns have their
+// update, its QR (on w.s2) overlaps the update of the rest of the trailing
+// matrix (on s); s waits for it before the next product with the trailing matrix.
 static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
 {
     const int b = w.b;
     const int np = num_panels(N, b);
-    const int rows = pqr_rows(b);
-    const size_t smem = pqr_smem(b);
     hipError_t e;
+    if (np == 0) return hipSuccess;
+    e = panel_qr(w, A, lda, N, 0, s);
+    if (e != hipSuccess) return e;
     for (int pi = 0; pi < np; ++pi) {
         const int p = pi * b, r0 = p + b, n = N - r0;
         double *Vp = w.Vx + panel_v_offset(N, b, pi);
         double *Tp = w.Tp + (long)pi * b * b;
-        double *taup = w.tau1 + (long)pi * b;
-        int G = (n + rows - 1) / rows;
-        void *args[] = {&A, &lda, (void *)&r0, (void *)&p, (void *)&n, (void *)&b, &Vp, &taup, &Tp, &w.part, &w.bar, &w.err};
-        e = launch_coop((const void *)panel_qr_kernel, dim3(G), dim3(256), args, smem, s);
-        if (e != hipSuccess) return e;
         double *A22 = A + (long)r0 * lda + r0;
-        // Y = A22 V
+        // Y = A22 V, with A22 held in its lower triangle: Y = L V + (strictly lower)^T V
         {
             const long tiles = (long)ceil_div(n, 128) * ceil_div(b, 32);
             const int sp = splits_for(tiles, n, 256);
-            e = gemm_mfma_splitk(A_RM{A22, lda}, B_RM{Vp, b}, EpiStore{w.Y, b, 1.0}, n, b, n, sp, w.splitk, s, GEMM_TALL);
+            e = gemm_mfma_splitk(A_Lo{A22, lda}, B_RM{Vp, b}, EpiStore{w.Y, b, 1.0}, n, b, n, sp, w.splitk, s, GEMM_TALL);
+            if (e != hipSuccess) return e;
+            e = gemm_mfma_splitk(A_SLoT{A22, lda}, B_RM{Vp, b}, EpiAxpby{w.Y, b, 1.0, 1.0}, n, b, n, sp, w.splitk, s,
+                                 GEMM_TALL);
             if (e != hipSuccess) return e;
         }
         // X = Y T
@@ -1066,9 +1087,26 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
         // W = X - 1/2 V S, and the operands [V|W], [W|V]
         e = gemm_mfma(GEMM_TALL, A_RM{Vp, b}, B_RM{w.sm + b * b, b}, EpiWform{w.X, Vp, w.VW, w.WV, b}, n, b, b, s);
         if (e != hipSuccess) return e;
-        // A22 -= [V|W] [W|V]^T
-        e = gemm_mfma(GEMM_SMALL, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, n, 2 * b, s);
-        if (e != hipSuccess) return e;
+        // A22 -= [V|W] [W|V]^T on the lower triangle (the only part later read)
+        if (pi + 1 < np) {
+            // the next panel's columns first (rows 0..n-1, columns 0..b-1 of A22) ...
+            e = gemm_mfma(GEMM_TALL, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, b, 2 * b,
+                          s);
+            if (e != hipSuccess) return e;
+            // ... then its QR on s2, overlapping the rest of the update on s
+            if ((e = hipEventRecord(w.ev_cols, s)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(w.s2, w.ev_cols, 0)) != hipSuccess) return e;
+            e = panel_qr(w, A, lda, N, pi + 1, w.s2);
+            if (e != hipSuccess) return e;
+            if ((e = hipEventRecord(w.ev_panel, w.s2)) != hipSuccess) return e;
+            e = gemm_mfma_lower(A_RM{w.VW + (long)b * 2 * b, 2 * b}, B_T{w.WV + (long)b * 2 * b, 2 * b},
+                                EpiAxpbyLower{A22 + (long)b * lda + b, lda, -1.0, 1.0}, n - b, 2 * b, s);
+            if (e != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, w.ev_panel, 0)) != hipSuccess) return e;
+        } else {
+            e = gemm_mfma_lower(A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpbyLower{A22, lda, -1.0, 1.0}, n, 2 * b, s);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -1104,7 +1142,9 @@ hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s)
     hipLaunchKernelGGL(band_to_tridiag_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, s, w.band, N, b, w.d, w.e, w.e2);
     double *bounds = w.sm + 3 * b * b;
     hipLaunchKernelGGL(tridiag_bounds_kernel, dim3(1), dim3(256), 0, s, w.d, w.e, N, bounds);
-    hipLaunchKernelGGL(bisect_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, s, w.d, w.e2, N, bounds, w.evals);
+    constexpr int LPE = 16, SH = 2;  // 16 lanes per eigenvalue, 2 shifts per lane: 32 points per pass
+    hipLaunchKernelGGL((bisect_kernel<LPE, SH>), dim3(ceil_div((long)N * LPE, 256)), dim3(256), 0, s, w.d, w.e2, N,
+                       bounds, w.evals);
     mark(w, MK_BISECT, s);
     return hipGetLastError();
 }

@@ -65,6 +65,27 @@ struct B_T_ {
     static constexpr bool kContigK = true;
     __device__ T operator()(int k, int j) const { return p[(long)j * ld + k]; }
 };
+// A symmetric matrix held in its lower triangle (row-major), as two operands:
+// the lower triangle with the diagonal, and the strictly lower triangle read
+// transposed (its elements above the diagonal).  A . B = A_Lo . B + A_SLoT . B.
+// Both restrict the K range of a tile (kRange) to the part that can be nonzero.
+struct A_Lo {
+    using value_type = double;
+    const double *p; long ld;
+    static constexpr bool kContigK = true;
+    static constexpr bool kRange = true;
+    __device__ double operator()(int i, int k) const { return (k <= i) ? p[(long)i * ld + k] : 0.0; }
+    __device__ static void range(int m0, int bm, int &klo, int &khi) { khi = min(khi, m0 + bm); }
+};
+struct A_SLoT {
+    using value_type = double;
+    const double *p; long ld;
+    static constexpr bool kContigK = false;
+    static constexpr bool kRange = true;
+    __device__ double operator()(int i, int k) const { return (k > i) ? p[(long)k * ld + i] : 0.0; }
+    __device__ static void range(int m0, int, int &klo, int &) { klo = max(klo, m0 + 1); }
+};
+
 using A_RM = A_RM_<double>;
 using A_T = A_T_<double>;
 using B_RM = B_RM_<double>;
@@ -89,6 +110,15 @@ struct EpiStoreF {  // C = alpha * acc, rounded to FP32
     float *p; long ld; double alpha;
     __device__ void operator()(int i, int j, double v, int) const { p[(long)i * ld + j] = (float)(alpha * v); }
 };
+struct EpiAxpbyLower {  // C = alpha * acc + beta * C on the tiles on or below the diagonal only
+    double *p; long ld; double alpha, beta;
+    static constexpr bool kLowerTiles = true;
+    __device__ void operator()(int i, int j, double v, int) const
+    {
+        double *c = p + (long)i * ld + j;
+        *c = alpha * v + beta * (*c);
+    }
+};
 struct EpiPartial {  // split-K partial sums, reduced by reduce_partials
     double *p; long M, N;
     __device__ void operator()(int i, int j, double v, int split) const
@@ -96,6 +126,12 @@ struct EpiPartial {  // split-K partial sums, reduced by reduce_partials
         p[((long)split * M + i) * N + j] = v;
     }
 };
+
+// ---------------------------------------------------------------- optional traits
+template <class T, class = void> struct has_krange : std::false_type {};
+template <class T> struct has_krange<T, std::void_t<decltype(T::kRange)>> : std::true_type {};
+template <class T, class = void> struct lower_tiles : std::false_type {};
+template <class T> struct lower_tiles<T, std::void_t<decltype(T::kLowerTiles)>> : std::true_type {};
 
 // ---------------------------------------------------------------- MFMA step per element type
 template <class T> struct Mfma;
@@ -131,9 +167,21 @@ gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave % WM, wn = wave / WM;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int kbeg = blockIdx.z * kchunk;
-    const int kend = min(K, kbeg + kchunk);
+    int tile_m = blockIdx.x, tile_n = blockIdx.y;
+    if constexpr (lower_tiles<EPI>::value) {
+        // blockIdx.x enumerates the tiles (I, J) with J <= I
+        static_assert(BM == BN, "square tiles");
+        const int t = blockIdx.x;
+        int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > t) --I;
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        tile_m = I;
+        tile_n = t - I * (I + 1) / 2;
+    }
+    const int m0 = tile_m * BM, n0 = tile_n * BN;
+    int kbeg = blockIdx.z * kchunk;
+    int kend = min(K, kbeg + kchunk);
+    if constexpr (has_krange<LA>::value) LA::range(m0, BM, kbeg, kend);
 
     typename MF::acc_t acc[TM][TN];
 #pragma unroll
@@ -141,24 +189,58 @@ gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = MF::zero();
 
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-#pragma unroll 4
-        for (int idx = tid; idx < BM * BK; idx += NT) {
+    // Each thread holds its share of the next K slice in registers while the
+    // matrix cores work on the current one from LDS (one slice of prefetch).
+    constexpr int PA = (BM * BK + NT - 1) / NT;
+    constexpr int PB = (BN * BK + NT - 1) / NT;
+    T ra[PA], rb[PB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < PA; ++u) {
+            const int idx = tid + u * NT;
             int mm, kk;
             if (LA::kContigK) { mm = idx / BK; kk = idx - mm * BK; }
             else { kk = idx / BM; mm = idx - kk * BM; }
             const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < M && gk < kend) ? la(gm, gk) : T(0);
+            ra[u] = (idx < BM * BK && gm < M && gk < kend) ? la(gm, gk) : T(0);
         }
-#pragma unroll 4
-        for (int idx = tid; idx < BN * BK; idx += NT) {
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            const int idx = tid + u * NT;
             int nn, kk;
             if (LB::kContigK) { nn = idx / BK; kk = idx - nn * BK; }
             else { kk = idx / BN; nn = idx - kk * BN; }
             const int gn = n0 + nn, gk = k0 + kk;
-            Bs[kk][nn] = (gn < N && gk < kend) ? lb(gk, gn) : T(0);
+            rb[u] = (idx < BN * BK && gn < N && gk < kend) ? lb(gk, gn) : T(0);
         }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int u = 0; u < PA; ++u) {
+            const int idx = tid + u * NT;
+            if (idx < BM * BK) {
+                int mm, kk;
+                if (LA::kContigK) { mm = idx / BK; kk = idx - mm * BK; }
+                else { kk = idx / BM; mm = idx - kk * BM; }
+                As[kk][mm] = ra[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            const int idx = tid + u * NT;
+            if (idx < BN * BK) {
+                int nn, kk;
+                if (LB::kContigK) { nn = idx / BK; kk = idx - nn * BK; }
+                else { kk = idx / BN; nn = idx - kk * BN; }
+                Bs[kk][nn] = rb[u];
+            }
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        stage();
         __syncthreads();
+        if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             T a[TM], b[TN];
@@ -229,6 +311,18 @@ hipError_t gemm_mfma(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K
                            dim3(ceil_div(M, 64), ceil_div(N, 64), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     }
+    return hipGetLastError();
+}
+
+// C = alpha A B + beta C on the tiles of a square C (M = N) on or below the
+// diagonal (64 x 64 tiles); the tiles above it are not touched.
+template <class LA, class LB>
+hipError_t gemm_mfma_lower(LA la, LB lb, EpiAxpbyLower epi, int N, int K, hipStream_t s)
+{
+    if (N <= 0) return hipSuccess;
+    const long T = ceil_div(N, 64);
+    hipLaunchKernelGGL((gemm_mfma_kernel<64, 64, 16, 2, 2, LA, LB, EpiAxpbyLower>), dim3((unsigned)(T * (T + 1) / 2), 1, 1),
+                       dim3(256), 0, s, la, lb, epi, N, N, K, K);
     return hipGetLastError();
 }
 
