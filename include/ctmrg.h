@@ -118,8 +118,51 @@ ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *ctx, double tol, int max_steps,
  * m entries) receives omega (normalized kept eigenvalues, zero padded). */
 ctmrg_status ctmrg_observables(ctmrg_ctx *ctx, ctmrg_observables_t *out, double *kept_spectrum);
 
-/* Fixed-point adjoint (dF/dK, d2F/dK2).  Not available in this build:
- * returns CTMRG_E_UNSUPPORTED. */
+/* Derivatives of the free energy per site F = beta f at the fixed point with
+ * respect to K, by implicit differentiation through the fixed-point map
+ * (tangent mode).  The state must be converged (Delta < 1e-6; the routine
+ * then converges it further in FP64, in the gauge in which the kept
+ * eigenvectors of consecutive steps are aligned inside every multiplet, until
+ * P repeats element by element).  The tangent t = dx/dK solves t = J t + d_K Phi
+ * (J: the derivative of one step, with the kept eigenvectors' derivative
+ * sum_i u_i (u_i^T dC' u_j) / (lambda_j - lambda_i) over the discarded
+ * eigenpairs i of C', and the corner's tangent carried as a full symmetric
+ * block, so that rotations inside the kept space -- degenerate or not -- are
+ * treated as gauge), and dF/dK follows from F = -1/2 ln ||P~||_F at
+ * the fixed point.  The iteration stops when the tangent changes by less than
+ * 1e-12, or when ds (hence dF/dK) changes by less than 1e-14 relative over two
+ * consecutive windows of ten iterations (slowly converging directions that do
+ * not move F; tangent_change reports the rest).  With second_order != 0 the
+ * second derivative is the
+ * central difference of dF/dK at K (1 +- 1e-4), each from its own converged
+ * fixed point.  The context's state, K and weight are left unchanged; work
+ * memory (about 16 (q m_eff)^2 doubles plus a full eigensolver workspace) is
+ * allocated on the first call and kept until ctmrg_destroy.  Runs in FP64
+ * whatever the context's precision.
+ * Errors: CTMRG_E_STATE if the state is not converged; CTMRG_E_NOT_CONVERGED
+ * if the aligned fixed point or the tangent iteration does not converge;
+ * CTMRG_E_NUMERICAL if the kept dimension changes or a multiplet is larger
+ * than 8. */
+typedef struct {
+    double F;              /* beta f = -1/2 ln ||P~||_F at the aligned fixed point           */
+    double dF_dK;          /* dF/dK, the energy per site                                      */
+    double d2F_dK2;        /* d2F/dK2 (second_order only; else 0)                             */
+    double gauge_residual; /* max |P_next - P| of the aligned fixed point                     */
+    double tangent_change; /* max change of the tangent in its last iteration                 */
+    int aligned_steps;     /* FP64 steps taken to the aligned fixed point                     */
+    int iterations;        /* tangent iterations                                              */
+    int n_eigen;           /* eigenpairs of C' used (those above rank_tol |lambda_1|)          */
+} ctmrg_derivative_t;
+
+ctmrg_status ctmrg_fixed_point_derivative(ctmrg_ctx *ctx, int second_order, ctmrg_derivative_t *out);
+
+/* Backward pass for the observables (f, E, M) of the fixed point as functions
+ * of K: *K_bar = obs_bar[0] df/dK + obs_bar[1] dE/dK, with f = F/K and E = dF/dK
+ * (the derivative form of the energy, which equals the impurity energy of
+ * ctmrg_observables at the fixed point).  dE/dK = d2F/dK2 is computed only when
+ * obs_bar[1] != 0 or d2F_dK2 is non-NULL.  The derivative of M is not available:
+ * obs_bar[2] must be 0 (else CTMRG_E_UNSUPPORTED).  Same requirements and
+ * errors as ctmrg_fixed_point_derivative. */
 ctmrg_status ctmrg_backward(ctmrg_ctx *ctx, const double obs_bar[3], double *K_bar, double *d2F_dK2);
 
 /* Checkpoint of the state (P, Omega, the normalization history, step count).

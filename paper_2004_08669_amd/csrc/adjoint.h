@@ -1,0 +1,79 @@
+// Derivative of the CTMRG fixed point with respect to the coupling K
+// (implicit differentiation through the fixed-point map, tangent mode).
+//
+// With P normalized by its Frobenius norm (the normalization does not change
+// the partition function per vertex, Sec. 3, Algorithm 3), the free energy per
+// site at a fixed point x* is F = beta f = -1/2 ln s*, s* = ||P~(x*)||_F.  Its
+// total derivative is
+//     dF/dK = -1/2 (d s / dK) / s*,   ds/dK = d_K s + d_x s . t,
+// where the tangent t = dx*/dK solves t = J t + d_K Phi (J = d Phi / dx at x*),
+// found by iterating t <- J t + d_K Phi.  J t is the hand-written directional
+// derivative of one step: the product rule through the contractions, and the
+// derivative of the kept eigenvectors of C',
+//     dU_j = sum_i u_i (u_i^T dC' u_j) / (lambda_j - lambda_i)   (i discarded),
+// over all eigenpairs i of C' outside the kept set.  Rotations inside the kept
+// space are gauge (only the kept subspace enters the next step), so the tangent
+// of the corner is carried as a full symmetric block
+//     dOmega = U_k^T dC' U_k / n_C - Lambda dn_C / n_C^2
+// instead of the derivative of a diagonal; no (near-)degenerate pair of kept
+// states then enters a denominator, and a pair split by the cut cannot occur
+// (the cut never splits a multiplet).  The base point is a fixed point in one
+// gauge: FP64 steps whose kept eigenvectors are rotated inside each multiplet
+// to best match the previous step's (orthogonal Procrustes), until P repeats
+// element by element.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "eig.h"
+
+namespace ctm {
+
+struct AdjInputs {
+    int q = 0, m = 0, d = 0;          // context cutoff m, kept dimension d of the converged state
+    const double *W = nullptr;        // q^2 x q^2 weight at K
+    const double *WH = nullptr;       // W * h4 (h4 = -sum of the plaquette bonds), so dW/dK = -WH
+    const double *A = nullptr;        // m x (q m) state (padded), omega (m), last kept U ((q m) x m)
+    const double *omega = nullptr;
+    const double *U = nullptr;
+    double gap_tol = 1e-10, rank_tol = 1e-13;
+    int max_aligned_steps = 500, max_iterations = 3000;
+    double gauge_tol = 1e-10;         // element-wise |P_next - P| of the aligned fixed point
+    double tangent_tol = 1e-12;       // max change of the tangent between iterations (or ds settled, see
+                                      // adjoint_dFdK)
+};
+
+struct AdjResult {
+    double F = 0.0;            // -1/2 ln s*
+    double dFdK = 0.0;
+    double gauge_residual = 0.0;
+    double tangent_change = 0.0;
+    int aligned_steps = 0;
+    int iterations = 0;
+    int n_eigen = 0;           // eigenpairs of C'* used (its rank)
+};
+
+struct AdjWork {
+    int q = 0, d = 0, n = 0, band = 32;
+    double *A = nullptr, *OA = nullptr, *Pt = nullptr, *om = nullptr, *omn = nullptr, *zero = nullptr;
+    double *Ucur = nullptr, *Uprev = nullptr, *Mov = nullptr;
+    double *X = nullptr, *C = nullptr, *Y = nullptr, *Z = nullptr, *Cb = nullptr, *Zb = nullptr;
+    double *Uall = nullptr, *M3 = nullptr, *lam = nullptr, *sel = nullptr;
+    double *dA = nullptr, *dAn = nullptr, *dOA = nullptr, *dom = nullptr, *domn = nullptr;
+    double *dX = nullptr, *dC = nullptr, *dY = nullptr, *dZ = nullptr, *dPt = nullptr;
+    double *T1 = nullptr, *Bm = nullptr, *R = nullptr, *dU = nullptr;
+    double *part = nullptr, *scal = nullptr, *hscal = nullptr;
+    PostOut *post = nullptr, *hpost = nullptr;
+    unsigned *err = nullptr;
+    EigWork eig;
+};
+
+hipError_t adj_alloc(AdjWork &w, int q, int d, int band);
+void adj_free(AdjWork &w);
+
+// Returns 0 on success; otherwise a ctmrg_status value with a message in *msg.
+int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s, std::string *msg);
+
+}  // namespace ctm

@@ -1,0 +1,558 @@
+// Derivative of the CTMRG fixed point with respect to K; see adjoint.h.
+#include <math.h>
+
+#include <algorithm>
+
+#include "adjoint.h"
+#include "blocks.h"
+#include "common.h"
+#include "contract.h"
+#include "ctmrg.h"
+#include "gemm.h"
+
+namespace ctm {
+
+namespace {
+
+constexpr int KB = 8;        // largest multiplet the alignment handles
+constexpr int NSCAL = 16;    // device scalars: 0 s*, 1 dn_C/n_C^3-scaled, 2 ds, 3 tangent change, 5 gauge residual
+
+enum { S_NORM = 0, S_DNC = 1, S_DS = 2, S_CHANGE = 3, S_GAUGE = 5 };
+enum { OP_SUM = 0, OP_SQRT = 1, OP_MAX = 2, OP_MAX_ACC = 3 };
+
+int grid_for(long n) { return (int)std::max<long>(1, std::min<long>(1024, (n + 255) / 256)); }
+
+// ---------------------------------------------------------------- small kernels
+
+// Ad (d x q d), omd (d), Ud (q d x d) from the padded state A (m x q m), omega (m), U (q m x m).
+__global__ void compact_kernel(const double *A, const double *om, const double *U, int q, int m, int d, double *Ad,
+                               double *omd, double *Ud)
+{
+    const long n = (long)q * d;
+    const long totA = (long)d * n;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < totA; idx += (long)gridDim.x * blockDim.x) {
+        const int g = (int)(idx / n);
+        const int c = (int)(idx - (long)g * n);
+        const int s = c / d, a = c - s * d;
+        Ad[idx] = A[(long)g * q * m + s * m + a];
+        const int r = g;  // reuse the index range for U: row c, column r
+        Ud[(long)c * d + r] = U[(long)(s * m + a) * m + r];
+    }
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < d; i += (long)gridDim.x * blockDim.x) omd[i] = om[i];
+}
+
+__global__ void __launch_bounds__(256) dot_partial_kernel(const double *x, const double *y, long n, double *part)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        acc += x[i] * y[i];
+    acc = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(256) maxdiff_partial_kernel(const double *x, const double *y, long n, double *part)
+{
+    __shared__ double red[4];
+    double mx = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        mx = fmax(mx, fabs(x[i] - y[i]));
+    mx = block_max<256>(mx, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = mx;
+}
+
+__global__ void finalize_kernel(const double *part, int np, double *out, int op, double scale)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    if (op == OP_SUM || op == OP_SQRT) {
+        for (int i = 0; i < np; ++i) acc += part[i];
+        *out = (op == OP_SQRT) ? sqrt(acc) : scale * acc;
+    } else {
+        for (int i = 0; i < np; ++i) acc = fmax(acc, part[i]);
+        *out = (op == OP_MAX_ACC) ? fmax(*out, acc) : acc;
+    }
+}
+
+// y = x / *s
+__global__ void div_by_kernel(const double *x, double *y, long n, const double *s)
+{
+    const double inv = 1.0 / *s;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = x[i] * inv;
+}
+
+__global__ void axpy_kernel(double *y, const double *x, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] += x[i];
+}
+
+// dst (rows x cols, ld_dst) = src (rows x cols, ld_src)
+__global__ void copy2d_kernel(const double *src, long ld_src, double *dst, long ld_dst, int rows, int cols)
+{
+    const long total = (long)rows * cols;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int r = (int)(idx / cols), c = (int)(idx - (long)r * cols);
+        dst[r * ld_dst + c] = src[r * ld_src + c];
+    }
+}
+
+// Symmetric k x k eigendecomposition by cyclic Jacobi (k <= KB, one thread).
+__device__ void small_jacobi(double (&S)[KB][KB], double (&V)[KB][KB], int k)
+{
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < k; ++p)
+            for (int r = p + 1; r < k; ++r) off += S[p][r] * S[p][r];
+        if (off < 1e-60) break;
+        for (int p = 0; p < k; ++p)
+            for (int r = p + 1; r < k; ++r) {
+                if (S[p][r] == 0.0) continue;
+                const double th = (S[r][r] - S[p][p]) / (2.0 * S[p][r]);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+                for (int i = 0; i < k; ++i) {  // columns p, r
+                    const double a = S[i][p], b = S[i][r];
+                    S[i][p] = c * a - sn * b;
+                    S[i][r] = sn * a + c * b;
+                }
+                for (int i = 0; i < k; ++i) {  // rows p, r
+                    const double a = S[p][i], b = S[r][i];
+                    S[p][i] = c * a - sn * b;
+                    S[r][i] = sn * a + c * b;
+                }
+                for (int i = 0; i < k; ++i) {
+                    const double a = V[i][p], b = V[i][r];
+                    V[i][p] = c * a - sn * b;
+                    V[i][r] = sn * a + c * b;
+                }
+            }
+    }
+}
+
+// Rotate the kept columns of U inside each multiplet to best match the previous
+// vectors (orthogonal Procrustes): with M = U_b^T Uprev_b, U_b <- U_b M (M^T M)^{-1/2}.
+// lamk: the kept eigenvalues in the order of the columns (descending |lambda|);
+// multiplets are separated by gaps |l_j| - |l_{j+1}| > gap_tol |l_1| (the cut rule).
+// One workgroup per column; only the first column of a multiplet works.
+__global__ void __launch_bounds__(64) align_kernel(double *U, int ldu, int n, const double *Mov, int d,
+                                                  const double *lamk, double gap_tol, unsigned *err)
+{
+    const int j = blockIdx.x;
+    const double tol = gap_tol * fabs(lamk[0]);
+    if (j > 0 && !(fabs(lamk[j - 1]) - fabs(lamk[j]) > tol)) return;
+    int k = 1;
+    while (j + k < d && !(fabs(lamk[j + k - 1]) - fabs(lamk[j + k]) > tol)) ++k;
+    __shared__ double R[KB][KB];
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        ok = 1;
+        if (k > KB) {
+            ok = 0;
+            raise_error(err, KERR_ALIGN);
+        } else {
+            double M[KB][KB], S[KB][KB], V[KB][KB];
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) M[a][b] = Mov[(long)(j + a) * d + (j + b)];
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) {
+                    double acc = 0.0;
+                    for (int c = 0; c < k; ++c) acc += M[c][a] * M[c][b];
+                    S[a][b] = acc;
+                }
+            small_jacobi(S, V, k);
+            double smax = 0.0, smin = INFINITY;
+            for (int a = 0; a < k; ++a) {
+                smax = fmax(smax, S[a][a]);
+                smin = fmin(smin, S[a][a]);
+            }
+            if (!(smin > 1e-6 * smax)) {
+                ok = 0;
+                raise_error(err, KERR_ALIGN);
+            } else {
+                // R = M V diag(sigma^-1/2) V^T
+                double T[KB][KB];
+                for (int a = 0; a < k; ++a)
+                    for (int b = 0; b < k; ++b) {
+                        double acc = 0.0;
+                        for (int c = 0; c < k; ++c) acc += V[a][c] * V[b][c] / sqrt(S[c][c]);
+                        T[a][b] = acc;
+                    }
+                for (int a = 0; a < k; ++a)
+                    for (int b = 0; b < k; ++b) {
+                        double acc = 0.0;
+                        for (int c = 0; c < k; ++c) acc += M[a][c] * T[c][b];
+                        R[a][b] = acc;
+                    }
+            }
+        }
+    }
+    __syncthreads();
+    if (!ok) return;
+    for (int r = threadIdx.x; r < n; r += 64) {
+        double x[KB];
+        for (int a = 0; a < k; ++a) x[a] = U[(long)r * ldu + j + a];
+        for (int c = 0; c < k; ++c) {
+            double acc = 0.0;
+            for (int a = 0; a < k; ++a) acc += x[a] * R[a][c];
+            U[(long)r * ldu + j + c] = acc;
+        }
+    }
+}
+
+// UL[r][c] = U[r][c] lam_c^3 for c < np (row length ld)
+__global__ void scale_cols_cube_kernel(const double *U, long ld, int rows, int np, const double *lam, double *UL)
+{
+    const long total = (long)rows * np;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int r = (int)(idx / np), c = (int)(idx - (long)r * np);
+        const double l = lam[c];
+        UL[r * ld + c] = U[r * ld + c] * l * l * l;
+    }
+}
+
+// The eigen part of the tangent, in place on B = U_all^T dC' U_k (np x d):
+//   kept rows i < d: the corner block dOm[i][j] = B[i][j] / n_C - delta_ij lam_j dn_C / n_C^2,
+//     and G[i][j] = 0 (rotations inside the kept space are gauge: the state carries them in dOm);
+//   other rows: G[i][j] = B[i][j] / (lam_j - lam_i) (no kept multiplet reaches past the cut).
+// dnc holds dn_C = <C'^3, dC'> / n_C^3.
+__global__ void eigen_tangent_kernel(double *B, int np, int d, const double *lam, double nC, const double *dnc,
+                                     double *dOm)
+{
+    const double dn = *dnc;
+    const long total = (long)np * d;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / d), j = (int)(idx - (long)i * d);
+        const double b = B[idx];
+        if (i < d) {
+            dOm[(long)i * d + j] = b / nC - (i == j ? lam[j] * dn / (nC * nC) : 0.0);
+            B[idx] = 0.0;
+        } else {
+            B[idx] = b / (lam[j] - lam[i]);
+        }
+    }
+}
+
+// dU[:, j] += R[:, j] / lam_j: the eigenvectors of C' with eigenvalue zero, through
+// the complement of the computed ones.
+__global__ void nullspace_tangent_kernel(double *dU, const double *R, long n, int d, const double *lam)
+{
+    const long total = n * d;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(idx % d);
+        dU[idx] += R[idx] / lam[j];
+    }
+}
+
+// dOA = Omega dA (rows scaled; the product dOmega A is added by a GEMM)
+__global__ void scale_rows_kernel(const double *om, const double *dA, int d, long n, double *dOA)
+{
+    const long total = (long)d * n;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x)
+        dOA[idx] = om[idx / n] * dA[idx];
+}
+
+// P = P~ / s:  dP = dP~ / s - P~ ds / s^2
+__global__ void tangent_norm_kernel(const double *dPt, const double *Pt, long total, const double *s, const double *ds,
+                                    double *dA)
+{
+    const double sv = *s, dsv = *ds;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x)
+        dA[i] = dPt[i] / sv - Pt[i] * dsv / (sv * sv);
+}
+
+// ---------------------------------------------------------------- host helpers
+
+hipError_t reduce_dot(const double *x, const double *y, long n, double *part, double *out, int op, double scale,
+                      hipStream_t s)
+{
+    const int np = grid_for(n);
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(np), dim3(256), 0, s, x, y, n, part);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, part, np, out, op, scale);
+    return hipGetLastError();
+}
+
+hipError_t reduce_maxdiff(const double *x, const double *y, long n, double *part, double *out, bool acc, hipStream_t s)
+{
+    const int np = grid_for(n);
+    hipLaunchKernelGGL(maxdiff_partial_kernel, dim3(np), dim3(256), 0, s, x, y, n, part);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, part, np, out, acc ? OP_MAX_ACC : OP_MAX, 1.0);
+    return hipGetLastError();
+}
+
+hipError_t copy2d(const double *src, long lds, double *dst, long ldd, int rows, int cols, hipStream_t s)
+{
+    hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for((long)rows * cols)), dim3(256), 0, s, src, lds, dst, ldd, rows,
+                       cols);
+    return hipGetLastError();
+}
+
+// U (n x d, row stride ldu) rotated inside each kept multiplet towards Uprev (n x d).
+hipError_t align_to(AdjWork &w, double *U, int ldu, const double *lamk, double gap_tol, hipStream_t s)
+{
+    const int n = w.n, d = w.d;
+    hipError_t e = gemm_mfma(GEMM_SMALL, A_T{U, ldu}, B_RM{w.Uprev, d}, EpiStore{w.Mov, d, 1.0}, d, d, n, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(align_kernel, dim3(d), dim3(64), 0, s, U, ldu, n, w.Mov, d, lamk, gap_tol, w.err);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- allocation
+
+hipError_t adj_alloc(AdjWork &w, int q, int d, int band)
+{
+    w.q = q;
+    w.d = d;
+    w.n = q * d;
+    w.band = band;
+    const size_t n = (size_t)w.n, dd = (size_t)d;
+    struct Req { double **p; size_t n; };
+    Req reqs[] = {
+        {&w.A, dd * n}, {&w.OA, dd * n}, {&w.Pt, dd * n}, {&w.om, n + 8}, {&w.omn, n + 8}, {&w.zero, n + 8},
+        {&w.Ucur, n * dd}, {&w.Uprev, n * dd}, {&w.Mov, dd * dd},
+        {&w.X, n * n}, {&w.C, n * n}, {&w.Y, n * n}, {&w.Z, n * n}, {&w.Cb, n * n}, {&w.Zb, n * n},
+        {&w.Uall, n * n}, {&w.M3, n * n}, {&w.lam, n + 8}, {&w.sel, n + 8},
+        {&w.dA, dd * n}, {&w.dAn, dd * n}, {&w.dOA, dd * n}, {&w.dom, dd * dd}, {&w.domn, dd * dd},
+        {&w.dX, n * n}, {&w.dC, n * n}, {&w.dY, n * n}, {&w.dZ, n * n}, {&w.dPt, dd * n},
+        {&w.T1, n * dd}, {&w.Bm, n * dd}, {&w.R, n * dd}, {&w.dU, n * dd},
+        {&w.part, 1024}, {&w.scal, NSCAL + n + 8},
+    };
+    for (auto &r : reqs) {
+        hipError_t e = hipMalloc((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc((void **)&w.post, sizeof(PostOut));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&w.hpost, sizeof(PostOut), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&w.hscal, sizeof(double) * NSCAL, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void **)&w.err, sizeof(unsigned) * 4);
+    if (e == hipSuccess) e = eig_alloc(w.eig, w.n, w.n, band);
+    if (e == hipSuccess) e = hipMemset(w.zero, 0, sizeof(double) * (n + 8));
+    return e;
+}
+
+void adj_free(AdjWork &w)
+{
+    double *bufs[] = {w.A, w.OA, w.Pt, w.om, w.omn, w.zero, w.Ucur, w.Uprev, w.Mov, w.X, w.C, w.Y, w.Z, w.Cb,
+                      w.Zb, w.Uall, w.M3, w.lam, w.sel, w.dA, w.dAn, w.dOA, w.dom, w.domn, w.dX, w.dC, w.dY, w.dZ,
+                      w.dPt, w.T1, w.Bm, w.R, w.dU, w.part, w.scal};
+    for (double *p : bufs)
+        if (p) (void)hipFree(p);
+    if (w.post) (void)hipFree(w.post);
+    if (w.hpost) (void)hipHostFree(w.hpost);
+    if (w.hscal) (void)hipHostFree(w.hscal);
+    if (w.err) (void)hipFree(w.err);
+    eig_free(w.eig);
+    const int band = w.band;
+    w = AdjWork();
+    w.band = band;
+}
+
+// ---------------------------------------------------------------- the derivative
+
+int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s, std::string *msg)
+{
+    const int q = in.q, d = in.d, n = q * d;
+    const int q2 = q * q;
+    hipError_t e = hipSuccess;
+#define ADJ_CK(expr)                                                          \
+    do {                                                                      \
+        if ((e = (expr)) != hipSuccess) {                                     \
+            *msg = std::string(#expr) + ": " + hipGetErrorString(e);          \
+            return e == hipErrorOutOfMemory ? CTMRG_E_OUT_OF_MEMORY : CTMRG_E_HIP; \
+        }                                                                     \
+    } while (0)
+    auto fetch_post = [&]() -> hipError_t {
+        hipError_t e2 = hipMemcpyAsync(w.hpost, w.post, sizeof(PostOut), hipMemcpyDeviceToHost, s);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+        return e2;
+    };
+    auto fetch_scal = [&]() -> hipError_t {
+        hipError_t e2 = hipMemcpyAsync(w.hscal, w.scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, s);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+        return e2;
+    };
+    auto take_err = [&]() -> unsigned {
+        unsigned h = 0;
+        (void)hipMemcpy(&h, w.err, sizeof(unsigned), hipMemcpyDeviceToHost);
+        (void)hipMemset(w.err, 0, sizeof(unsigned));
+        return h | eig_take_errors(w.eig);
+    };
+    if (w.q != q || w.d != d || !w.A) {
+        adj_free(w);
+        ADJ_CK(adj_alloc(w, q, d, w.band));
+    }
+    ADJ_CK(hipMemsetAsync(w.err, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(compact_kernel, dim3(grid_for((long)d * n)), dim3(256), 0, s, in.A, in.omega, in.U, q, in.m, d,
+                       w.A, w.om, w.Uprev);
+    ADJ_CK(hipGetLastError());
+
+    // ---- 1. fixed point in the aligned gauge, P normalized by its Frobenius norm
+    double resid = INFINITY;
+    int k = 0;
+    for (k = 0; k < in.max_aligned_steps; ++k) {
+        ADJ_CK(extension_products(w.A, w.om, w.OA, w.X, q, d, s));
+        ADJ_CK(weight_mix(in.W, w.X, w.C, q, d, s));
+        ADJ_CK(eig_values(w.eig, w.C, n, n, s));
+        ADJ_CK(eig_post(w.eig, n, d, in.gap_tol, in.rank_tol, w.zero, w.omn, w.sel, w.post, s));
+        ADJ_CK(fetch_post());
+        const PostOut po = *w.hpost;
+        if (po.m_eff != d) {
+            *msg = "the kept dimension changed from " + std::to_string(d) + " to " + std::to_string(po.m_eff) +
+                   " while converging the aligned fixed point";
+            return CTMRG_E_NUMERICAL;
+        }
+        ADJ_CK(eig_vectors(w.eig, nullptr, 0, n, d, w.sel, po.nclusters, w.Ucur, d, s));
+        ADJ_CK(align_to(w, w.Ucur, d, w.sel, in.gap_tol, s));
+        ADJ_CK(halfrow_products(w.A, w.Ucur, w.Y, q, d, s));
+        ADJ_CK(weight_mix(in.W, w.Y, w.Z, q, d, s));
+        ADJ_CK(projection(w.Ucur, w.Z, w.Pt, q, d, s));
+        ADJ_CK(reduce_dot(w.Pt, w.Pt, (long)d * n, w.part, w.scal + S_NORM, OP_SQRT, 1.0, s));
+        hipLaunchKernelGGL(div_by_kernel, dim3(grid_for((long)d * n)), dim3(256), 0, s, w.Pt, w.dAn, (long)d * n,
+                           w.scal + S_NORM);
+        ADJ_CK(reduce_maxdiff(w.dAn, w.A, (long)d * n, w.part, w.scal + S_GAUGE, false, s));
+        ADJ_CK(hipMemcpyAsync(w.A, w.dAn, sizeof(double) * d * n, hipMemcpyDeviceToDevice, s));
+        ADJ_CK(hipMemcpyAsync(w.om, w.omn, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
+        ADJ_CK(hipMemcpyAsync(w.Uprev, w.Ucur, sizeof(double) * n * d, hipMemcpyDeviceToDevice, s));
+        ADJ_CK(fetch_scal());
+        if (unsigned ke = take_err()) {
+            *msg = "kernel error " + std::to_string(ke) + " in an aligned step (a multiplet larger than 8, or "
+                   "subspaces that do not overlap)";
+            return CTMRG_E_NUMERICAL;
+        }
+        resid = w.hscal[S_GAUGE];
+        if (!std::isfinite(resid)) {
+            *msg = "non-finite state in an aligned step";
+            return CTMRG_E_NUMERICAL;
+        }
+        if (k >= 1 && resid < in.gauge_tol) break;
+    }
+    res->aligned_steps = k + 1;
+    res->gauge_residual = resid;
+    if (!(resid < in.gauge_tol)) {
+        *msg = "the aligned fixed point did not converge (|P_next - P| = " + std::to_string(resid) + ")";
+        return CTMRG_E_NOT_CONVERGED;
+    }
+
+    // ---- 2. at x*: all eigenpairs of C'*, the kept block aligned with the last step
+    ADJ_CK(extension_products(w.A, w.om, w.OA, w.X, q, d, s));
+    ADJ_CK(weight_mix(in.W, w.X, w.C, q, d, s));
+    ADJ_CK(eig_values(w.eig, w.C, n, n, s));
+    ADJ_CK(eig_post(w.eig, n, n, in.gap_tol, in.rank_tol, w.zero, w.omn, w.sel, w.post, s));
+    ADJ_CK(fetch_post());
+    const PostOut pa = *w.hpost;
+    const int np = pa.m_eff;  // eigenpairs above the rank threshold, all multiplets whole
+    if (np < d) {
+        *msg = "the spectrum of C' at the fixed point has fewer than d resolvable eigenpairs";
+        return CTMRG_E_NUMERICAL;
+    }
+    const double nC = pa.n_C;
+    ADJ_CK(eig_vectors(w.eig, nullptr, 0, n, np, w.sel, pa.nclusters, w.Uall, n, s));
+    ADJ_CK(hipMemcpyAsync(w.lam, w.sel, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+    ADJ_CK(copy2d(w.Uall, n, w.Ucur, d, n, d, s));
+    ADJ_CK(align_to(w, w.Ucur, d, w.lam, in.gap_tol, s));
+    ADJ_CK(copy2d(w.Ucur, d, w.Uall, n, n, d, s));
+    // M3 = U diag(lambda^3) U^T = C'^3 (on the resolved spectrum)
+    ADJ_CK(hipMemsetAsync(w.dX, 0, sizeof(double) * (size_t)n * n, s));
+    hipLaunchKernelGGL(scale_cols_cube_kernel, dim3(grid_for((long)n * np)), dim3(256), 0, s, w.Uall, (long)n, n, np,
+                       w.lam, w.dX);
+    ADJ_CK(gemm_mfma(GEMM_LARGE, A_RM{w.dX, n}, B_T{w.Uall, n}, EpiStore{w.M3, n, 1.0}, n, n, np, s));
+    // P~*, its norm s*, and the K-derivative parts of C' and Z (dW/dK = -WH)
+    ADJ_CK(halfrow_products(w.A, w.Ucur, w.Y, q, d, s));
+    ADJ_CK(weight_mix(in.W, w.Y, w.Z, q, d, s));
+    ADJ_CK(projection(w.Ucur, w.Z, w.Pt, q, d, s));
+    ADJ_CK(reduce_dot(w.Pt, w.Pt, (long)d * n, w.part, w.scal + S_NORM, OP_SQRT, 1.0, s));
+    ADJ_CK(gemm_mfma(GEMM_MIX, A_T{in.WH, q2}, B_Mix{w.X, q, d, n}, EpiMix_<double, true>{w.Cb, q, d, n, -1.0}, q2,
+                     d * d, q2, s));
+    ADJ_CK(gemm_mfma(GEMM_MIX, A_T{in.WH, q2}, B_Mix{w.Y, q, d, n}, EpiMix_<double, true>{w.Zb, q, d, n, -1.0}, q2,
+                     d * d, q2, s));
+    ADJ_CK(fetch_scal());
+    if (unsigned ke = take_err()) {
+        *msg = "kernel error " + std::to_string(ke) + " at the fixed point";
+        return CTMRG_E_NUMERICAL;
+    }
+    const double sstar = w.hscal[S_NORM];
+    res->F = -0.5 * log(sstar);
+    res->n_eigen = np;
+
+    // ---- 3. tangent iteration t <- J t + d_K Phi (dK = 1)
+    const long nd = (long)d * n;
+    ADJ_CK(hipMemsetAsync(w.dA, 0, sizeof(double) * nd, s));
+    ADJ_CK(hipMemsetAsync(w.dom, 0, sizeof(double) * d * d, s));
+    double change = INFINITY, ds = 0.0, ds_prev[2] = {NAN, NAN};
+    bool functional_converged = false;
+    int it = 0;
+    for (it = 0; it < in.max_iterations; ++it) {
+        // dOA = dOmega A + Omega dA (dOmega: the full symmetric corner tangent)
+        hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(nd)), dim3(256), 0, s, w.om, w.dA, d, (long)n, w.dOA);
+        ADJ_CK(gemm_mfma(GEMM_SMALL, A_RM{w.dom, d}, B_RM{w.A, n}, EpiAxpby{w.dOA, n, 1.0, 1.0}, d, n, d, s));
+        // dX = dA^T (Omega A) + A^T (dOmega A + Omega dA)
+        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.dA, n}, B_RM{w.OA, n}, EpiStore{w.dX, n, 1.0}, n, n, d, s));
+        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.A, n}, B_RM{w.dOA, n}, EpiAxpby{w.dX, n, 1.0, 1.0}, n, n, d, s));
+        // dC' = W-mix(dX) + W'-mix(X*)
+        ADJ_CK(weight_mix(in.W, w.dX, w.dC, q, d, s));
+        hipLaunchKernelGGL(axpy_kernel, dim3(grid_for((long)n * n)), dim3(256), 0, s, w.dC, w.Cb, (long)n * n);
+        // eigenvector and eigenvalue derivatives
+        ADJ_CK(gemm_mfma(GEMM_TALL, A_RM{w.dC, n}, B_RM{w.Ucur, d}, EpiStore{w.T1, d, 1.0}, n, d, n, s));
+        ADJ_CK(gemm_mfma(GEMM_TALL, A_T{w.Uall, n}, B_RM{w.T1, d}, EpiStore{w.Bm, d, 1.0}, np, d, n, s));
+        if (np < n) {
+            ADJ_CK(copy2d(w.T1, d, w.R, d, n, d, s));
+            ADJ_CK(gemm_mfma(GEMM_TALL, A_RM{w.Uall, n}, B_RM{w.Bm, d}, EpiAxpby{w.R, d, -1.0, 1.0}, n, d, np, s));
+        }
+        ADJ_CK(reduce_dot(w.M3, w.dC, (long)n * n, w.part, w.scal + S_DNC, OP_SUM, 1.0 / (nC * nC * nC), s));
+        hipLaunchKernelGGL(eigen_tangent_kernel, dim3(grid_for((long)np * d)), dim3(256), 0, s, w.Bm, np, d, w.lam,
+                           nC, w.scal + S_DNC, w.domn);
+        ADJ_CK(gemm_mfma(GEMM_TALL, A_RM{w.Uall, n}, B_RM{w.Bm, d}, EpiStore{w.dU, d, 1.0}, n, d, np, s));
+        if (np < n)
+            hipLaunchKernelGGL(nullspace_tangent_kernel, dim3(grid_for((long)n * d)), dim3(256), 0, s, w.dU, w.R,
+                               (long)n, d, w.lam);
+        // dY = dA^T U + A^T dU,  dZ = W-mix(dY) + W'-mix(Y*),  dP~ = dU^T Z* + U^T dZ
+        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.dA, n}, B_Ublk{w.Ucur, d}, EpiStore{w.dY, n, 1.0}, n, n, d, s));
+        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.A, n}, B_Ublk{w.dU, d}, EpiAxpby{w.dY, n, 1.0, 1.0}, n, n, d, s));
+        ADJ_CK(weight_mix(in.W, w.dY, w.dZ, q, d, s));
+        hipLaunchKernelGGL(axpy_kernel, dim3(grid_for((long)n * n)), dim3(256), 0, s, w.dZ, w.Zb, (long)n * n);
+        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.dU, d}, B_RM{w.Z, n}, EpiStore{w.dPt, n, 1.0}, d, n, n, s));
+        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.Ucur, d}, B_RM{w.dZ, n}, EpiAxpby{w.dPt, n, 1.0, 1.0}, d, n, n, s));
+        // normalization by the Frobenius norm
+        ADJ_CK(reduce_dot(w.Pt, w.dPt, nd, w.part, w.scal + S_DS, OP_SUM, 1.0 / sstar, s));
+        hipLaunchKernelGGL(tangent_norm_kernel, dim3(grid_for(nd)), dim3(256), 0, s, w.dPt, w.Pt, nd,
+                           w.scal + S_NORM, w.scal + S_DS, w.dAn);
+        ADJ_CK(reduce_maxdiff(w.dAn, w.dA, nd, w.part, w.scal + S_CHANGE, false, s));
+        ADJ_CK(reduce_maxdiff(w.domn, w.dom, (long)d * d, w.part, w.scal + S_CHANGE, true, s));
+        std::swap(w.dA, w.dAn);
+        std::swap(w.dom, w.domn);
+        if (it % 10 == 9 || it + 1 == in.max_iterations) {
+            ADJ_CK(fetch_scal());
+            change = w.hscal[S_CHANGE];
+            ds = w.hscal[S_DS];
+            if (!std::isfinite(change) || !std::isfinite(ds)) {
+                *msg = "non-finite tangent";
+                return CTMRG_E_NUMERICAL;
+            }
+            if (change < in.tangent_tol) break;
+            // Directions of the tangent that converge slowly without moving s: stop once ds itself
+            // has settled over two consecutive windows of ten iterations.
+            const double tol_ds = 1e-14 * fabs(ds);
+            if (it >= 99 && fabs(ds - ds_prev[0]) <= tol_ds && fabs(ds_prev[0] - ds_prev[1]) <= tol_ds) {
+                functional_converged = true;
+                break;
+            }
+            ds_prev[1] = ds_prev[0];
+            ds_prev[0] = ds;
+        }
+    }
+    res->iterations = it + 1;
+    res->tangent_change = change;
+    res->dFdK = -0.5 * ds / sstar;
+    if (!(change < in.tangent_tol) && !functional_converged) {
+        *msg = "the tangent iteration did not converge (change " + std::to_string(change) + ")";
+        return CTMRG_E_NOT_CONVERGED;
+    }
+    return CTMRG_OK;
+#undef ADJ_CK
+}
+
+}  // namespace ctm

@@ -49,6 +49,7 @@ enum {
     KERR_BARRIER_TIMEOUT = 1,
     KERR_NONFINITE = 4,
     KERR_NO_CONVERGENCE = 8,
+    KERR_ALIGN = 16,
 };
 CTMRG_DEVINL void raise_error(unsigned *err, unsigned code)
 {

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "common.h"
 #include "contract.h"
 #include "ctmrg.h"
@@ -36,6 +37,9 @@ struct ctmrg_ctx {
     PostOut *dPost = nullptr;
     PostOut *hPost = nullptr;
     EigWork eig;
+    // fixed-point derivative: its workspace and the weight at K +- dK
+    AdjWork adj;
+    double *dWd = nullptr, *dWHd = nullptr;
     // host-side status
     int m_eff = 1;
     int steps = 0;
@@ -108,6 +112,9 @@ void free_all(ctmrg_ctx *c)
     if (c->dPost) (void)hipFree(c->dPost);
     if (c->hPost) (void)hipHostFree(c->hPost);
     eig_free(c->eig);
+    adj_free(c->adj);
+    if (c->dWd) (void)hipFree(c->dWd);
+    if (c->dWHd) (void)hipFree(c->dWHd);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     for (int i = 0; i < MK_COUNT; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -418,9 +425,78 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *c, ctmrg_observables_t *out, double *k
     return CTMRG_OK;
 }
 
-ctmrg_status ctmrg_backward(ctmrg_ctx *c, const double *, double *, double *)
+namespace {
+
+ctmrg_status derivative_at(ctmrg_ctx *c, const double *W, const double *WH, AdjResult *r)
 {
-    return fail(c, CTMRG_E_UNSUPPORTED, "the fixed-point adjoint is not part of this build");
+    AdjInputs in;
+    in.q = c->q;
+    in.m = c->m;
+    in.d = c->m_eff;
+    in.W = W;
+    in.WH = WH;
+    in.A = c->dA;
+    in.omega = c->dOmega;
+    in.U = c->dU;
+    in.gap_tol = c->opt.gap_tol;
+    in.rank_tol = c->opt.rank_tol;
+    c->adj.band = c->opt.band;
+    std::string msg;
+    const int st = adjoint_dFdK(c->adj, in, r, c->stream, &msg);
+    if (st != CTMRG_OK) return fail(c, (ctmrg_status)st, "fixed-point derivative: " + msg);
+    return CTMRG_OK;
+}
+
+}  // namespace
+
+ctmrg_status ctmrg_fixed_point_derivative(ctmrg_ctx *c, int second_order, ctmrg_derivative_t *out)
+{
+    if (!c || !out) return CTMRG_E_INVALID_ARG;
+    if (c->steps < 2 || !c->have_U || !(c->delta < 1e-6))
+        return fail(c, CTMRG_E_STATE, "the state is not converged (Delta >= 1e-6 or fewer than two steps)");
+    AdjResult r;
+    ctmrg_status st = derivative_at(c, c->dW, c->dWH, &r);
+    if (st != CTMRG_OK) return st;
+    *out = ctmrg_derivative_t{};
+    out->F = r.F;
+    out->dF_dK = r.dFdK;
+    out->gauge_residual = r.gauge_residual;
+    out->tangent_change = r.tangent_change;
+    out->aligned_steps = r.aligned_steps;
+    out->iterations = r.iterations;
+    out->n_eigen = r.n_eigen;
+    if (second_order) {
+        const size_t q4 = (size_t)c->q * c->q * c->q * c->q;
+        if (!c->dWd) HIPCHK(c, hipMalloc((void **)&c->dWd, sizeof(double) * q4));
+        if (!c->dWHd) HIPCHK(c, hipMalloc((void **)&c->dWHd, sizeof(double) * q4));
+        const double h = 1e-4 * c->K;
+        double dF[2];
+        for (int side = 0; side < 2; ++side) {
+            const double Ks = c->K + (side == 0 ? h : -h);
+            HIPCHK(c, build_weight(c->dV, c->q, c->dim, Ks, c->dWd, c->dWHd, c->stream));
+            AdjResult rs;
+            st = derivative_at(c, c->dWd, c->dWHd, &rs);
+            if (st != CTMRG_OK) return st;
+            dF[side] = rs.dFdK;
+        }
+        out->d2F_dK2 = (dF[0] - dF[1]) / (2.0 * h);
+    }
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_backward(ctmrg_ctx *c, const double *obs_bar, double *K_bar, double *d2F_dK2)
+{
+    if (!c || !obs_bar || !K_bar) return CTMRG_E_INVALID_ARG;
+    if (obs_bar[2] != 0.0) return fail(c, CTMRG_E_UNSUPPORTED, "the derivative of M is not available");
+    const int second = (obs_bar[1] != 0.0 || d2F_dK2 != nullptr) ? 1 : 0;
+    ctmrg_derivative_t d;
+    ctmrg_status st = ctmrg_fixed_point_derivative(c, second, &d);
+    if (st != CTMRG_OK) return st;
+    const double K = c->K;
+    const double dfdK = d.dF_dK / K - d.F / (K * K);  // f = F / K
+    *K_bar = obs_bar[0] * dfdK + (second ? obs_bar[1] * d.d2F_dK2 : 0.0);
+    if (d2F_dK2) *d2F_dK2 = d.d2F_dK2;
+    return CTMRG_OK;
 }
 
 ctmrg_status ctmrg_export_state(ctmrg_ctx *c, void *host_buf, size_t *bytes)

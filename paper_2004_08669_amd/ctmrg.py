@@ -64,6 +64,19 @@ class Observables(ctypes.Structure):
     ]
 
 
+class Derivative(ctypes.Structure):
+    _fields_ = [
+        ("F", ctypes.c_double),
+        ("dF_dK", ctypes.c_double),
+        ("d2F_dK2", ctypes.c_double),
+        ("gauge_residual", ctypes.c_double),
+        ("tangent_change", ctypes.c_double),
+        ("aligned_steps", ctypes.c_int),
+        ("iterations", ctypes.c_int),
+        ("n_eigen", ctypes.c_int),
+    ]
+
+
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -91,6 +104,7 @@ def load():
                                      ctypes.c_int),
         "ctmrg_observables": ([_vp, ctypes.POINTER(Observables), _dp], ctypes.c_int),
         "ctmrg_backward": ([_vp, _dp, _dp, _dp], ctypes.c_int),
+        "ctmrg_fixed_point_derivative": ([_vp, ctypes.c_int, ctypes.POINTER(Derivative)], ctypes.c_int),
         "ctmrg_export_state": ([_vp, _vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ctmrg_import_state": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
         "ctmrg_set_state": ([_vp, ctypes.c_int, _dp, _dp], ctypes.c_int),
@@ -218,12 +232,20 @@ class CTMRG:
         out["kept_spectrum"] = spec
         return out
 
-    def backward(self, obs_bar):
+    def fixed_point_derivative(self, second_order: bool = False) -> dict:
+        """dF/dK (and d2F/dK2) of F = beta f at the converged fixed point (see include/ctmrg.h)."""
+        d = Derivative()
+        self._check(self._lib.ctmrg_fixed_point_derivative(self._h, 1 if second_order else 0, ctypes.byref(d)))
+        return {name: getattr(d, name) for name, _ in Derivative._fields_}
+
+    def backward(self, obs_bar, want_d2: bool = False):
+        """K_bar = obs_bar . d(f, E, M)/dK (obs_bar[2] must be 0); also d2F/dK2 when requested."""
         ob = _f64(obs_bar)
         kb = ctypes.c_double(0.0)
         d2 = ctypes.c_double(0.0)
-        self._check(self._lib.ctmrg_backward(self._h, _p(ob), ctypes.byref(kb), ctypes.byref(d2)))
-        return kb.value, d2.value
+        self._check(self._lib.ctmrg_backward(self._h, _p(ob), ctypes.byref(kb),
+                                             ctypes.byref(d2) if want_d2 else None))
+        return kb.value, (d2.value if want_d2 else None)
 
     def export_state(self) -> bytes:
         n = ctypes.c_size_t(0)

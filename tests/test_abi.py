@@ -18,7 +18,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ["ctmrg_init", "ctmrg_step", "ctmrg_run_to_fixed_point", "ctmrg_observables",
                      "ctmrg_backward", "ctmrg_export_state", "ctmrg_import_state", "ctmrg_destroy",
-                     "ctmrg_last_error", "ctmrg_workspace_size", "ctmrg_eigh_topk"]:
+                     "ctmrg_last_error", "ctmrg_workspace_size", "ctmrg_eigh_topk",
+                     "ctmrg_fixed_point_derivative"]:
         assert required in names
 
 
@@ -72,3 +73,16 @@ def test_precision_option_is_validated_without_a_gpu_call():
     V = np.array([[1.0], [-1.0]])
     h = ctypes.c_void_p()
     assert lib.ctmrg_init(2, 1, ctmrg._p(V), 1.0, 4, ctypes.byref(o), ctypes.byref(h)) == 1
+
+
+def test_derivative_entry_points_reject_bad_arguments_without_a_gpu_call():
+    from paper_2004_08669_amd import ctmrg
+    if not os.path.exists(ctmrg.LIB_PATH):
+        pytest.skip("libctmrg.so not built")
+    lib = ctmrg.load()
+    d = ctmrg.Derivative()
+    assert lib.ctmrg_fixed_point_derivative(None, 0, ctypes.byref(d)) == 1
+    import numpy as np
+    ob = np.zeros(3)
+    kb = ctypes.c_double(0.0)
+    assert lib.ctmrg_backward(None, ctmrg._p(ob), ctypes.byref(kb), None) == 1

@@ -1,0 +1,151 @@
+"""The fixed-point derivative (tangent-mode implicit differentiation, FP64) through the C ABI.
+
+References that do not come from the GPU path:
+  * q = 2: dF/dK is the energy per site, Onsager's closed form; d2F/dK2 is its K-derivative
+    (tests/exact.py differentiates the closed form);
+  * q = 20: the oracle's central difference [F(K+h) - F(K-h)] / 2h of its own fixed points
+    (h = 1e-4, each converged to Delta < 1e-13: accurate to about 1e-8), the oracle's impurity
+    energy at the same m (equal to dF/dK at an exact fixed point), and the central difference
+    of that energy for d2F/dK2 (accurate to about 1e-7).
+"""
+import numpy as np
+import pytest
+
+import ctmrg_inputs as I
+import exact as E
+from oracle import ctmrg_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_08669_amd import ctmrg
+    ctmrg.load()
+    return ctmrg
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _converged(ct, V, K, m, tol=1e-13, max_steps=3000):
+    g = ct.CTMRG(V, K, m)
+    ks, d, conv = g.run_to_fixed_point(tol, max_steps)
+    assert conv, (ks, d)
+    return g
+
+
+@pytest.mark.parametrize("T,m", [(2.0, 16), (1.5, 12), (2.5, 16)])
+def test_derivative_ising_onsager(T, m):
+    ct = _lib()
+    K = 1.0 / T
+    say(f"[derivative ising] T={T} m={m}")
+    g = _converged(ct, I.ising(), K, m)
+    r = g.fixed_point_derivative(second_order=True)
+    g.close()
+    say(f"  {r}")
+    assert abs(r["F"] + E.ising_minus_beta_f(K)) <= 1e-10 * E.ising_minus_beta_f(K)
+    assert abs(r["dF_dK"] - E.ising_energy(K)) <= 1e-8
+    d2 = E.ising_d2F_dK2(K)
+    assert abs(r["d2F_dK2"] - d2) <= 1e-5 * abs(d2)
+
+
+def _oracle_fixed_point(V, K, m, tol=1e-13, max_steps=5000, start=None):
+    o = O.OracleCTMRG(V, K, m)
+    if start is not None:
+        o.import_state(start.P, start.omega, k=1)
+    for i in range(max_steps):
+        o.step()
+        if i >= 2 and o.delta < tol:
+            break
+        if i % 50 == 49:
+            say(f"  oracle K={K:.8f} step {i + 1} delta {o.delta:.2e}")
+    assert o.delta < tol
+    return o
+
+
+def test_derivative_dodecahedron_m12():
+    ct = _lib()
+    V = I.dodecahedron()
+    T, m = 0.40, 12
+    K = 1.0 / T
+    say(f"[derivative dodecahedron] T={T} m={m}")
+    g = _converged(ct, V, K, m)
+    obs = g.observables()
+    r = g.fixed_point_derivative(second_order=True)
+    g.close()
+    say(f"  {r}")
+    o = _oracle_fixed_point(V, K, m)
+    oo = o.observables()
+    h = 1e-4
+    op = _oracle_fixed_point(V, K + h, m, start=o).observables()
+    om = _oracle_fixed_point(V, K - h, m, start=o).observables()
+    fd = -(op["minus_beta_f"] - om["minus_beta_f"]) / (2 * h)
+    d2 = (op["E"] - om["E"]) / (2 * h)
+    F0 = -oo["minus_beta_f"]
+    say(f"  dF/dK {r['dF_dK']:.13f}  oracle FD {fd:.13f}  oracle E_imp {oo['E']:.13f}  gpu E_imp {obs['E']:.13f}")
+    say(f"  d2F/dK2 {r['d2F_dK2']:.9f}  oracle central difference of E_imp {d2:.9f}")
+    assert abs(r["F"] - F0) <= 1e-11 * abs(F0)
+    assert abs(r["dF_dK"] - fd) <= 1e-7
+    assert abs(r["dF_dK"] - oo["E"]) <= 1e-9
+    assert abs(r["dF_dK"] - obs["E"]) <= 1e-9
+    assert abs(r["d2F_dK2"] - d2) <= 1e-5 * abs(d2)
+
+
+def test_backward_combines_the_derivatives():
+    ct = _lib()
+    V = I.dodecahedron()
+    K = 1.0 / 0.40
+    say("[backward] q=20 m=8 T=0.40")
+    g = _converged(ct, V, K, 8)
+    r = g.fixed_point_derivative(second_order=True)
+    kb, d2 = g.backward([1.0, 0.0, 0.0], want_d2=True)
+    # f = F / K
+    assert abs(kb - (r["dF_dK"] / K - r["F"] / K ** 2)) <= 1e-12 * abs(kb)
+    assert abs(d2 - r["d2F_dK2"]) <= 1e-9 * abs(d2)
+    kb2, _ = g.backward([0.0, 2.0, 0.0])
+    assert abs(kb2 - 2.0 * r["d2F_dK2"]) <= 1e-9 * abs(kb2)
+    with pytest.raises(ct.CTMRGError) as e:
+        g.backward([0.0, 0.0, 1.0])
+    assert e.value.status == 7
+    g.close()
+    # before convergence
+    g = ct.CTMRG(V, K, 8)
+    g.step(1)
+    with pytest.raises(ct.CTMRGError) as e:
+        g.fixed_point_derivative()
+    assert e.value.status == 6
+    g.close()
+
+
+def test_derivative_m128_equals_impurity_energy():
+    """At m = 128 (C' 2560 x 2560, the size of the temperature sweep with derivatives): the
+    derivative of F equals the energy of the impurity plaquette on the same fixed point."""
+    ct = _lib()
+    V = I.dodecahedron()
+    K = 1.0 / 0.40
+    say("[derivative m=128] T=0.40")
+    g = _converged(ct, V, K, 128, tol=1e-12, max_steps=2000)
+    obs = g.observables()
+    r = g.fixed_point_derivative()
+    g.close()
+    say(f"  {r}; E_imp {obs['E']:.13f}")
+    assert abs(r["dF_dK"] - obs["E"]) <= 1e-8
+
+
+def test_autograd_function():
+    """K.grad of f through torch.autograd equals df/dK = (E - f)/K at the fixed point."""
+    torch = pytest.importorskip("torch")
+    ct = _lib()
+    from paper_2004_08669_amd.autograd import CTMRGFixedPoint
+    V = I.dodecahedron()
+    say("[autograd] q=20 m=8 T=0.40")
+    K = torch.tensor(1.0 / 0.40, dtype=torch.float64, requires_grad=True)
+    f, Eo, M = CTMRGFixedPoint.apply(K, V, 8)
+    f.backward()
+    ref = (Eo.item() - f.item()) / K.item()
+    say(f"  f {f.item():.12f} E {Eo.item():.12f} K.grad {K.grad.item():.12f} (E - f)/K {ref:.12f}")
+    assert abs(K.grad.item() - ref) <= 1e-9

@@ -167,6 +167,16 @@ def test_ising_energy_is_dF_dK():
     assert abs(-(fp - fm) / (2 * h) - e) < 1e-7
 
 
+def test_ising_second_difference_of_F_is_the_closed_form():
+    """d2(beta f)/dK2 by the second difference of the oracle's free energy (the reference the
+    GPU derivative tests use at q = 20) against the K-derivative of Onsager's energy."""
+    K, H = 0.5, 1e-3
+    F = [-O.run_fixed_point(I.ising(), K + t * H, 16, tol=1e-14)[1]["minus_beta_f"] for t in (-1, 0, 1)]
+    d2 = (F[0] - 2 * F[1] + F[2]) / (H * H)
+    ref = E.ising_d2F_dK2(K)
+    assert abs(d2 - ref) <= 1e-4 * abs(ref)
+
+
 def test_cube_is_three_ising_copies():
     T = 0.6
     K = 1.0 / T
