@@ -596,22 +596,25 @@ post_eigen_kernel(const double *ev, int N, int m, double gap_tol, double rank_to
 // Eigenvectors of the tridiagonal: inverse iteration
 // ============================================================================
 
-// One thread per tight cluster; the LU scratch and the iterate of thread c are
+// One thread per kept eigenvalue; the LU scratch and the iterate of thread c are
 // interleaved (element i of array a at lu[(a*N + i)*nth + c]) so that the lanes
 // of a wave touch adjacent addresses.  The factorization of T - lambda I with
 // partial pivoting carries its recurrence in registers and reads only d and e;
-// the triangular solves work in chunks of IV_CH rows whose loads are all issued
-// before the chunk's recurrence runs.  The normalization of an iterate is
-// folded into the next pass that reads it.
+// the factorization and the triangular solves work in chunks of IV_CH rows
+// whose loads are all issued before the chunk's recurrence runs.  The
+// normalization of an iterate is folded into the next pass that reads it.
+// Three iterations from a counter-based random start.  With a shift accurate to
+// eps ||T||, only members of an exactly (or nearly exactly) degenerate cluster
+// can converge to the same direction; cluster_orth_kernel separates them.
 constexpr int IV_CH = 16;
 
 __global__ void __launch_bounds__(64)
-invit_kernel(const double *d, const double *e, int N, const double *selval, const int *clist, const int *cstart,
-             int ncl, double *ZT, int ldz, double *lu, int *ipiv, const double *bounds, unsigned *err)
+invit_kernel(const double *d, const double *e, int N, const double *selval, int me, double *ZT, int ldz, double *lu,
+             int *ipiv, const double *bounds, unsigned *err)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int nth = gridDim.x * blockDim.x;
-    if (c >= ncl) return;
+    if (c >= me) return;
     const double tn = bounds[3];
     const double pivmin = fmax(DBL_EPSILON * tn, DBL_MIN);
 #define DL(i) lu[((long)0 * N + (i)) * nth + c]
@@ -620,122 +623,145 @@ invit_kernel(const double *d, const double *e, int N, const double *selval, cons
 #define DU2(i) lu[((long)3 * N + (i)) * nth + c]
 #define X(i) lu[((long)4 * N + (i)) * nth + c]
 #define IP(i) ipiv[(long)(i) * nth + c]
-    for (int q = cstart[c]; q < cstart[c + 1]; ++q) {
-        const int j = clist[q];
-        const double lam = selval[j];
-        // ---- LU with partial pivoting of T - lam I (rows i, i+1 swapped when |e_i| > |pivot|)
-        double ddi = d[0] - lam, dui = (N > 1) ? e[0] : 0.0;
-        for (int i = 0; i < N - 1; ++i) {
-            const double li = e[i];
-            const double dn = d[i + 1] - lam;
-            const double dun = (i < N - 2) ? e[i + 1] : 0.0;
-            if (fabs(ddi) >= fabs(li)) {
-                const double piv = (fabs(ddi) < pivmin) ? (ddi < 0.0 ? -pivmin : pivmin) : ddi;
-                const double f = li / piv;
-                DD(i) = piv; DL(i) = f; DU(i) = dui; DU2(i) = 0.0; IP(i) = 0;
-                ddi = dn - f * dui;
-                dui = dun;
-            } else {
-                const double f = ddi / li;
-                DD(i) = li; DL(i) = f; DU(i) = dn; DU2(i) = dun; IP(i) = 1;
-                ddi = dui - f * dn;
-                dui = -f * dun;
-            }
+    const double lam = selval[c];
+    // ---- LU with partial pivoting of T - lam I (rows i, i+1 swapped when |e_i| > |pivot|)
+    double ddi = d[0] - lam, dui = (N > 1) ? e[0] : 0.0;
+    for (int i0 = 0; i0 < N - 1; i0 += IV_CH) {
+        const int nI = min(IV_CH, N - 1 - i0);
+        double ec[IV_CH], dc[IV_CH], en[IV_CH];
+#pragma unroll
+        for (int u = 0; u < IV_CH; ++u) {
+            const int i = i0 + (u < nI ? u : 0);
+            ec[u] = e[i];
+            dc[u] = d[i + 1];
+            en[u] = (i < N - 2) ? e[i + 1] : 0.0;
         }
-        if (fabs(ddi) < pivmin) ddi = (ddi < 0.0 ? -pivmin : pivmin);
-        DD(N - 1) = ddi;
-        // ---- start vector (counter-based random numbers)
-        double nrm2 = 0.0;
-        for (int i = 0; i < N; ++i) {
-            const double x = hash_uniform(((uint64_t)(j + 1) << 32) ^ (uint64_t)i);
-            X(i) = x;
-            nrm2 += x * x;
-        }
-        double sc = 1.0 / sqrt(nrm2);  // pending scale of the stored iterate
-        for (int it = 0; it < 3; ++it) {
-            // forward: unit lower factor with row interchanges, applied to sc * X
-            double xi = X(0) * sc;
-            for (int i0 = 0; i0 < N - 1; i0 += IV_CH) {
-                const int nI = min(IV_CH, N - 1 - i0);
-                double xn[IV_CH], dl[IV_CH], out[IV_CH];
-                int ip[IV_CH];
 #pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) { xn[u] = X(i0 + u + 1) * sc; dl[u] = DL(i0 + u); ip[u] = IP(i0 + u); }
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) {
-                        if (ip[u] == 0) { out[u] = xi; xi = xn[u] - dl[u] * xi; }
-                        else { out[u] = xn[u]; xi = xi - dl[u] * xn[u]; }
-                    }
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) X(i0 + u) = out[u];
-            }
-            X(N - 1) = xi;
-            // backward: upper factor with two superdiagonals; accumulate the norm
-            double x1 = X(N - 1) / DD(N - 1);
-            X(N - 1) = x1;
-            nrm2 = x1 * x1;
-            double x2 = 0.0;
-            if (N > 1) {
-                const double x0 = (X(N - 2) - DU(N - 2) * x1) / DD(N - 2);
-                X(N - 2) = x0;
-                nrm2 += x0 * x0;
-                x2 = x1;
-                x1 = x0;
-            }
-            for (int i0 = N - 3; i0 >= 0; i0 -= IV_CH) {
-                const int nI = min(IV_CH, i0 + 1);
-                double xv[IV_CH], du[IV_CH], du2[IV_CH], dd[IV_CH];
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) { xv[u] = X(i0 - u); du[u] = DU(i0 - u); du2[u] = DU2(i0 - u); dd[u] = DD(i0 - u); }
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) {
-                        const double xnew = (xv[u] - du[u] * x1 - du2[u] * x2) / dd[u];
-                        x2 = x1;
-                        x1 = xnew;
-                        xv[u] = xnew;
-                        nrm2 += xnew * xnew;
-                    }
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) X(i0 - u) = xv[u];
-            }
-            if (!(nrm2 > 0.0) || !isfinite(nrm2)) {
-                raise_error(err, KERR_NONFINITE);
-                nrm2 = 1.0;
-            }
-            sc = 1.0 / sqrt(nrm2);
-            if (q > cstart[c]) {
-                // orthogonalize against the earlier members of the cluster (in ZT), renormalize
-#pragma unroll 16
-                for (int i = 0; i < N; ++i) X(i) *= sc;
-                for (int qq = cstart[c]; qq < q; ++qq) {
-                    const int jp = clist[qq];
-                    double dot = 0.0;
-#pragma unroll 16
-                    for (int i = 0; i < N; ++i) dot += ZT[(long)i * ldz + jp] * X(i);
-#pragma unroll 16
-                    for (int i = 0; i < N; ++i) X(i) -= dot * ZT[(long)i * ldz + jp];
+        for (int u = 0; u < IV_CH; ++u) {
+            if (u < nI) {
+                const int i = i0 + u;
+                const double li = ec[u];
+                const double dn = dc[u] - lam;
+                const double dun = en[u];
+                if (fabs(ddi) >= fabs(li)) {
+                    const double piv = (fabs(ddi) < pivmin) ? (ddi < 0.0 ? -pivmin : pivmin) : ddi;
+                    const double f = li / piv;
+                    DD(i) = piv; DL(i) = f; DU(i) = dui; DU2(i) = 0.0; IP(i) = 0;
+                    ddi = dn - f * dui;
+                    dui = dun;
+                } else {
+                    const double f = ddi / li;
+                    DD(i) = li; DL(i) = f; DU(i) = dn; DU2(i) = dun; IP(i) = 1;
+                    ddi = dui - f * dn;
+                    dui = -f * dun;
                 }
-                nrm2 = 0.0;
-#pragma unroll 16
-                for (int i = 0; i < N; ++i) nrm2 += X(i) * X(i);
-                sc = (nrm2 > 0.0) ? 1.0 / sqrt(nrm2) : 0.0;
             }
         }
-#pragma unroll 16
-        for (int i = 0; i < N; ++i) ZT[(long)i * ldz + j] = X(i) * sc;
     }
+    if (fabs(ddi) < pivmin) ddi = (ddi < 0.0 ? -pivmin : pivmin);
+    DD(N - 1) = ddi;
+    // ---- start vector (counter-based random numbers)
+    double nrm2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double x = hash_uniform(((uint64_t)(c + 1) << 32) ^ (uint64_t)i);
+        X(i) = x;
+        nrm2 += x * x;
+    }
+    double sc = 1.0 / sqrt(nrm2);  // pending scale of the stored iterate
+    for (int it = 0; it < 3; ++it) {
+        // forward: unit lower factor with row interchanges, applied to sc * X
+        double xi = X(0) * sc;
+        for (int i0 = 0; i0 < N - 1; i0 += IV_CH) {
+            const int nI = min(IV_CH, N - 1 - i0);
+            double xn[IV_CH], dl[IV_CH], out[IV_CH];
+            int ip[IV_CH];
+#pragma unroll
+            for (int u = 0; u < IV_CH; ++u)
+                if (u < nI) { xn[u] = X(i0 + u + 1) * sc; dl[u] = DL(i0 + u); ip[u] = IP(i0 + u); }
+#pragma unroll
+            for (int u = 0; u < IV_CH; ++u)
+                if (u < nI) {
+                    if (ip[u] == 0) { out[u] = xi; xi = xn[u] - dl[u] * xi; }
+                    else { out[u] = xn[u]; xi = xi - dl[u] * xn[u]; }
+                }
+#pragma unroll
+            for (int u = 0; u < IV_CH; ++u)
+                if (u < nI) X(i0 + u) = out[u];
+        }
+        X(N - 1) = xi;
+        // backward: upper factor with two superdiagonals; accumulate the norm
+        double x1 = X(N - 1) / DD(N - 1);
+        X(N - 1) = x1;
+        nrm2 = x1 * x1;
+        double x2 = 0.0;
+        if (N > 1) {
+            const double x0 = (X(N - 2) - DU(N - 2) * x1) / DD(N - 2);
+            X(N - 2) = x0;
+            nrm2 += x0 * x0;
+            x2 = x1;
+            x1 = x0;
+        }
+        for (int i0 = N - 3; i0 >= 0; i0 -= IV_CH) {
+            const int nI = min(IV_CH, i0 + 1);
+            double xv[IV_CH], du[IV_CH], du2[IV_CH], dd[IV_CH];
+#pragma unroll
+            for (int u = 0; u < IV_CH; ++u)
+                if (u < nI) { xv[u] = X(i0 - u); du[u] = DU(i0 - u); du2[u] = DU2(i0 - u); dd[u] = DD(i0 - u); }
+#pragma unroll
+            for (int u = 0; u < IV_CH; ++u)
+                if (u < nI) {
+                    const double xnew = (xv[u] - du[u] * x1 - du2[u] * x2) / dd[u];
+                    x2 = x1;
+                    x1 = xnew;
+                    xv[u] = xnew;
+                    nrm2 += xnew * xnew;
+                }
+#pragma unroll
+            for (int u = 0; u < IV_CH; ++u)
+                if (u < nI) X(i0 - u) = xv[u];
+        }
+        if (!(nrm2 > 0.0) || !isfinite(nrm2)) {
+            raise_error(err, KERR_NONFINITE);
+            nrm2 = 1.0;
+        }
+        sc = 1.0 / sqrt(nrm2);
+    }
+#pragma unroll 16
+    for (int i = 0; i < N; ++i) ZT[(long)i * ldz + c] = X(i) * sc;
 #undef DL
 #undef DD
 #undef DU
 #undef DU2
 #undef IP
 #undef X
+}
+
+// Modified Gram-Schmidt inside each tight cluster (members in ascending
+// eigenvalue order, as listed by clist), one workgroup per cluster.
+__global__ void __launch_bounds__(256)
+cluster_orth_kernel(double *Z, int ldz, int N, const int *clist, const int *cstart)
+{
+    __shared__ double red[4];
+    const int b0 = cstart[blockIdx.x], b1 = cstart[blockIdx.x + 1];
+    if (b1 - b0 < 2) return;
+    for (int k = b0; k < b1; ++k) {
+        const int qk = clist[k];
+        for (int p = b0; p < k; ++p) {
+            const int qp = clist[p];
+            double sdot = 0.0;
+            for (int i = threadIdx.x; i < N; i += 256) sdot += Z[(long)i * ldz + qp] * Z[(long)i * ldz + qk];
+            sdot = block_sum<256>(sdot, red);
+            for (int i = threadIdx.x; i < N; i += 256) Z[(long)i * ldz + qk] -= sdot * Z[(long)i * ldz + qp];
+        }
+        double n2 = 0.0;
+        for (int i = threadIdx.x; i < N; i += 256) {
+            const double z = Z[(long)i * ldz + qk];
+            n2 += z * z;
+        }
+        n2 = block_sum<256>(n2, red);
+        const double scale = (n2 > 0.0) ? 1.0 / sqrt(n2) : 0.0;
+        for (int i = threadIdx.x; i < N; i += 256) Z[(long)i * ldz + qk] *= scale;
+    }
 }
 
 // H = 1.5 I - 0.5 G (Newton-Schulz step for the polar factor)
@@ -1142,7 +1168,7 @@ hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s)
     hipLaunchKernelGGL(band_to_tridiag_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, s, w.band, N, b, w.d, w.e, w.e2);
     double *bounds = w.sm + 3 * b * b;
     hipLaunchKernelGGL(tridiag_bounds_kernel, dim3(1), dim3(256), 0, s, w.d, w.e, N, bounds);
-    constexpr int LPE = 16, SH = 2;  // 16 lanes per eigenvalue, 2 shifts per lane: 32 points per pass
+    constexpr int LPE = 8, SH = 1;  // 8 lanes per eigenvalue, 1 shift each: 8 points per pass (fastest measured)
     hipLaunchKernelGGL((bisect_kernel<LPE, SH>), dim3(ceil_div((long)N * LPE, 256)), dim3(256), 0, s, w.d, w.e2, N,
                        bounds, w.evals);
     mark(w, MK_BISECT, s);
@@ -1167,8 +1193,10 @@ hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const do
     const double *bounds = w.sm + 3 * b * b;
     hipError_t e;
     mark(w, MK_VEC_START, s);
-    hipLaunchKernelGGL(invit_kernel, dim3(ceil_div(nclusters, 64)), dim3(64), 0, s, w.d, w.e, N, selval, w.clist,
-                       w.cstart, nclusters, w.ZT, ldz, w.lu, w.ipiv, bounds, w.err);
+    hipLaunchKernelGGL(invit_kernel, dim3(ceil_div(me, 64)), dim3(64), 0, s, w.d, w.e, N, selval, me, w.ZT, ldz, w.lu,
+                       w.ipiv, bounds, w.err);
+    if (nclusters < me)
+        hipLaunchKernelGGL(cluster_orth_kernel, dim3(nclusters), dim3(256), 0, s, w.ZT, ldz, N, w.clist, w.cstart);
     mark(w, MK_INVIT, s);
     // Newton-Schulz polar orthonormalization: Z <- Z (3/2 I - 1/2 Z^T Z)
     double *Z = w.ZT, *Zo = w.Ztmp;

@@ -193,17 +193,59 @@ def test_dodecahedron_free_boundary_m8_symmetric_phase():
 
 
 def test_dodecahedron_free_boundary_m8_500_steps():
-    """The same configuration run for 500 steps.  The symmetric state loses stability after
-    ~60 steps and the symmetry breaks along a direction picked by rounding: in the oracle alone a
-    1e-14 relative change of K moves f by 4e-7 (relative 2e-7), E by 1e-4 and S_E by 1e-2 at step
-    500, and Delta is still ~1e-5.  The comparison is therefore bounded by that measured
-    sensitivity, not by the FP64 parity tolerance."""
-    say("[fixed point] dodecahedron m=8 T=0.5 free, 500 steps")
-    og, oo = _run_both(I.dodecahedron(), 2.0, 8, "free", 500)
+    """The same configuration over 500 steps.  The symmetric state loses stability after ~60
+    steps and the symmetry breaks along a direction picked by rounding, so two correct codes end
+    on different branches (measured: a 1e-14 relative change of K in the oracle alone moves S_E by
+    1e-2 at step 500).  The GPU is therefore compared with the oracle along the oracle's own
+    trajectory: at steps 100, 200, 300, 400 and 498 it takes the oracle's state and makes two
+    steps, and f, E, |M|, S_E, m_eff and the kept spectrum must match two oracle steps from the
+    same state.  The GPU's own 500-step run is checked for a valid end state."""
+    ct = _lib()
+    V, K, m = I.dodecahedron(), 2.0, 8
+    say("[free boundary, 500 steps] dodecahedron m=8 T=0.5, shadowing the oracle")
+    o = O.OracleCTMRG(V, K, m, bc="free")
+    checks = {100, 200, 300, 400, 498}
+    worst = {"f": 0.0, "E": 0.0, "M": 0.0, "S": 0.0, "w": 0.0}
+    for k in range(1, 501):
+        o.step()
+        if k not in checks:
+            continue
+        P, om = o.P.copy(), o.omega.copy()
+        ref = O.OracleCTMRG(V, K, m, bc="free")
+        ref.import_state(P, om, k=k)
+        ref.step()
+        ref.step()
+        oo = ref.observables()
+        g = ct.CTMRG(V, K, m, bc="free")
+        g.set_state(P, om)
+        g.step(2)
+        og = g.observables()
+        g.close()
+        assert og["m_eff"] == oo["m_eff"], (k, og["m_eff"], oo["m_eff"])
+        me = oo["m_eff"]
+        dw = float(np.abs(og["kept_spectrum"][:me] - ref.omega[:me]).max())
+        worst["f"] = max(worst["f"], abs(og["f"] - oo["f"]) / abs(oo["f"]))
+        worst["E"] = max(worst["E"], abs(og["E"] - oo["E"]))
+        worst["M"] = max(worst["M"], abs(abs(og["M"]) - abs(oo["M"])))
+        worst["S"] = max(worst["S"], abs(og["S_E"] - oo["S_E"]))
+        worst["w"] = max(worst["w"], dw)
+        say(f"  step {k}: m_eff {me} f {oo['f']:.12f} |M| {abs(oo['M']):.6f} S_E {oo['S_E']:.6f}  worst so far {worst}")
+    assert worst["f"] <= 1e-10
+    assert worst["E"] <= 1e-8
+    assert worst["M"] <= 1e-7
+    assert worst["S"] <= 1e-9
+    assert worst["w"] <= 1e-10
+    # the GPU's own 500 steps end on some branch: a valid state of the same model
+    g = ct.CTMRG(V, K, m, bc="free")
+    g.step(500)
+    og = g.observables()
+    g.close()
+    oo = o.observables()
+    say(f"  500 steps: gpu f {og['f']:.10f} |M| {abs(og['M']):.4f} S_E {og['S_E']:.4f}; "
+        f"oracle f {oo['f']:.10f} |M| {abs(oo['M']):.4f} S_E {oo['S_E']:.4f}")
     assert og["m_eff"] == oo["m_eff"]
-    assert abs(og["f"] - oo["f"]) <= 5e-6 * abs(oo["f"])
-    assert abs(og["E"] - oo["E"]) <= 2e-3
-    assert abs(abs(og["M"]) - abs(oo["M"])) <= 5e-2
+    assert abs(og["f"] - oo["f"]) <= 1e-2 * abs(oo["f"])
+    assert 0.0 <= abs(og["M"]) <= 1.0 and 0.0 <= og["S_E"] <= np.log(20 * m)
 
 
 @pytest.mark.parametrize("T,tol", [(0.40, 1e-12), (0.48, 1e-11)])
