@@ -62,12 +62,16 @@ CTMRG_DEVINL void raise_error(unsigned *err, unsigned code)
 // Grid-wide barrier for a launch whose workgroups are all resident (cooperative
 // launch).  bar[0] counts arrivals, bar[1] is the generation.  `gen` is the
 // generation this workgroup read at kernel start; it is advanced on each call.
-// Every thread's stores complete before the workgroup arrives; one thread per
-// workgroup performs the agent-scope release before arriving and the acquire
-// after the wait, so plain loads after the barrier see every workgroup's
-// stores made before it.  Polling uses relaxed loads (an acquire load in the
-// loop would invalidate the cache on every iteration).  Returns false (and
-// raises KERR_BARRIER_TIMEOUT) if the wait hit the spin limit.
+// Every thread's memory operations complete before the workgroup arrives.
+// With FENCED, one thread per workgroup performs the agent-scope release before
+// arriving and the acquire after the wait, so plain loads after the barrier see
+// every workgroup's plain stores made before it.  Without it no cache is written
+// back or invalidated: only data exchanged through the device-coherent accesses
+// above (st_coh / ld_coh) is ordered by the barrier, which leaves the caches of
+// concurrently running kernels alone.  Polling uses relaxed loads (an acquire
+// load in the loop would invalidate the cache on every iteration).  Returns
+// false (and raises KERR_BARRIER_TIMEOUT) if the wait hit the spin limit.
+template <bool FENCED = true>
 CTMRG_DEVINL bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, unsigned *err)
 {
     __shared__ int ok_shared;
@@ -75,7 +79,7 @@ CTMRG_DEVINL bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, u
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        fence_release_agent();
+        if (FENCED) fence_release_agent();
         unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == nblocks - 1) {
             stu_coh(&bar[0], 0u);
@@ -92,7 +96,7 @@ CTMRG_DEVINL bool grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, u
                 }
             }
         }
-        fence_acquire_agent();
+        if (FENCED) fence_acquire_agent();
         ok_shared = ok;
     }
     gen += 1u;

@@ -38,7 +38,10 @@ __host__ __device__ inline int bulge_nsteps(int N, int b, int j) { return 1 + (N
 static int max_steps(int N, int b) { return N > 2 ? bulge_nsteps(N, b, 0) : 0; }
 
 // ============================================================================
-// Stage 1: Householder QR of one panel (cooperative; one grid barrier per column)
+// Stage 1: Householder QR of one panel (cooperative; one grid barrier per column;
+// the workgroups exchange their partial sums through device-coherent accesses, so
+// the barriers do no cache maintenance that would disturb the trailing update
+// running beside the panel)
 // ============================================================================
 
 // Rows per workgroup: the panel slice of a workgroup is 4096 doubles (32 KB).
@@ -87,10 +90,10 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
         if (tid < b) {
             double t = 0.0;
             for (int k = 0; k < RG; ++k) t += red[k * b + tid];
-            part[((long)buf * G + g) * b + tid] = t;
-            if (i >= row0 && i < row0 + nloc) rowbuf[buf * b + tid] = pan[(i - row0) * b + tid];
+            st_coh(&part[((long)buf * G + g) * b + tid], t);
+            if (i >= row0 && i < row0 + nloc) st_coh(&rowbuf[buf * b + tid], pan[(i - row0) * b + tid]);
         }
-        grid_barrier(bar, G, gen, err);
+        grid_barrier<false>(bar, G, gen, err);
         {
             // partial sums of the G workgroups: row group rg adds workgroups rg, rg+RG, ...
             double t = 0.0;
@@ -98,14 +101,14 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
             for (; k + 7 * RG < G; k += 8 * RG) {
                 double x[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = part[((long)buf * G + k + u * RG) * b + cl];
+                for (int u = 0; u < 8; ++u) x[u] = ld_coh(&part[((long)buf * G + k + u * RG) * b + cl]);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) t += x[u];
             }
-            for (; k < G; k += RG) t += part[((long)buf * G + k) * b + cl];
+            for (; k < G; k += RG) t += ld_coh(&part[((long)buf * G + k) * b + cl]);
             red[rg * b + cl] = t;
         }
-        if (tid < b) wv[tid] = rowbuf[buf * b + tid];
+        if (tid < b) wv[tid] = ld_coh(&rowbuf[buf * b + tid]);
         __syncthreads();
         if (tid < b) {
             double t = 0.0;
@@ -164,9 +167,9 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
             const double v2 = (gr == c2) ? 1.0 : (gr > c2 ? pan[r * b + c2] : 0.0);
             s += v1 * v2;
         }
-        gpart[(long)g * b * b + idx] = s;
+        st_coh(&gpart[(long)g * b * b + idx], s);
     }
-    grid_barrier(bar, G, gen, err);
+    grid_barrier<false>(bar, G, gen, err);
     if (g != 0) return;
     for (int idx = tid; idx < b * b; idx += 256) {
         double s = 0.0;
@@ -174,11 +177,11 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, do
         for (; k + 8 <= G; k += 8) {
             double x[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = gpart[(long)(k + u) * b * b + idx];
+            for (int u = 0; u < 8; ++u) x[u] = ld_coh(&gpart[(long)(k + u) * b * b + idx]);
 #pragma unroll
             for (int u = 0; u < 8; ++u) s += x[u];
         }
-        for (; k < G; ++k) s += gpart[(long)k * b * b + idx];
+        for (; k < G; ++k) s += ld_coh(&gpart[(long)k * b * b + idx]);
         gram[idx] = s;
         Tm[idx] = 0.0;
     }
@@ -455,7 +458,12 @@ __global__ void __launch_bounds__(256) bisect_kernel(const double *d, const doub
                     for (int v = 0; v < S; ++v) {
                         double qq = q[v];
                         if (fabs(qq) < pivmin) qq = -pivmin;
-                        qq = dv[u] - x[v] - ev[u] / qq;
+                        // e2 / q by the hardware reciprocal and one Newton step (an ulp or two:
+                        // a relative perturbation of e2 of that size, far inside the count's
+                        // backward error)
+                        double r = __builtin_amdgcn_rcp(qq);
+                        r = fma(r, fma(-qq, r, 1.0), r);
+                        qq = dv[u] - x[v] - ev[u] * r;
                         cnt[v] += qq < 0.0 ? 1 : 0;
                         q[v] = qq;
                     }
