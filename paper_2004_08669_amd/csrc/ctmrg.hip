@@ -154,7 +154,7 @@ ctmrg_status reset_state(ctmrg_ctx *c)
 ctmrg_status check_kernel_errors(ctmrg_ctx *c)
 {
     unsigned e = eig_take_errors(c->eig);
-    if (e & KERR_BARRIER_TIMEOUT)
+    if (e & KERR_WAIT_TIMEOUT)
         return fail(c, CTMRG_E_NUMERICAL, "a bounded kernel wait hit its spin limit (code " + std::to_string(e) + ")");
     if (e & KERR_NONFINITE) return fail(c, CTMRG_E_NUMERICAL, "inverse iteration produced a non-finite vector");
     return CTMRG_OK;

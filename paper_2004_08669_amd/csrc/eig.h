@@ -3,8 +3,9 @@
 // the m largest in magnitude.
 //
 //   stage 1  dense -> band (half-bandwidth b): blocked Householder QR of each
-//            b-column panel below the band (one cooperative kernel per panel,
-//            one grid barrier per column) and a two-sided compact-WY update of
+//            b-column panel below the band (one cooperative kernel per panel;
+//            its workgroups exchange per-column partial sums through device-
+//            coherent slots) and a two-sided compact-WY update of
 //            the trailing matrix with GEMMs on the matrix cores; the matrix is
 //            held in its lower triangle (products with it read the lower
 //            triangle twice, once transposed; the update writes only tiles on
@@ -36,7 +37,9 @@ struct EigWork {
     double *Y = nullptr;       // n x b
     double *X = nullptr;       // n x b
     double *sm = nullptr;      // 4 * b * b
-    double *part = nullptr;    // cooperative partial sums
+    double *part = nullptr;    // panel QR: exchange slots (two sets)
+    unsigned long pqr_launches = 0;  // panel QR launches so far (the parity picks the slot set)
+    int pqr_gprev = 0;         // workgroups of the previous panel QR launch
     double *splitk = nullptr;  // split-K partials
     size_t splitk_elems = 0;
     // stage 2
@@ -54,7 +57,6 @@ struct EigWork {
     int *ipiv = nullptr;       // N kmax
     int *clist = nullptr;      // kmax: kept indices in ascending-eigenvalue order
     int *cstart = nullptr;     // kmax + 1 cluster offsets
-    unsigned *bar = nullptr;   // grid barrier words (2)
     unsigned *err = nullptr;   // kernel error flags
     hipEvent_t *marks = nullptr;  // optional stage-boundary events (see MarkId)
     // look-ahead: the next panel's QR runs on s2 while the trailing update runs on the caller's stream

@@ -38,167 +38,219 @@ __host__ __device__ inline int bulge_nsteps(int N, int b, int j) { return 1 + (N
 static int max_steps(int N, int b) { return N > 2 ? bulge_nsteps(N, b, 0) : 0; }
 
 // ============================================================================
-// Stage 1: Householder QR of one panel (cooperative; one grid barrier per column;
-// the workgroups exchange their partial sums through device-coherent accesses, so
-// the barriers do no cache maintenance that would disturb the trailing update
-// running beside the panel)
+// Stage 1: Householder QR of one panel (cooperative).  Each workgroup holds a
+// slice of 4096 / B rows in registers, 16 elements per thread.  Per column, every
+// workgroup stores its partial products of that column with all columns into
+// exchange slots with device-coherent stores, and reads the slots of all the
+// others, waiting until none holds the empty marker any more.  There is no
+// barrier and no flag: one store and one load separate the columns, and no
+// cache is written back or invalidated, so the trailing update running beside
+// the panel keeps its caches.  The products with the finished columns give
+// V^T v of the compact-WY factor T along the way.
+//
+// Exchange slots: two sets (launch parity), each [B columns][Gmax workgroups][B]
+// partials followed by [B columns][B] copies of panel row i.  A launch fills the
+// set of its parity and first returns the other set (filled by the previous
+// launch, over its Gprev workgroups) to the marker, so every launch starts on
+// an empty set.  Launches on one workspace run one after another.
 // ============================================================================
 
-// Rows per workgroup: the panel slice of a workgroup is 4096 doubles (32 KB).
 static inline int pqr_rows(int b) { return 4096 / b; }
-static inline size_t pqr_smem(int b) { return sizeof(double) * (4096 + 256 + 8 + 3 * b + 2 * b * b); }
+static inline int pqr_gmax(int Nmax, int b) { return (Nmax + pqr_rows(b) - 1) / pqr_rows(b); }
+__host__ __device__ inline size_t pqr_slot_set(int b, int Gmax) { return (size_t)b * Gmax * b + (size_t)b * b; }
 
-__global__ void __launch_bounds__(256)
-panel_qr_kernel(double *A, long lda, int r0, int p, int n, int b, double *Vx, double *tau_out, double *T_out,
-                double *part, unsigned *bar, unsigned *err)
+// The empty marker: all bits set (a NaN that arithmetic never produces; computed
+// NaNs are stored as the default quiet NaN).
+#define PQR_EMPTY (-1LL)
+
+CTMRG_DEVINL bool pqr_empty(double v) { return __double_as_longlong(v) == PQR_EMPTY; }
+CTMRG_DEVINL double pqr_publishable(double v) { return v == v ? v : __longlong_as_double(0x7FF8000000000000LL); }
+
+// Value of column i in the caller's row: lanes are grouped B to a row, lane c of a
+// group holds column c.
+template <int B>
+CTMRG_DEVINL double col_bcast(double v, int i, int lane)
 {
-    extern __shared__ double sm[];
-    const int rows = 4096 / b;
-    const int RG = 256 / b;  // row groups; column lane = tid % b
-    double *pan = sm;                 // [rows][b]
-    double *red = pan + 4096;         // [RG][b] = 256
-    double *bc = red + 256;           // 8 scalars
-    double *wv = bc + 8;              // [b]  w_c
-    double *sv = wv + b;              // [b]  S_c
-    double *tl = sv + b;              // [b]  taus
-    double *gram = tl + b;            // [b][b]
-    double *Tm = gram + b * b;        // [b][b]
+    if constexpr (B == 32) {
+        const int lo = __double2loint(v), hi = __double2hiint(v);
+        const int l0 = __builtin_amdgcn_readlane(lo, i), h0 = __builtin_amdgcn_readlane(hi, i);
+        const int l1 = __builtin_amdgcn_readlane(lo, i + 32), h1 = __builtin_amdgcn_readlane(hi, i + 32);
+        return (lane & 32) ? __hiloint2double(h1, l1) : __hiloint2double(h0, l0);
+    } else {
+        return __shfl(v, (lane & ~(B - 1)) + i, 64);
+    }
+}
+
+// Panel columns [p, p + B) of A, rows [r0, r0 + n).  On return the panel holds R on
+// and above its diagonal and the Householder vectors below it (unit diagonal
+// implied); Vx (n x B, row-major) holds V explicitly, tau_out the B scalars and
+// T_out the upper-triangular B x B factor with Q = I - V T V^T.
+template <int B>
+__global__ void __launch_bounds__(256)
+panel_qr_kernel(double *A, long lda, int r0, int p, int n, double *Vx, double *tau_out, double *T_out,
+                double *slots, int Gmax, int parity, int Gprev, unsigned *err)
+{
+    constexpr int RG = 256 / B;    // row groups
+    constexpr int KR = 16;         // rows per thread: local rows rg + RG k
+    constexpr int ROWS = RG * KR;  // 4096 / B
+    __shared__ double red[4][B];
+    __shared__ double rowl[B];
+    __shared__ double red2[RG][B];
+    __shared__ double gram[B][B + 1];
+    __shared__ double tl[B];
 
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
-    const int row0 = g * rows;
-    const int nloc = min(rows, n - row0);
-    unsigned gen = ldu_coh(&bar[1]);
-    double *rowbuf = part + 2L * G * b;          // [2][b]
-    double *gpart = rowbuf + 2L * b;             // [G][b*b]
+    const int lane = tid & 63, wave = tid >> 6;
+    const int c = tid & (B - 1), rg = tid / B;
+    const int row0 = g * ROWS;
+    const int nloc = min(ROWS, n - row0);
+    const long set = (long)pqr_slot_set(B, Gmax);
+    double *part = slots + parity * set;       // [B][Gmax][B]
+    double *rowv = part + (long)B * Gmax * B;  // [B][B]
 
-    for (int idx = tid; idx < rows * b; idx += 256) {
-        const int r = idx / b, c = idx - (idx / b) * b;
-        pan[idx] = (r < nloc) ? A[(long)(r0 + row0 + r) * lda + p + c] : 0.0;
+    // the previous launch's set back to empty
+    {
+        double *old = slots + (parity ^ 1) * set;
+        const long used = (long)Gprev * B;
+        for (long idx = (long)g * 256 + tid; idx < (long)B * used; idx += (long)G * 256) {
+            const long ii = idx / used;
+            st_coh(&old[ii * Gmax * B + (idx - ii * used)], __longlong_as_double(PQR_EMPTY));
+        }
+        if (g == 0)
+            for (int idx = tid; idx < B * B; idx += 256)
+                st_coh(&old[(long)B * Gmax * B + idx], __longlong_as_double(PQR_EMPTY));
     }
-    __syncthreads();
 
-    const int cl = tid % b, rg = tid / b;
-    for (int i = 0; i < b; ++i) {
-        const int buf = i & 1;
-        double s = 0.0;
-        if (cl >= i) {
-            for (int r = rg; r < nloc; r += RG)
-                if (row0 + r > i) s += pan[r * b + i] * pan[r * b + cl];
+    double x[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int r = rg + RG * k;
+        x[k] = (r < nloc) ? A[(long)(r0 + row0 + r) * lda + p + c] : 0.0;
+    }
+
+    for (int i = 0; i < B; ++i) {
+        double *part_i = part + (long)i * Gmax * B;
+        double *rowv_i = rowv + i * B;
+        // column i in every row, and this thread's share of sum_{rows > i} a_ri a_rc
+        double y[KR];
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            y[k] = col_bcast<B>(x[k], i, lane);
+            if (row0 + rg + RG * k > i) t += y[k] * x[k];
         }
-        red[rg * b + cl] = s;
+#pragma unroll
+        for (int o = B; o < 64; o <<= 1) t += __shfl_xor(t, o, 64);
+        if (lane < B) red[wave][c] = t;
+        if (g == 0 && rg == i % RG) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < (B + RG - 1) / RG; ++k)
+                if (k == i / RG) v = x[k];
+            rowl[c] = v;
+        }
         __syncthreads();
-        if (tid < b) {
-            double t = 0.0;
-            for (int k = 0; k < RG; ++k) t += red[k * b + tid];
-            st_coh(&part[((long)buf * G + g) * b + tid], t);
-            if (i >= row0 && i < row0 + nloc) st_coh(&rowbuf[buf * b + tid], pan[(i - row0) * b + tid]);
+        // publish this workgroup's partials (and row i, from workgroup 0)
+        if (wave == 0 && lane < B) {
+            st_coh(&part_i[(long)g * B + c], pqr_publishable(red[0][c] + red[1][c] + red[2][c] + red[3][c]));
+            if (g == 0) st_coh(&rowv_i[c], pqr_publishable(rowl[c]));
         }
-        grid_barrier<false>(bar, G, gen, err);
+        // gather: row group rg adds workgroups rg, rg + RG, ... (the same order everywhere),
+        // reading again until no slot it needs is empty
+        double ts, arow, alpha;
         {
-            // partial sums of the G workgroups: row group rg adds workgroups rg, rg+RG, ...
-            double t = 0.0;
-            int k = rg;
-            for (; k + 7 * RG < G; k += 8 * RG) {
-                double x[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = ld_coh(&part[((long)buf * G + k + u * RG) * b + cl]);
-#pragma unroll
-                for (int u = 0; u < 8; ++u) t += x[u];
+            unsigned spins = 0;
+            for (;;) {
+                bool full = true;
+                ts = 0.0;
+                int gg = rg;
+                for (; gg + 3 * RG < G; gg += 4 * RG) {
+                    const double v0 = ld_coh(&part_i[(long)gg * B + c]);
+                    const double v1 = ld_coh(&part_i[(long)(gg + RG) * B + c]);
+                    const double v2 = ld_coh(&part_i[(long)(gg + 2 * RG) * B + c]);
+                    const double v3 = ld_coh(&part_i[(long)(gg + 3 * RG) * B + c]);
+                    full = full && !pqr_empty(v0) && !pqr_empty(v1) && !pqr_empty(v2) && !pqr_empty(v3);
+                    ts += (v0 + v1) + (v2 + v3);
+                }
+                for (; gg < G; gg += RG) {
+                    const double v = ld_coh(&part_i[(long)gg * B + c]);
+                    full = full && !pqr_empty(v);
+                    ts += v;
+                }
+                arow = ld_coh(&rowv_i[c]);
+                alpha = ld_coh(&rowv_i[i]);
+                full = full && !pqr_empty(arow) && !pqr_empty(alpha);
+                if (__all(full)) break;
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > CTMRG_SPIN_LIMIT) {
+                    if (lane == 0) raise_error(err, KERR_WAIT_TIMEOUT);
+                    break;
+                }
             }
-            for (; k < G; k += RG) t += ld_coh(&part[((long)buf * G + k) * b + cl]);
-            red[rg * b + cl] = t;
         }
-        if (tid < b) wv[tid] = ld_coh(&rowbuf[buf * b + tid]);
+        red2[rg][c] = ts;
         __syncthreads();
-        if (tid < b) {
-            double t = 0.0;
-            for (int k = 0; k < RG; ++k) t += red[k * b + tid];
-            sv[tid] = t;
+        double Sc = 0.0, Si = 0.0;
+#pragma unroll
+        for (int k = 0; k < RG; ++k) {
+            Sc += red2[k][c];
+            Si += red2[k][i];
         }
-        __syncthreads();
-        if (tid == 0) {
-            const double alpha = wv[i];
-            const double xn2 = sv[i];
-            double beta, tau, scale;
-            if (xn2 == 0.0) {
-                beta = alpha; tau = 0.0; scale = 0.0;
-            } else {
-                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
+        // reflector of column i (every thread of every workgroup computes the same values)
+        double beta, tau, scale;
+        if (Si == 0.0) {
+            beta = alpha; tau = 0.0; scale = 0.0;
+        } else {
+            beta = -copysign(sqrt(alpha * alpha + Si), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        const double wc = arow + scale * Sc;  // v_i^T a_c; for c < i this is (V^T V)[c][i]
+        if (g == 0) {
+            if (rg == 0 && c < i) gram[c][i] = wc;
+            if (tid == 0) tl[i] = tau;
+        }
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int gr = row0 + rg + RG * k;
+            if (c > i) {
+                if (gr >= i) x[k] -= tau * ((gr == i) ? 1.0 : y[k] * scale) * wc;
+            } else if (c == i) {
+                if (gr == i) x[k] = beta;
+                else if (gr > i) x[k] = y[k] * scale;
             }
-            bc[0] = beta; bc[1] = tau; bc[2] = scale;
-            tl[i] = tau;
         }
-        __syncthreads();
-        if (tid < b && tid > i) wv[tid] = wv[tid] + bc[2] * sv[tid];
-        __syncthreads();
-        const double beta = bc[0], tau_i = bc[1], scale = bc[2];
-        // columns right of i first (they read the old column i)
-        for (int idx = tid; idx < nloc * b; idx += 256) {
-            const int r = idx / b, c = idx - (idx / b) * b, gr = row0 + r;
-            if (gr < i || c <= i) continue;
-            const double v = (gr == i) ? 1.0 : pan[r * b + i] * scale;
-            pan[idx] -= tau_i * v * wv[c];
-        }
-        __syncthreads();
-        for (int r = tid; r < nloc; r += 256) {
-            const int gr = row0 + r;
-            if (gr < i) continue;
-            pan[r * b + i] = (gr == i) ? beta : pan[r * b + i] * scale;
-        }
-        __syncthreads();
     }
 
-    // write back R (on and above the diagonal) and V (below), and the explicit V
-    for (int idx = tid; idx < nloc * b; idx += 256) {
-        const int r = idx / b, c = idx - (idx / b) * b, gr = row0 + r;
-        const double val = pan[idx];
-        A[(long)(r0 + gr) * lda + p + c] = val;
-        Vx[(long)gr * b + c] = (gr == c) ? 1.0 : (gr > c ? val : 0.0);
-    }
-    // partial Gram matrix V^T V of this slice
-    for (int idx = tid; idx < b * b; idx += 256) {
-        const int c1 = idx / b, c2 = idx - (idx / b) * b;
-        double s = 0.0;
-        for (int r = 0; r < nloc; ++r) {
-            const int gr = row0 + r;
-            const double v1 = (gr == c1) ? 1.0 : (gr > c1 ? pan[r * b + c1] : 0.0);
-            const double v2 = (gr == c2) ? 1.0 : (gr > c2 ? pan[r * b + c2] : 0.0);
-            s += v1 * v2;
+    // R and V back to the panel, and the explicit V
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int r = rg + RG * k, gr = row0 + r;
+        if (r < nloc) {
+            A[(long)(r0 + gr) * lda + p + c] = x[k];
+            Vx[(long)gr * B + c] = (gr == c) ? 1.0 : (gr > c ? x[k] : 0.0);
         }
-        st_coh(&gpart[(long)g * b * b + idx], s);
     }
-    grid_barrier<false>(bar, G, gen, err);
     if (g != 0) return;
-    for (int idx = tid; idx < b * b; idx += 256) {
-        double s = 0.0;
-        int k = 0;
-        for (; k + 8 <= G; k += 8) {
-            double x[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = ld_coh(&gpart[(long)(k + u) * b * b + idx]);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += x[u];
-        }
-        for (; k < G; ++k) s += ld_coh(&gpart[(long)k * b * b + idx]);
-        gram[idx] = s;
-        Tm[idx] = 0.0;
-    }
     __syncthreads();
-    // T (upper triangular): T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] (V^T v_i)[0:i]
-    for (int i = 0; i < b; ++i) {
-        if (tid < i) {
+    // T (upper triangular), row j by thread j: T[j][j] = tau_j and, for i > j,
+    // T[j][i] = -tau_i sum_{l < i} T[j][l] (V^T V)[l][i]
+    if (tid < B) {
+        const int j = tid;
+        double trow[B];
+#pragma unroll
+        for (int l = 0; l < B; ++l) trow[l] = (l == j) ? tl[l] : 0.0;
+#pragma unroll
+        for (int ii = 1; ii < B; ++ii) {
             double s = 0.0;
-            for (int l = tid; l < i; ++l) s += Tm[tid * b + l] * gram[l * b + i];
-            Tm[tid * b + i] = -tl[i] * s;
-        } else if (tid == i) {
-            Tm[i * b + i] = tl[i];
+#pragma unroll
+            for (int l = 0; l < ii; ++l) s += trow[l] * gram[l][ii];
+            if (ii > j) trow[ii] = -tl[ii] * s;
         }
-        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < B; ++l) T_out[j * B + l] = trow[l];
+        tau_out[j] = tl[j];
     }
-    for (int idx = tid; idx < b * b; idx += 256) T_out[idx] = Tm[idx];
-    if (tid < b) tau_out[tid] = tl[tid];
 }
 
 // Epilogue that forms W = X - 1/2 V S and the two concatenated operands
@@ -947,7 +999,6 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     const int np = num_panels(Nmax, b);
     const int Tmax = max_steps(Nmax, b) + 1;
     const int nJ = (Nmax + b - 1) / b;
-    const int G = (Nmax + pqr_rows(b) - 1) / pqr_rows(b) + 1;
     size_t s = 0;
     s += align_up(sizeof(double) * (size_t)panel_v_offset(Nmax, b, np) + 8);
     s += align_up(sizeof(double) * (size_t)np * b * b + 8);
@@ -955,7 +1006,7 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += 2 * align_up(sizeof(double) * (size_t)Nmax * 2 * b);
     s += 2 * align_up(sizeof(double) * (size_t)Nmax * b);
     s += align_up(sizeof(double) * 4 * b * b);
-    s += align_up(sizeof(double) * ((size_t)G * (2 * b + b * b) + 2 * b + 64));
+    s += align_up(sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b)));
     s += align_up(sizeof(double) * (size_t)std::max<size_t>((size_t)64 * Nmax * std::max(b, 64), (size_t)64 * kmax * kmax + 64 * 64 * 64));
     s += align_up(sizeof(double) * (size_t)Nmax * 2 * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax * b);
@@ -968,7 +1019,7 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += align_up(sizeof(double) * 5 * (size_t)Nmax * kpad);
     s += align_up(sizeof(int) * (size_t)Nmax * kpad);
     s += 2 * align_up(sizeof(int) * (size_t)(kmax + 2));
-    s += align_up(sizeof(double) * 8) + 2 * align_up(64);
+    s += align_up(sizeof(double) * 8) + align_up(64);
     return s;
 }
 
@@ -980,7 +1031,6 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
     w.Tmax = max_steps(Nmax, b) + 1;
     w.nJmax = (Nmax + b - 1) / b;
     const int np = num_panels(Nmax, b);
-    const int G = (Nmax + pqr_rows(b) - 1) / pqr_rows(b) + 1;
     const size_t kpad = ((size_t)kmax + 63) / 64 * 64;  // threads of invit_kernel
     w.splitk_elems = std::max<size_t>((size_t)64 * Nmax * std::max(b, 64), (size_t)64 * kmax * kmax + 64 * 64 * 64);
     struct Req { void **p; size_t bytes; };
@@ -995,7 +1045,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.Y, sizeof(double) * (size_t)Nmax * b},
         {(void **)&w.X, sizeof(double) * (size_t)Nmax * b},
         {(void **)&w.sm, sizeof(double) * 4 * b * b},
-        {(void **)&w.part, sizeof(double) * ((size_t)G * (2 * b + b * b) + 2 * b + 64)},
+        {(void **)&w.part, sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b))},
         {(void **)&w.splitk, sizeof(double) * w.splitk_elems},
         {(void **)&w.band, sizeof(double) * (size_t)Nmax * 2 * b},
         {(void **)&w.refl, sizeof(double) * (size_t)Nmax * w.Tmax * b},
@@ -1012,7 +1062,6 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.ipiv, sizeof(int) * (size_t)Nmax * kpad},
         {(void **)&w.clist, sizeof(int) * (size_t)(kmax + 2) * 2},
         {(void **)&w.cstart, sizeof(int) * (size_t)(kmax + 2)},
-        {(void **)&w.bar, 64},
         {(void **)&w.err, 64},
     };
     for (auto &r : reqs) {
@@ -1022,7 +1071,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
             return e;
         }
     }
-    (void)hipMemset(w.bar, 0, 64);
+    (void)hipMemset(w.part, 0xFF, sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b)));  // all slots empty
     (void)hipMemset(w.err, 0, 64);
     hipError_t e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_cols, hipEventDisableTiming);
@@ -1038,7 +1087,7 @@ void eig_free(EigWork &w)
 {
     void *ptrs[] = {w.Vx, w.Tp, w.tau1, w.VW, w.WV, w.Y, w.X, w.sm, w.part, w.splitk, w.band, w.refl, w.rtau,
                     w.T2, w.d, w.e, w.e2, w.evals, w.ZT, w.Ztmp, w.G, w.lu, w.ipiv, w.clist,
-                    w.cstart, w.bar, w.err};
+                    w.cstart, w.err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w.ev_cols) (void)hipEventDestroy(w.ev_cols);
@@ -1076,8 +1125,16 @@ static hipError_t panel_qr(EigWork &w, double *A, long lda, int N, int pi, hipSt
     double *Tp = w.Tp + (long)pi * b * b;
     double *taup = w.tau1 + (long)pi * b;
     int G = (n + rows - 1) / rows;
-    void *args[] = {&A, &lda, (void *)&r0, (void *)&p, (void *)&n, (void *)&b, &Vp, &taup, &Tp, &w.part, &w.bar, &w.err};
-    return launch_coop((const void *)panel_qr_kernel, dim3(G), dim3(256), args, pqr_smem(b), s);
+    int Gmax = pqr_gmax(w.Nmax, b), parity = (int)(w.pqr_launches & 1), Gprev = w.pqr_gprev;
+    if (G > Gmax) return hipErrorInvalidValue;
+    void *args[] = {&A, &lda, (void *)&r0, (void *)&p, (void *)&n, &Vp, &taup, &Tp, &w.part, &Gmax, &parity, &Gprev, &w.err};
+    const void *fn = b == 32 ? (const void *)panel_qr_kernel<32> : (const void *)panel_qr_kernel<16>;
+    hipError_t e = launch_coop(fn, dim3(G), dim3(256), args, 0, s);
+    if (e == hipSuccess) {
+        ++w.pqr_launches;
+        w.pqr_gprev = G;
+    }
+    return e;
 }
 
 // Dense -> band.  Look-ahead: once the next panel's b columns have their
