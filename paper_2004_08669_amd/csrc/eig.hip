@@ -1153,15 +1153,28 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
         double *Vp = w.Vx + panel_v_offset(N, b, pi);
         double *Tp = w.Tp + (long)pi * b * b;
         double *A22 = A + (long)r0 * lda + r0;
-        // Y = A22 V, with A22 held in its lower triangle: Y = L V + (strictly lower)^T V
+        // Y = A22 V, with A22 held in its lower triangle: Y = L V + (strictly lower)^T V.
+        // The K range of each 128-row tile (a triangle's worth) is cut into equal
+        // chunks, so every workgroup streams the same number of slices.
         {
-            const long tiles = (long)ceil_div(n, 128) * ceil_div(b, 32);
-            const int sp = splits_for(tiles, n, 256);
-            e = gemm_mfma_splitk(A_Lo{A22, lda}, B_RM{Vp, b}, EpiStore{w.Y, b, 1.0}, n, b, n, sp, w.splitk, s, GEMM_TALL);
-            if (e != hipSuccess) return e;
-            e = gemm_mfma_splitk(A_SLoT{A22, lda}, B_RM{Vp, b}, EpiAxpby{w.Y, b, 1.0, 1.0}, n, b, n, sp, w.splitk, s,
-                                 GEMM_TALL);
-            if (e != hipSuccess) return e;
+            const int ch = n >= 4096 ? 512 : 256;
+            const int nt = ceil_div(n, 128);
+            int n1 = 0, n2 = 0;
+            for (int I = 0; I < nt; ++I) {
+                n1 += tile_items<A_LoItems>(I, 128, n, ch);
+                n2 += tile_items<A_SLoTItems>(I, 128, n, ch);
+            }
+            if ((size_t)(n1 + n2) * 128 * b > w.splitk_elems) return hipErrorInvalidValue;
+            double *p1 = w.splitk, *p2 = w.splitk + (long)n1 * 128 * b;
+            if (n1 > 0)
+                hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 32, 4, 1, A_LoItems, B_RM, EpiItems>), dim3(n1), dim3(256),
+                                   0, s, A_LoItems{{A22, lda}}, B_RM{Vp, b}, EpiItems{p1, b}, n, b, n, ch);
+            if (n2 > 0)
+                hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 32, 4, 1, A_SLoTItems, B_RM, EpiItems>), dim3(n2),
+                                   dim3(256), 0, s, A_SLoTItems{{A22, lda}}, B_RM{Vp, b}, EpiItems{p2, b}, n, b, n, ch);
+            hipLaunchKernelGGL((reduce_items_kernel<A_LoItems, A_SLoTItems>), dim3(ceil_div(128 * b, 256), nt),
+                               dim3(256), 0, s, p1, p2, n, b, n, ch, w.Y, (long)b);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         // X = Y T
         e = gemm_mfma(GEMM_TALL, A_RM{w.Y, b}, B_RM{Tp, b}, EpiStore{w.X, b, 1.0}, n, b, b, s);

@@ -86,6 +86,26 @@ struct A_SLoT {
     __device__ static void range(int m0, int, int &klo, int &) { klo = max(klo, m0 + 1); }
 };
 
+// Work items for a balanced split of the K range of those operands: the K range
+// [k_lo, k_hi) of row tile I (rows [bm I, bm I + bm)) is cut into chunks of ch,
+// and blockIdx.x enumerates the (tile, chunk) items tile by tile (kItems).
+struct A_LoItems : A_Lo {
+    static constexpr bool kItems = true;
+    __host__ __device__ static int k_lo(int, int) { return 0; }
+    __host__ __device__ static int k_hi(int I, int bm, int K) { return K < bm * (I + 1) ? K : bm * (I + 1); }
+};
+struct A_SLoTItems : A_SLoT {
+    static constexpr bool kItems = true;
+    __host__ __device__ static int k_lo(int I, int bm) { return bm * I + 1; }
+    __host__ __device__ static int k_hi(int, int, int K) { return K; }
+};
+template <class LA>
+__host__ __device__ inline int tile_items(int I, int bm, int K, int ch)
+{
+    const int lo = LA::k_lo(I, bm), hi = LA::k_hi(I, bm, K);
+    return hi > lo ? (hi - lo + ch - 1) / ch : 0;
+}
+
 using A_RM = A_RM_<double>;
 using A_T = A_T_<double>;
 using B_RM = B_RM_<double>;
@@ -119,6 +139,10 @@ struct EpiAxpbyLower {  // C = alpha * acc + beta * C on the tiles on or below t
         *c = alpha * v + beta * (*c);
     }
 };
+struct EpiItems {  // partial sums of work items (128-row tiles), reduced by reduce_items_kernel
+    double *p; long N;
+    __device__ void operator()(int i, int j, double v, int item) const { p[((long)item * 128 + (i & 127)) * N + j] = v; }
+};
 struct EpiPartial {  // split-K partial sums, reduced by reduce_partials
     double *p; long M, N;
     __device__ void operator()(int i, int j, double v, int split) const
@@ -130,6 +154,8 @@ struct EpiPartial {  // split-K partial sums, reduced by reduce_partials
 // ---------------------------------------------------------------- optional traits
 template <class T, class = void> struct has_krange : std::false_type {};
 template <class T> struct has_krange<T, std::void_t<decltype(T::kRange)>> : std::true_type {};
+template <class T, class = void> struct has_items : std::false_type {};
+template <class T> struct has_items<T, std::void_t<decltype(T::kItems)>> : std::true_type {};
 template <class T, class = void> struct lower_tiles : std::false_type {};
 template <class T> struct lower_tiles<T, std::void_t<decltype(T::kLowerTiles)>> : std::true_type {};
 
@@ -178,9 +204,25 @@ gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
         tile_m = I;
         tile_n = t - I * (I + 1) / 2;
     }
+    int split = blockIdx.z, kbeg, kend;
+    if constexpr (has_items<LA>::value) {
+        // blockIdx.x enumerates the work items; kchunk is the chunk length
+        int item = blockIdx.x, I = 0;
+        const int ntile = (M + BM - 1) / BM;
+        for (; I < ntile; ++I) {
+            const int cnt = tile_items<LA>(I, BM, K, kchunk);
+            if (item < cnt) break;
+            item -= cnt;
+        }
+        tile_m = I;
+        split = blockIdx.x;
+        kbeg = LA::k_lo(I, BM) + item * kchunk;
+        kend = min(LA::k_hi(I, BM, K), kbeg + kchunk);
+    } else {
+        kbeg = blockIdx.z * kchunk;
+        kend = min(K, kbeg + kchunk);
+    }
     const int m0 = tile_m * BM, n0 = tile_n * BN;
-    int kbeg = blockIdx.z * kchunk;
-    int kend = min(K, kbeg + kchunk);
     if constexpr (has_krange<LA>::value) LA::range(m0, BM, kbeg, kend);
 
     typename MF::acc_t acc[TM][TN];
@@ -263,7 +305,7 @@ gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + (wm * TM + i) * 16 + MF::row(lane, r);
                 const int col = n0 + (wn * TN + j) * 16 + (lane & 15);
-                if (row < M && col < N) epi(row, col, (double)acc[i][j][r], blockIdx.z);
+                if (row < M && col < N) epi(row, col, (double)acc[i][j][r], split);
             }
 }
 
@@ -279,6 +321,45 @@ __global__ void reduce_partials_kernel(const double *part, int splits, int M, in
         const int i = (int)(idx / N), j = (int)(idx - (long)i * N);
         epi(i, j, s, 0);
     }
+}
+
+// Y = sum of the work-item partials (EpiItems) of two operands: blockIdx.y is the
+// 128-row tile, each thread one output element; the items of the first operand,
+// then those of the second, are added in order.
+template <class LA1, class LA2>
+__global__ void __launch_bounds__(256)
+reduce_items_kernel(const double *p1, const double *p2, int M, int N, int K, int ch, double *Y, long ldy)
+{
+    __shared__ int sred[2][4];
+    const int I = blockIdx.y;
+    // first item of tile I in each list: sum of the item counts of the tiles before it
+    int a1 = 0, a2 = 0;
+    for (int t = threadIdx.x; t < I; t += blockDim.x) {
+        a1 += tile_items<LA1>(t, 128, K, ch);
+        a2 += tile_items<LA2>(t, 128, K, ch);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a1 += __shfl_xor(a1, off, 64);
+        a2 += __shfl_xor(a2, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sred[0][threadIdx.x >> 6] = a1;
+        sred[1][threadIdx.x >> 6] = a2;
+    }
+    __syncthreads();
+    const int f1 = sred[0][0] + sred[0][1] + sred[0][2] + sred[0][3];
+    const int f2 = sred[1][0] + sred[1][1] + sred[1][2] + sred[1][3];
+    const int c1 = tile_items<LA1>(I, 128, K, ch), c2 = tile_items<LA2>(I, 128, K, ch);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = idx / N, j = idx - r * N, i = I * 128 + r;
+    if (r >= 128 || i >= M) return;
+    const double *q1 = p1 + ((long)f1 * 128 + r) * N + j;
+    const double *q2 = p2 + ((long)f2 * 128 + r) * N + j;
+    const long step = 128L * N;
+    double s = 0.0;
+    for (int u = 0; u < c1; ++u) s += q1[u * step];
+    for (int u = 0; u < c2; ++u) s += q2[u * step];
+    Y[(long)i * ldy + j] = s;
 }
 
 // Tile configurations.
