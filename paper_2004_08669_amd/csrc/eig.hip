@@ -891,64 +891,86 @@ bt2_tfactor_kernel(const double *refl, const double *rtau, int N, int b, int Tma
     for (int idx = tid; idx < b * b; idx += 256) dst[idx] = Tm[idx];
 }
 
-constexpr int BT2_NC = 32;
+// Application of one group G(J,t) = I - V T V^T to 64 columns of Z on the
+// matrix cores.  V is 2b x b (banded: V[r][i] is nonzero for 0 <= r - i < b) and T
+// is b x b upper triangular; both sit in LDS.  Each wave owns 16 columns and keeps
+// them in registers through the three products W = V^T Z, W2 = T W, Z -= V W2:
+// the accumulator layout of v_mfma_f64_16x16x4_f64 (lane l, register j: row
+// l/16 + 4 j, column l%16) is the B-operand layout of k-step j, so W and W2 feed
+// the next product without leaving the registers, and Z, loaded as row
+// 4 s + l/16 in register s, takes the update of output tile R in registers 4 R + j.
+constexpr int BT2_NC = 64;
 
+template <int B>
 __global__ void __launch_bounds__(256)
-bt2_apply_kernel(double *Z, int ldz, int N, int ncols, int b, int Tmax, int nJ, int wave, const double *refl,
+bt2_apply_kernel(double *Z, int ldz, int N, int ncols, int Tmax, int nJ, int wave, const double *refl,
                  const double *T2)
 {
-    extern __shared__ double sh[];
-    double *V = sh;                    // [2b][b]
-    double *Tm = V + 2 * b * b;        // [b][b]
-    double *Zt = Tm + b * b;           // [2b][NC]
-    double *W = Zt + 2 * b * BT2_NC;   // [b][NC]
-    double *W2 = W + b * BT2_NC;       // [b][NC]
+    constexpr int KS = B / 2;   // k-steps over the 2B rows of a group; Z values per lane
+    constexpr int BT = B / 16;  // 16-row tiles of W
+    using MF = Mfma<double>;
+    __shared__ double V[2 * B][B + 1];
+    __shared__ double Tm[B][B + 1];
     const int J = blockIdx.x;
     const int t = wave - (nJ - 1 - J);
     if (t < 0 || t >= Tmax) return;
-    if (J * b >= N - 2 || t >= bulge_nsteps(N, b, J * b)) return;
-    const int col0 = blockIdx.y * BT2_NC;
-    const int ncol = min(BT2_NC, ncols - col0);
-    if (ncol <= 0) return;
-    const int base = J * b + 1 + t * b;
-    const int nrow = min(2 * b - 1, N - base);
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < 2 * b * b; idx += 256) {
-        const int i = idx / (2 * b), r = idx - (idx / (2 * b)) * (2 * b);
-        const int j = J * b + i;
+    if (J * B >= N - 2 || t >= bulge_nsteps(N, B, J * B)) return;
+    const int base = J * B + 1 + t * B;
+    const int nrow = min(2 * B - 1, N - base);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int idx = tid; idx < 2 * B * B; idx += 256) {
+        const int i = idx / (2 * B), r = idx - i * (2 * B);
+        const int j = J * B + i;
         double val = 0.0;
-        if (r < nrow && j < N - 2 && t < bulge_nsteps(N, b, j) && r - i >= 0 && r - i < b)
-            val = refl[((long)j * Tmax + t) * b + (r - i)];
-        V[r * b + i] = val;
+        if (r < nrow && j < N - 2 && t < bulge_nsteps(N, B, j) && r - i >= 0 && r - i < B)
+            val = refl[((long)j * Tmax + t) * B + (r - i)];
+        V[r][i] = val;
     }
-    const double *Ts = T2 + ((long)J * Tmax + t) * b * b;
-    for (int idx = tid; idx < b * b; idx += 256) Tm[idx] = Ts[idx];
-    for (int idx = tid; idx < 2 * b * BT2_NC; idx += 256) {
-        const int r = idx / BT2_NC, c = idx - (idx / BT2_NC) * BT2_NC;
-        Zt[idx] = (r < nrow && c < ncol) ? Z[(long)(base + r) * ldz + col0 + c] : 0.0;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < b * BT2_NC; idx += 256) {
-        const int i = idx / BT2_NC, c = idx - (idx / BT2_NC) * BT2_NC;
-        double s = 0.0;
-        for (int r = i; r < i + b && r < 2 * b; ++r) s += V[r * b + i] * Zt[r * BT2_NC + c];
-        W[idx] = s;
+    const double *Ts = T2 + ((long)J * Tmax + t) * B * B;
+    for (int idx = tid; idx < B * B; idx += 256) Tm[idx / B][idx % B] = Ts[idx];
+    const int col = blockIdx.y * BT2_NC + wv * 16 + (lane & 15);
+    const bool okc = col < ncols;
+    const int lr = lane >> 4, lc = lane & 15;
+    double z[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int r = 4 * s + lr;
+        z[s] = (okc && r < nrow) ? Z[(long)(base + r) * ldz + col] : 0.0;
     }
     __syncthreads();
-    for (int idx = tid; idx < b * BT2_NC; idx += 256) {
-        const int i = idx / BT2_NC, c = idx - (idx / BT2_NC) * BT2_NC;
-        double s = 0.0;
-        for (int k = i; k < b; ++k) s += Tm[i * b + k] * W[k * BT2_NC + c];
-        W2[idx] = s;
+    // W = V^T Z
+    MF::acc_t w[BT];
+#pragma unroll
+    for (int I = 0; I < BT; ++I) {
+        w[I] = MF::zero();
+#pragma unroll
+        for (int s = 0; s < KS; ++s) w[I] = MF::mma(V[4 * s + lr][16 * I + lc], z[s], w[I]);
     }
-    __syncthreads();
-    for (int idx = tid; idx < 2 * b * BT2_NC; idx += 256) {
-        const int r = idx / BT2_NC, c = idx - (idx / BT2_NC) * BT2_NC;
-        if (r >= nrow || c >= ncol) continue;
-        double s = 0.0;
-        const int ilo = max(0, r - b + 1), ihi = min(b - 1, r);
-        for (int i = ilo; i <= ihi; ++i) s += V[r * b + i] * W2[i * BT2_NC + c];
-        Z[(long)(base + r) * ldz + col0 + c] = Zt[idx] - s;
+    // W2 = T W (T upper triangular: blocks below the diagonal are zero)
+    MF::acc_t w2[BT];
+#pragma unroll
+    for (int I2 = 0; I2 < BT; ++I2) {
+        w2[I2] = MF::zero();
+#pragma unroll
+        for (int I = I2; I < BT; ++I)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) w2[I2] = MF::mma(Tm[16 * I2 + lc][16 * I + 4 * s4 + lr], w[I][s4], w2[I2]);
+    }
+    // Z -= V W2
+#pragma unroll
+    for (int R = 0; R < 2 * BT; ++R) {
+        MF::acc_t d = MF::zero();
+#pragma unroll
+        for (int I = 0; I < BT; ++I)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) d = MF::mma(V[16 * R + lc][16 * I + 4 * s4 + lr], w2[I][s4], d);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) z[4 * R + j] -= d[j];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int r = 4 * s + lr;
+        if (okc && r < nrow) Z[(long)(base + r) * ldz + col] = z[s];
     }
 }
 
@@ -1296,11 +1318,14 @@ hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const do
         const int Tmax = w.Tmax;
         hipLaunchKernelGGL(bt2_tfactor_kernel, dim3(nJ * Tmax), dim3(256), sizeof(double) * (4 * b * b + b), s, w.refl,
                            w.rtau, N, b, Tmax, nJ, w.T2);
-        const size_t smem = sizeof(double) * (3 * b * b + 4 * b * BT2_NC);
         const int nwave = nJ + Tmax - 1;
         for (int wv = 0; wv < nwave; ++wv) {
-            hipLaunchKernelGGL(bt2_apply_kernel, dim3(nJ, ceil_div(me, BT2_NC)), dim3(256), smem, s, Z, ldz, N, me, b,
-                               Tmax, nJ, wv, w.refl, w.T2);
+            if (b == 32)
+                hipLaunchKernelGGL(bt2_apply_kernel<32>, dim3(nJ, ceil_div(me, BT2_NC)), dim3(256), 0, s, Z, ldz, N, me,
+                                   Tmax, nJ, wv, w.refl, w.T2);
+            else
+                hipLaunchKernelGGL(bt2_apply_kernel<16>, dim3(nJ, ceil_div(me, BT2_NC)), dim3(256), 0, s, Z, ldz, N, me,
+                                   Tmax, nJ, wv, w.refl, w.T2);
         }
     }
     mark(w, MK_BT2, s);
