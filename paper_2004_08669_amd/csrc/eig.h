@@ -50,6 +50,7 @@ struct EigWork {
     // tridiagonal
     double *d = nullptr, *e = nullptr, *e2 = nullptr;  // N
     double *evals = nullptr;   // N, ascending
+    double *slices = nullptr;  // spectrum slicing: 2 x 4096 points, then their 2 x 4096 Sturm counts (int)
     double *ZT = nullptr;      // N x kmax (row-major, ld kmax)
     double *Ztmp = nullptr;    // N x kmax
     double *G = nullptr;       // kmax x kmax

@@ -462,6 +462,72 @@ __global__ void __launch_bounds__(256) tridiag_bounds_kernel(const double *d, co
     }
 }
 
+// Spectrum slicing: Sturm counts at two sorted point sets of PQR_SLICE points
+// each, one lane per point.  Set 0 is uniform on [lo, hi]; set 1 is geometric
+// about zero, +-tn 2^(-s j) down to 2^-46 tn, so that small eigenvalues start
+// from a bracket of relative width 1.6%.  bisect_kernel starts eigenvalue k from
+// the tighter of the two brackets [x_j, x_j+1) with count(x_j) <= k < count(x_j+1).
+constexpr int BIS_SLICE = 4096;
+
+CTMRG_DEVINL double slice_point(int g, const double *bounds)
+{
+    const double lo = bounds[0], hi = bounds[1], tn = bounds[3];
+    const int set = g / BIS_SLICE, j = g - set * BIS_SLICE;
+    if (set == 0) return lo + (double)(j + 1) * ((hi - lo) / (double)(BIS_SLICE + 1));
+    constexpr int half = BIS_SLICE / 2;
+    const double step = 46.0 / (double)(half - 1);
+    return j < half ? -tn * exp2(-step * (double)j) : tn * exp2(-step * (double)(half - 1 - (j - half)));
+}
+
+__global__ void __launch_bounds__(256) bisect_slice_kernel(const double *d, const double *e2, int N, const double *bounds,
+                                                           double *xs, int *cnt)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 2 * BIS_SLICE) return;
+    const double pivmin = bounds[2];
+    const double x = slice_point(g, bounds);
+    double q = d[0] - x;
+    int c = q < 0.0 ? 1 : 0;
+    for (int i0 = 1; i0 < N; i0 += 16) {
+        const int nI = min(16, N - i0);
+        double dv[16], ev[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = (u < nI) ? i0 + u : i0;
+            dv[u] = d[i];
+            ev[u] = e2[i - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (u < nI) {
+                double qq = q;
+                if (fabs(qq) < pivmin) qq = -pivmin;
+                double r = __builtin_amdgcn_rcp(qq);
+                r = fma(r, fma(-qq, r, 1.0), r);
+                qq = dv[u] - x - ev[u] * r;
+                c += qq < 0.0 ? 1 : 0;
+                q = qq;
+            }
+        }
+    }
+    xs[g] = x;
+    cnt[g] = c;
+}
+
+// Narrow [lo, hi) for eigenvalue k with one sorted set of slice points (counts
+// non-decreasing); a set whose counts disagree around k is ignored.
+CTMRG_DEVINL void slice_bracket(const double *xs, const int *cnt, int k, double &lo, double &hi)
+{
+    int a = -1, b = BIS_SLICE;  // cnt[a] <= k < cnt[b], with a = -1 and b = BIS_SLICE the ends
+    while (b - a > 1) {
+        const int mid = (a + b) >> 1;
+        if (cnt[mid] <= k) a = mid;
+        else b = mid;
+    }
+    if (a >= 0 && cnt[a] <= k) lo = fmax(lo, xs[a]);
+    if (b < BIS_SLICE && cnt[b] > k) hi = fmin(hi, xs[b]);
+}
+
 // Multisection by groups of lanes: LPE lanes work on one eigenvalue index k and
 // each evaluates S Sturm counts per pass (their recurrences interleave), so one
 // pass over T splits the bracket at LPE*S points and gains log2(LPE*S + 1) bits.
@@ -470,7 +536,7 @@ __global__ void __launch_bounds__(256) tridiag_bounds_kernel(const double *d, co
 // e2[i] (one broadcast load per wave).
 template <int LPE, int S>
 __global__ void __launch_bounds__(256) bisect_kernel(const double *d, const double *e2, int N, const double *bounds,
-                                                     double *evals)
+                                                     const double *xs, const int *cnts, double *evals)
 {
     constexpr int P = LPE * S;
     const int lane = threadIdx.x & 63;
@@ -478,6 +544,11 @@ __global__ void __launch_bounds__(256) bisect_kernel(const double *d, const doub
     const int k = (int)((blockIdx.x * (long)blockDim.x + threadIdx.x) / LPE);
     const bool active = k < N;
     double lo = bounds[0], hi = bounds[1];
+    if (active) {
+        slice_bracket(xs, cnts, k, lo, hi);
+        slice_bracket(xs + BIS_SLICE, cnts + BIS_SLICE, k, lo, hi);
+        if (!(lo < hi)) { lo = bounds[0]; hi = bounds[1]; }
+    }
     const double pivmin = bounds[2], tn = bounds[3];
     const double abstol = DBL_EPSILON * tn;
     bool done = !active;
@@ -1035,6 +1106,7 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax);
     s += align_up(sizeof(double) * (size_t)nJ * Tmax * b * b);
     s += 4 * align_up(sizeof(double) * (size_t)Nmax);
+    s += align_up(sizeof(double) * 4 * BIS_SLICE);
     s += 2 * align_up(sizeof(double) * (size_t)Nmax * kmax);
     s += align_up(sizeof(double) * (size_t)kmax * kmax);
     const size_t kpad = ((size_t)kmax + 63) / 64 * 64;
@@ -1077,6 +1149,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.e, sizeof(double) * (size_t)Nmax},
         {(void **)&w.e2, sizeof(double) * (size_t)Nmax},
         {(void **)&w.evals, sizeof(double) * (size_t)Nmax},
+        {(void **)&w.slices, sizeof(double) * 4 * BIS_SLICE},
         {(void **)&w.ZT, sizeof(double) * (size_t)Nmax * kmax},
         {(void **)&w.Ztmp, sizeof(double) * (size_t)Nmax * kmax},
         {(void **)&w.G, sizeof(double) * (size_t)kmax * kmax},
@@ -1108,7 +1181,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
 void eig_free(EigWork &w)
 {
     void *ptrs[] = {w.Vx, w.Tp, w.tau1, w.VW, w.WV, w.Y, w.X, w.sm, w.part, w.splitk, w.band, w.refl, w.rtau,
-                    w.T2, w.d, w.e, w.e2, w.evals, w.ZT, w.Ztmp, w.G, w.lu, w.ipiv, w.clist,
+                    w.T2, w.d, w.e, w.e2, w.evals, w.slices, w.ZT, w.Ztmp, w.G, w.lu, w.ipiv, w.clist,
                     w.cstart, w.err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1268,9 +1341,12 @@ hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s)
     hipLaunchKernelGGL(band_to_tridiag_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, s, w.band, N, b, w.d, w.e, w.e2);
     double *bounds = w.sm + 3 * b * b;
     hipLaunchKernelGGL(tridiag_bounds_kernel, dim3(1), dim3(256), 0, s, w.d, w.e, N, bounds);
+    double *xs = w.slices;
+    int *cnts = (int *)(w.slices + 2 * BIS_SLICE);
+    hipLaunchKernelGGL(bisect_slice_kernel, dim3(2 * BIS_SLICE / 256), dim3(256), 0, s, w.d, w.e2, N, bounds, xs, cnts);
     constexpr int LPE = 8, SH = 1;  // 8 lanes per eigenvalue, 1 shift each: 8 points per pass (fastest measured)
     hipLaunchKernelGGL((bisect_kernel<LPE, SH>), dim3(ceil_div((long)N * LPE, 256)), dim3(256), 0, s, w.d, w.e2, N,
-                       bounds, w.evals);
+                       bounds, xs, cnts, w.evals);
     mark(w, MK_BISECT, s);
     return hipGetLastError();
 }
