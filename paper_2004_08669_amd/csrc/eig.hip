@@ -462,7 +462,64 @@ __global__ void __launch_bounds__(256) tridiag_bounds_kernel(const double *d, co
     }
 }
 
-// Spectrum slicing: Sturm counts at two sorted point sets of PQR_SLICE points
+// Sturm counts of T - x_v I for S shifts at once: the number of negative pivots of
+// the LDL^T recurrence q_i = d_i - x - e_{i-1}^2 / q_{i-1} (a tiny pivot is replaced
+// by -pivmin).  e2 / q takes the hardware reciprocal and one Newton step: an ulp or
+// two, a relative perturbation of e2 of that size, far inside the count's backward
+// error.  d and e2 are read in chunks of 16 (the same address in every lane), the
+// next chunk's loads issued before the current chunk's recurrence runs.
+template <int S>
+CTMRG_DEVINL void sturm_counts(const double *d, const double *e2, int N, const double (&x)[S], double pivmin,
+                               int (&cnt)[S])
+{
+    constexpr int C = 16;
+    double q[S];
+#pragma unroll
+    for (int v = 0; v < S; ++v) {
+        q[v] = d[0] - x[v];
+        cnt[v] = q[v] < 0.0 ? 1 : 0;
+    }
+    double da[C], ea[C], db[C], eb[C];
+    auto load = [&](double (&dd)[C], double (&ee)[C], int i0) {
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+            const int i = min(i0 + u, N - 1);
+            dd[u] = d[i];
+            ee[u] = e2[i - 1];
+        }
+    };
+    auto run = [&](const double (&dd)[C], const double (&ee)[C], int i0) {
+        const int nI = min(C, N - i0);
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+            if (u < nI) {
+#pragma unroll
+                for (int v = 0; v < S; ++v) {
+                    double qq = q[v];
+                    if (fabs(qq) < pivmin) qq = -pivmin;
+                    double r = __builtin_amdgcn_rcp(qq);
+                    r = fma(r, fma(-qq, r, 1.0), r);
+                    qq = dd[u] - x[v] - ee[u] * r;
+                    cnt[v] += qq < 0.0 ? 1 : 0;
+                    q[v] = qq;
+                }
+            }
+        }
+    };
+    int i0 = 1;
+    if (i0 < N) load(da, ea, i0);
+    while (i0 < N) {
+        if (i0 + C < N) load(db, eb, i0 + C);
+        run(da, ea, i0);
+        i0 += C;
+        if (i0 >= N) break;
+        if (i0 + C < N) load(da, ea, i0 + C);
+        run(db, eb, i0);
+        i0 += C;
+    }
+}
+
+// Spectrum slicing: Sturm counts at two sorted point sets of BIS_SLICE points
 // each, one lane per point.  Set 0 is uniform on [lo, hi]; set 1 is geometric
 // about zero, +-tn 2^(-s j) down to 2^-46 tn, so that small eigenvalues start
 // from a bracket of relative width 1.6%.  bisect_kernel starts eigenvalue k from
@@ -485,33 +542,11 @@ __global__ void __launch_bounds__(256) bisect_slice_kernel(const double *d, cons
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= 2 * BIS_SLICE) return;
     const double pivmin = bounds[2];
-    const double x = slice_point(g, bounds);
-    double q = d[0] - x;
-    int c = q < 0.0 ? 1 : 0;
-    for (int i0 = 1; i0 < N; i0 += 16) {
-        const int nI = min(16, N - i0);
-        double dv[16], ev[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = (u < nI) ? i0 + u : i0;
-            dv[u] = d[i];
-            ev[u] = e2[i - 1];
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            if (u < nI) {
-                double qq = q;
-                if (fabs(qq) < pivmin) qq = -pivmin;
-                double r = __builtin_amdgcn_rcp(qq);
-                r = fma(r, fma(-qq, r, 1.0), r);
-                qq = dv[u] - x - ev[u] * r;
-                c += qq < 0.0 ? 1 : 0;
-                q = qq;
-            }
-        }
-    }
-    xs[g] = x;
-    cnt[g] = c;
+    const double x[1] = {slice_point(g, bounds)};
+    int c[1];
+    sturm_counts<1>(d, e2, N, x, pivmin, c);
+    xs[g] = x[0];
+    cnt[g] = c[0];
 }
 
 // Narrow [lo, hi) for eigenvalue k with one sorted set of slice points (counts
@@ -557,42 +592,11 @@ __global__ void __launch_bounds__(256) bisect_kernel(const double *d, const doub
         // the whole wave stops when every group has
         if (__all(done)) break;
         const double w = (hi - lo) / (double)(P + 1);
-        double x[S], q[S];
+        double x[S];
         int cnt[S];
 #pragma unroll
-        for (int u = 0; u < S; ++u) {
-            x[u] = fmin(hi, lo + (double)(sub * S + u + 1) * w);
-            q[u] = d[0] - x[u];
-            cnt[u] = q[u] < 0.0 ? 1 : 0;
-        }
-        for (int i0 = 1; i0 < N; i0 += 16) {
-            const int nI = min(16, N - i0);
-            double dv[16], ev[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int i = (u < nI) ? i0 + u : i0;
-                dv[u] = d[i];
-                ev[u] = e2[i - 1];
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                if (u < nI) {
-#pragma unroll
-                    for (int v = 0; v < S; ++v) {
-                        double qq = q[v];
-                        if (fabs(qq) < pivmin) qq = -pivmin;
-                        // e2 / q by the hardware reciprocal and one Newton step (an ulp or two:
-                        // a relative perturbation of e2 of that size, far inside the count's
-                        // backward error)
-                        double r = __builtin_amdgcn_rcp(qq);
-                        r = fma(r, fma(-qq, r, 1.0), r);
-                        qq = dv[u] - x[v] - ev[u] * r;
-                        cnt[v] += qq < 0.0 ? 1 : 0;
-                        q[v] = qq;
-                    }
-                }
-            }
-        }
+        for (int u = 0; u < S; ++u) x[u] = fmin(hi, lo + (double)(sub * S + u + 1) * w);
+        sturm_counts<S>(d, e2, N, x, pivmin, cnt);
         // eigenvalue k lies in [x_a, x_b) with x_a the largest point of count <= k, x_b the smallest of count > k
         double nlo = lo, nhi = hi;
 #pragma unroll
@@ -1344,7 +1348,7 @@ hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s)
     double *xs = w.slices;
     int *cnts = (int *)(w.slices + 2 * BIS_SLICE);
     hipLaunchKernelGGL(bisect_slice_kernel, dim3(2 * BIS_SLICE / 256), dim3(256), 0, s, w.d, w.e2, N, bounds, xs, cnts);
-    constexpr int LPE = 8, SH = 1;  // 8 lanes per eigenvalue, 1 shift each: 8 points per pass (fastest measured)
+    constexpr int LPE = 16, SH = 1;  // 16 lanes per eigenvalue, 1 shift each: 16 points per pass (fastest measured)
     hipLaunchKernelGGL((bisect_kernel<LPE, SH>), dim3(ceil_div((long)N * LPE, 256)), dim3(256), 0, s, w.d, w.e2, N,
                        bounds, xs, cnts, w.evals);
     mark(w, MK_BISECT, s);
