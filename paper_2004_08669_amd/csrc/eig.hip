@@ -253,13 +253,93 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, double *Vx, double *t
     }
 }
 
-// Epilogue that forms W = X - 1/2 V S and the two concatenated operands
-// [V | W] and [W | V] of the rank-2b trailing update.
-struct EpiWform {
-    const double *X; const double *V; double *VW; double *WV; int b;
-    __device__ void operator()(int i, int j, double acc, int) const
+// The two-sided update of a panel needs W = X - 1/2 V S with X = Y T and
+// S = T^T V^T X = T^T (V^T Y) T, i.e. W = [Y | V] [T ; -1/2 S]:
+//  * vty_partial_kernel: partial sums of V^T Y (b x b) on the matrix cores, one per
+//    workgroup over rows strided by the grid (k-steps of 4 rows);
+//  * wy_small_kernel (one workgroup): M0 = sum of the partials, S = T^T M0 T, and
+//    the 2b x b right factor [T ; -1/2 S];
+//  * one GEMM [Y | V] [T ; -1/2 S] whose epilogue writes [V | W] and [W | V].
+constexpr int VTY_WG = 64;
+
+template <int B>
+__global__ void __launch_bounds__(256) vty_partial_kernel(const double *V, const double *Y, int n, double *part)
+{
+    using MF = Mfma<double>;
+    constexpr int TB = B / 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave >= TB * TB) return;
+    const int I = wave / TB, J = wave % TB;
+    const int lr = lane >> 4, lc = lane & 15;
+    MF::acc_t acc = MF::zero();
+    const int stride = gridDim.x * 4;
+    int r0 = blockIdx.x * 4;
+    for (; r0 + 7 * stride + 4 <= n; r0 += 8 * stride) {
+        double a[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long r = r0 + u * stride + lr;
+            a[u] = V[r * B + 16 * I + lc];
+            y[u] = Y[r * B + 16 * J + lc];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = MF::mma(a[u], y[u], acc);
+    }
+    for (; r0 < n; r0 += stride) {
+        const int r = r0 + lr;
+        const double a = r < n ? V[(long)r * B + 16 * I + lc] : 0.0;
+        const double y = r < n ? Y[(long)r * B + 16 * J + lc] : 0.0;
+        acc = MF::mma(a, y, acc);
+    }
+    double *dst = part + (long)blockIdx.x * B * B;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[(16 * I + lr + 4 * j) * B + 16 * J + lc] = acc[j];
+}
+
+__global__ void __launch_bounds__(1024) wy_small_kernel(const double *part, int nparts, const double *T, int b,
+                                                        double *B2)
+{
+    __shared__ double M0[32][33], Ts[32][33], Mt[32][33];
+    const int tid = threadIdx.x;
+    const int i = tid / b, j = tid - (tid / b) * b;
+    const bool act = tid < b * b;
+    if (act) {
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int g = 0;
+        for (; g + 8 <= nparts; g += 8)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s[u] += part[(long)(g + u) * b * b + tid];
+        for (; g < nparts; ++g) s[0] += part[(long)g * b * b + tid];
+        M0[i][j] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+        Ts[i][j] = T[tid];
+    }
+    __syncthreads();
+    if (act) {  // Mt = M0 T
+        double t = 0.0;
+        for (int k = 0; k < b; ++k) t += M0[i][k] * Ts[k][j];
+        Mt[i][j] = t;
+    }
+    __syncthreads();
+    if (act) {  // S = T^T Mt; B2 = [T ; -S/2]
+        double t = 0.0;
+        for (int k = 0; k < b; ++k) t += Ts[k][i] * Mt[k][j];
+        B2[tid] = Ts[i][j];
+        B2[b * b + tid] = -0.5 * t;
+    }
+}
+
+// [Y | V] as one n x 2b operand
+struct A_YV {
+    using value_type = double;
+    const double *Y; const double *V; int b;
+    static constexpr bool kContigK = true;
+    __device__ double operator()(int i, int k) const { return k < b ? Y[(long)i * b + k] : V[(long)i * b + k - b]; }
+};
+// Writes [V | W] and [W | V] from W = acc
+struct EpiVW {
+    const double *V; double *VW; double *WV; int b;
+    __device__ void operator()(int i, int j, double w, int) const
     {
-        const double w = X[(long)i * b + j] - 0.5 * acc;
         const double v = V[(long)i * b + j];
         VW[(long)i * 2 * b + j] = v;
         VW[(long)i * 2 * b + b + j] = w;
@@ -1275,21 +1355,17 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
                                dim3(256), 0, s, p1, p2, n, b, n, ch, w.Y, (long)b);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-        // X = Y T
-        e = gemm_mfma(GEMM_TALL, A_RM{w.Y, b}, B_RM{Tp, b}, EpiStore{w.X, b, 1.0}, n, b, b, s);
-        if (e != hipSuccess) return e;
-        // M = V^T X
+        // W = [Y | V] [T ; -1/2 S] with S = T^T (V^T Y) T, and the operands [V|W], [W|V]
         {
-            const int sp = splits_for(1, n, 128);
-            e = gemm_mfma_splitk(A_T{Vp, b}, B_RM{w.X, b}, EpiStore{w.sm, b, 1.0}, b, b, n, sp, w.splitk, s);
+            const int gv = std::min(VTY_WG, std::max(1, ceil_div(n, 4)));
+            if (b == 32)
+                hipLaunchKernelGGL(vty_partial_kernel<32>, dim3(gv), dim3(256), 0, s, Vp, w.Y, n, w.splitk);
+            else
+                hipLaunchKernelGGL(vty_partial_kernel<16>, dim3(gv), dim3(256), 0, s, Vp, w.Y, n, w.splitk);
+            hipLaunchKernelGGL(wy_small_kernel, dim3(1), dim3(1024), 0, s, w.splitk, gv, Tp, b, w.sm);
+            e = gemm_mfma(GEMM_TALL, A_YV{w.Y, Vp, b}, B_RM{w.sm, b}, EpiVW{Vp, w.VW, w.WV, b}, n, b, 2 * b, s);
             if (e != hipSuccess) return e;
         }
-        // S = T^T M
-        e = gemm_mfma(GEMM_SMALL, A_T{Tp, b}, B_RM{w.sm, b}, EpiStore{w.sm + b * b, b, 1.0}, b, b, b, s);
-        if (e != hipSuccess) return e;
-        // W = X - 1/2 V S, and the operands [V|W], [W|V]
-        e = gemm_mfma(GEMM_TALL, A_RM{Vp, b}, B_RM{w.sm + b * b, b}, EpiWform{w.X, Vp, w.VW, w.WV, b}, n, b, b, s);
-        if (e != hipSuccess) return e;
         // A22 -= [V|W] [W|V]^T on the lower triangle (the only part later read)
         if (pi + 1 < np) {
             // the next panel's columns first (rows 0..n-1, columns 0..b-1 of A22) ...
