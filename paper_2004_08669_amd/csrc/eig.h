@@ -47,6 +47,9 @@ struct EigWork {
     double *refl = nullptr;    // (N * Tmax * b) reflectors
     double *rtau = nullptr;    // (N * Tmax)
     double *T2 = nullptr;      // nJ * Tmax * b * b
+    // back-transform of stage 1: per group of panels, the Gram matrix of its V and its T
+    double *bt1_gram = nullptr, *bt1_T = nullptr;
+    double *bt1_W = nullptr;   // 2 x (4 b) x kmax: V_G^T Z and T_G V_G^T Z of one group
     // tridiagonal
     double *d = nullptr, *e = nullptr, *e2 = nullptr;  // N
     double *evals = nullptr;   // N, ascending

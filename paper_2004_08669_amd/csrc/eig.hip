@@ -23,7 +23,7 @@ static int num_panels(int N, int b)
     for (int p = 0; p + b <= N - 2; p += b) ++np;
     return np;
 }
-static long panel_v_offset(int N, int b, int pi)
+__host__ __device__ inline long panel_v_offset(int N, int b, int pi)
 {
     long off = 0;
     for (int i = 0; i < pi; ++i) off += (long)(N - (i + 1) * b) * b;
@@ -1130,6 +1130,128 @@ bt2_apply_kernel(double *Z, int ldz, int N, int ncols, int Tmax, int nJ, int wav
 }
 
 // ============================================================================
+// Back-transform of stage 1: panels grouped BT1_G at a time
+// ============================================================================
+//
+// Group k holds panels p = k G .. k G + G - 1 (fewer, or none, at the end); their
+// product Q_p Q_p+1 ... = I - V_G T_G V_G^T with V_G = [V_p | V_p+1 | ...] (panel
+// p + j starts j b rows below panel p) and T_G the compact-WY factor of the G b
+// reflectors in order: T[0:i, i] = -tau_i T[0:i, 0:i] (V_G^T V_G)[0:i, i].  One
+// group then costs one pass of three GEMMs over Z instead of G passes.
+constexpr int BT1_G = 4;
+
+// V_G as a function of (row r from the first panel's first row, column c).
+template <int B>
+struct VGroup {
+    const double *V[BT1_G];  // explicit V of each panel (n_j x B, row-major), or null
+    int n0;                  // rows of the first panel
+    __device__ double at(int r, int c) const
+    {
+        const int j = c / B, lc = c % B, lr = r - j * B;
+        const double *v = V[0];
+#pragma unroll
+        for (int u = 1; u < BT1_G; ++u)
+            if (j == u) v = V[u];
+        return (v != nullptr && lr >= 0 && lr < n0 - j * B) ? v[(long)lr * B + lc] : 0.0;
+    }
+};
+template <int B>
+struct A_VG {  // V_G, n x G B
+    using value_type = double;
+    VGroup<B> g;
+    static constexpr bool kContigK = true;
+    __device__ double operator()(int i, int k) const { return g.at(i, k); }
+};
+template <int B>
+struct A_VGT {  // V_G^T, G B x n
+    using value_type = double;
+    VGroup<B> g;
+    static constexpr bool kContigK = false;
+    __device__ double operator()(int i, int k) const { return g.at(k, i); }
+};
+
+// Gram matrix V_G^T V_G (upper 16 x 16 tiles) of every group on the matrix cores:
+// one workgroup per group, wave w owning the tile rows TR w .. TR w + TR - 1.
+template <int B>
+__global__ void __launch_bounds__(256) bt1_gram_kernel(const double *Vx, const double *tau1, int N, int np,
+                                                       double *gram)
+{
+    using MF = Mfma<double>;
+    constexpr int GB = BT1_G * B, GT = GB / 16, TR = GT / 4;
+    static_assert(TR * 4 == GT, "four waves");
+    const int grp = blockIdx.x, p0 = grp * BT1_G;
+    VGroup<B> vg;
+    long off = panel_v_offset(N, B, p0);
+    for (int j = 0; j < BT1_G; ++j) {
+        vg.V[j] = (p0 + j < np) ? Vx + off : nullptr;
+        off += (long)(N - (p0 + j + 1) * B) * B;
+    }
+    vg.n0 = N - (p0 + 1) * B;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
+    const int I0 = TR * wave;
+    MF::acc_t acc[TR][GT];
+#pragma unroll
+    for (int a = 0; a < TR; ++a)
+#pragma unroll
+        for (int J = 0; J < GT; ++J) acc[a][J] = MF::zero();
+    for (int r0 = 0; r0 < vg.n0; r0 += 4) {
+        const int r = r0 + lr;
+        double av[TR];
+#pragma unroll
+        for (int a = 0; a < TR; ++a) av[a] = vg.at(r, 16 * (I0 + a) + lc);
+#pragma unroll
+        for (int J = 0; J < GT; ++J) {
+            if (J >= I0) {
+                const double bj = vg.at(r, 16 * J + lc);
+#pragma unroll
+                for (int a = 0; a < TR; ++a)
+                    if (J >= I0 + a) acc[a][J] = MF::mma(av[a], bj, acc[a][J]);
+            }
+        }
+    }
+    double *G = gram + (long)grp * GB * GB;
+#pragma unroll
+    for (int a = 0; a < TR; ++a)
+#pragma unroll
+        for (int J = 0; J < GT; ++J)
+            if (J >= I0 + a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) G[(16 * (I0 + a) + lr + 4 * q) * GB + 16 * J + lc] = acc[a][J][q];
+}
+
+// T_G of every group from its Gram matrix and the taus (zero for missing panels);
+// column i of T in LDS, one column per step.
+template <int B>
+__global__ void __launch_bounds__(256) bt1_tg_kernel(const double *gram, const double *tau1, int np, double *TG)
+{
+    constexpr int GB = BT1_G * B;
+    extern __shared__ double sh[];
+    double *T = sh;              // [GB][GB + 1]
+    double *gc = T + GB * (GB + 1);  // [GB]
+    const int grp = blockIdx.x, p0 = grp * BT1_G;
+    const double *G = gram + (long)grp * GB * GB;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < GB * (GB + 1); idx += 256) T[idx] = 0.0;
+    __syncthreads();
+    for (int i = 0; i < GB; ++i) {
+        const int pj = p0 + i / B;
+        const double tau = (pj < np) ? tau1[(long)p0 * B + i] : 0.0;
+        for (int l = tid; l < i; l += 256) gc[l] = G[l * GB + i];
+        __syncthreads();
+        if (tid < i) {
+            double s = 0.0;
+            for (int l = tid; l < i; ++l) s += T[tid * (GB + 1) + l] * gc[l];
+            T[tid * (GB + 1) + i] = -tau * s;
+        } else if (tid == i) {
+            T[i * (GB + 1) + i] = tau;
+        }
+        __syncthreads();
+    }
+    double *dst = TG + (long)grp * GB * GB;
+    for (int idx = tid; idx < GB * GB; idx += 256) dst[idx] = T[(idx / GB) * (GB + 1) + idx % GB];
+}
+
+// ============================================================================
 // Final copy with sign convention: each eigenvector is negated if its first
 // entry of largest magnitude is negative.
 // ============================================================================
@@ -1189,6 +1311,8 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax);
     s += align_up(sizeof(double) * (size_t)nJ * Tmax * b * b);
+    s += 2 * align_up(sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_G * b * BT1_G * b + 8);
+    s += align_up(sizeof(double) * 2 * (size_t)BT1_G * b * kmax);
     s += 4 * align_up(sizeof(double) * (size_t)Nmax);
     s += align_up(sizeof(double) * 4 * BIS_SLICE);
     s += 2 * align_up(sizeof(double) * (size_t)Nmax * kmax);
@@ -1229,6 +1353,9 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.refl, sizeof(double) * (size_t)Nmax * w.Tmax * b},
         {(void **)&w.rtau, sizeof(double) * (size_t)Nmax * w.Tmax},
         {(void **)&w.T2, sizeof(double) * (size_t)w.nJmax * w.Tmax * b * b},
+        {(void **)&w.bt1_gram, sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_G * b * BT1_G * b + 8},
+        {(void **)&w.bt1_T, sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_G * b * BT1_G * b + 8},
+        {(void **)&w.bt1_W, sizeof(double) * 2 * (size_t)BT1_G * b * kmax},
         {(void **)&w.d, sizeof(double) * (size_t)Nmax},
         {(void **)&w.e, sizeof(double) * (size_t)Nmax},
         {(void **)&w.e2, sizeof(double) * (size_t)Nmax},
@@ -1252,7 +1379,10 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
     }
     (void)hipMemset(w.part, 0xFF, sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b)));  // all slots empty
     (void)hipMemset(w.err, 0, 64);
-    hipError_t e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
+    const size_t tg_smem = sizeof(double) * ((size_t)BT1_G * b * (BT1_G * b + 1) + BT1_G * b);
+    hipError_t e = hipFuncSetAttribute(b == 32 ? (const void *)bt1_tg_kernel<32> : (const void *)bt1_tg_kernel<16>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)tg_smem);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_cols, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_panel, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -1265,7 +1395,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
 void eig_free(EigWork &w)
 {
     void *ptrs[] = {w.Vx, w.Tp, w.tau1, w.VW, w.WV, w.Y, w.X, w.sm, w.part, w.splitk, w.band, w.refl, w.rtau,
-                    w.T2, w.d, w.e, w.e2, w.evals, w.slices, w.ZT, w.Ztmp, w.G, w.lu, w.ipiv, w.clist,
+                    w.T2, w.bt1_gram, w.bt1_T, w.bt1_W, w.d, w.e, w.e2, w.evals, w.slices, w.ZT, w.Ztmp, w.G, w.lu, w.ipiv, w.clist,
                     w.cstart, w.err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1441,6 +1571,32 @@ hipError_t eig_post(EigWork &w, int N, int m, double gap_tol, double rank_tol, c
     return hipGetLastError();
 }
 
+// Z[r0:, :] -= V_G T_G V_G^T Z[r0:, :] for panel group k.
+template <int B>
+static hipError_t bt1_apply_group(EigWork &w, double *Z, int ldz, int N, int me, int np, int k, hipStream_t s)
+{
+    constexpr int GB = BT1_G * B;
+    const int p0 = k * BT1_G, r0 = p0 * B + B, n = N - r0;
+    VGroup<B> vg;
+    long off = panel_v_offset(N, B, p0);
+    for (int j = 0; j < BT1_G; ++j) {
+        vg.V[j] = (p0 + j < np) ? w.Vx + off : nullptr;
+        off += (long)(N - (p0 + j + 1) * B) * B;
+    }
+    vg.n0 = n;
+    const double *TG = w.bt1_T + (long)k * GB * GB;
+    double *Zs = Z + (long)r0 * ldz;
+    double *W1 = w.bt1_W, *W2 = w.bt1_W + (long)GB * me;
+    const long tiles = (long)ceil_div(GB, 64) * ceil_div(me, 64);
+    int sp = splits_for(tiles, n, 128);
+    while (sp > 1 && (size_t)sp * GB * me > w.splitk_elems) sp /= 2;
+    hipError_t e = gemm_mfma_splitk(A_VGT<B>{vg}, B_RM{Zs, ldz}, EpiStore{W1, me, 1.0}, GB, me, n, sp, w.splitk, s);
+    if (e != hipSuccess) return e;
+    e = gemm_mfma(GEMM_SMALL, A_RM{TG, GB}, B_RM{W1, me}, EpiStore{W2, me, 1.0}, GB, me, GB, s);
+    if (e != hipSuccess) return e;
+    return gemm_mfma(GEMM_LARGE, A_VG<B>{vg}, B_RM{W2, me}, EpiAxpby{Zs, ldz, -1.0, 1.0}, n, me, GB, s);
+}
+
 hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const double *selval, int nclusters,
                        double *U, int ldu, hipStream_t s)
 {
@@ -1485,21 +1641,24 @@ hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const do
         }
     }
     mark(w, MK_BT2, s);
-    // stage-1 back-transform, last panel first
+    // stage-1 back-transform, groups of BT1_G panels, last group first
     const int np = num_panels(N, b);
-    for (int pi = np - 1; pi >= 0; --pi) {
-        const int r0 = pi * b + b, n = N - r0;
-        const double *Vp = w.Vx + panel_v_offset(N, b, pi);
-        const double *Tp = w.Tp + (long)pi * b * b;
-        double *Zs = Z + (long)r0 * ldz;
-        const long tiles = ceil_div(me, 64);
-        const int sp = splits_for(tiles, n, 128);
-        e = gemm_mfma_splitk(A_T{Vp, b}, B_RM{Zs, ldz}, EpiStore{w.Y, me, 1.0}, b, me, n, sp, w.splitk, s);
-        if (e != hipSuccess) return e;
-        e = gemm_mfma(GEMM_SMALL, A_RM{Tp, b}, B_RM{w.Y, me}, EpiStore{w.X, me, 1.0}, b, me, b, s);
-        if (e != hipSuccess) return e;
-        e = gemm_mfma(GEMM_LARGE, A_RM{Vp, b}, B_RM{w.X, me}, EpiAxpby{Zs, ldz, -1.0, 1.0}, n, me, b, s);
-        if (e != hipSuccess) return e;
+    if (np > 0) {
+        const int ngr = ceil_div(np, BT1_G), GB = BT1_G * b;
+        if (b == 32) {
+            hipLaunchKernelGGL(bt1_gram_kernel<32>, dim3(ngr), dim3(256), 0, s, w.Vx, w.tau1, N, np, w.bt1_gram);
+            hipLaunchKernelGGL(bt1_tg_kernel<32>, dim3(ngr), dim3(256), sizeof(double) * (GB * (GB + 1) + GB), s,
+                               w.bt1_gram, w.tau1, np, w.bt1_T);
+        } else {
+            hipLaunchKernelGGL(bt1_gram_kernel<16>, dim3(ngr), dim3(256), 0, s, w.Vx, w.tau1, N, np, w.bt1_gram);
+            hipLaunchKernelGGL(bt1_tg_kernel<16>, dim3(ngr), dim3(256), sizeof(double) * (GB * (GB + 1) + GB), s,
+                               w.bt1_gram, w.tau1, np, w.bt1_T);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int k = ngr - 1; k >= 0; --k) {
+            e = b == 32 ? bt1_apply_group<32>(w, Z, ldz, N, me, np, k, s) : bt1_apply_group<16>(w, Z, ldz, N, me, np, k, s);
+            if (e != hipSuccess) return e;
+        }
     }
     hipLaunchKernelGGL(sign_fix_copy_kernel, dim3(ldu), dim3(256), 0, s, Z, ldz, N, me, U, ldu);
     mark(w, MK_BT1, s);
