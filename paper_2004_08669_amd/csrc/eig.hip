@@ -1170,16 +1170,18 @@ struct A_VGT {  // V_G^T, G B x n
     __device__ double operator()(int i, int k) const { return g.at(k, i); }
 };
 
-// Gram matrix V_G^T V_G (upper 16 x 16 tiles) of every group on the matrix cores:
-// one workgroup per group, wave w owning the tile rows TR w .. TR w + TR - 1.
+// Gram matrix V_G^T V_G (upper 16 x 16 tiles) of every group on the matrix cores,
+// as BT1_RS partial sums over row chunks: workgroup (group, chunk), wave w owning
+// the tile rows TR w .. TR w + TR - 1; four k-steps of loads are issued at once.
+constexpr int BT1_RS = 16;
+
 template <int B>
-__global__ void __launch_bounds__(256) bt1_gram_kernel(const double *Vx, const double *tau1, int N, int np,
-                                                       double *gram)
+__global__ void __launch_bounds__(256) bt1_gram_kernel(const double *Vx, int N, int np, double *gram)
 {
     using MF = Mfma<double>;
-    constexpr int GB = BT1_G * B, GT = GB / 16, TR = GT / 4;
+    constexpr int GB = BT1_G * B, GT = GB / 16, TR = GT / 4, U = 4;
     static_assert(TR * 4 == GT, "four waves");
-    const int grp = blockIdx.x, p0 = grp * BT1_G;
+    const int grp = blockIdx.x, chunk = blockIdx.y, p0 = grp * BT1_G;
     VGroup<B> vg;
     long off = panel_v_offset(N, B, p0);
     for (int j = 0; j < BT1_G; ++j) {
@@ -1187,6 +1189,8 @@ __global__ void __launch_bounds__(256) bt1_gram_kernel(const double *Vx, const d
         off += (long)(N - (p0 + j + 1) * B) * B;
     }
     vg.n0 = N - (p0 + 1) * B;
+    const int steps = (vg.n0 + 3) / 4, per = (steps + BT1_RS - 1) / BT1_RS;
+    const int s_lo = chunk * per, s_hi = min(steps, s_lo + per);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
     const int I0 = TR * wave;
     MF::acc_t acc[TR][GT];
@@ -1194,22 +1198,27 @@ __global__ void __launch_bounds__(256) bt1_gram_kernel(const double *Vx, const d
     for (int a = 0; a < TR; ++a)
 #pragma unroll
         for (int J = 0; J < GT; ++J) acc[a][J] = MF::zero();
-    for (int r0 = 0; r0 < vg.n0; r0 += 4) {
-        const int r = r0 + lr;
-        double av[TR];
+    for (int s0 = s_lo; s0 < s_hi; s0 += U) {
+        double av[U][TR], bv[U][GT];
 #pragma unroll
-        for (int a = 0; a < TR; ++a) av[a] = vg.at(r, 16 * (I0 + a) + lc);
+        for (int u = 0; u < U; ++u) {
+            const int r = 4 * (s0 + u) + lr;
+            const bool ok = s0 + u < s_hi;
 #pragma unroll
-        for (int J = 0; J < GT; ++J) {
-            if (J >= I0) {
-                const double bj = vg.at(r, 16 * J + lc);
+            for (int a = 0; a < TR; ++a) av[u][a] = ok ? vg.at(r, 16 * (I0 + a) + lc) : 0.0;
 #pragma unroll
-                for (int a = 0; a < TR; ++a)
-                    if (J >= I0 + a) acc[a][J] = MF::mma(av[a], bj, acc[a][J]);
-            }
+            for (int J = 0; J < GT; ++J) bv[u][J] = (ok && J >= I0) ? vg.at(r, 16 * J + lc) : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int J = 0; J < GT; ++J)
+                if (J >= I0)
+#pragma unroll
+                    for (int a = 0; a < TR; ++a)
+                        if (J >= I0 + a) acc[a][J] = MF::mma(av[u][a], bv[u][J], acc[a][J]);
     }
-    double *G = gram + (long)grp * GB * GB;
+    double *G = gram + ((long)grp * BT1_RS + chunk) * GB * GB;
 #pragma unroll
     for (int a = 0; a < TR; ++a)
 #pragma unroll
@@ -1229,14 +1238,18 @@ __global__ void __launch_bounds__(256) bt1_tg_kernel(const double *gram, const d
     double *T = sh;              // [GB][GB + 1]
     double *gc = T + GB * (GB + 1);  // [GB]
     const int grp = blockIdx.x, p0 = grp * BT1_G;
-    const double *G = gram + (long)grp * GB * GB;
+    const double *G = gram + (long)grp * BT1_RS * GB * GB;
     const int tid = threadIdx.x;
     for (int idx = tid; idx < GB * (GB + 1); idx += 256) T[idx] = 0.0;
     __syncthreads();
     for (int i = 0; i < GB; ++i) {
         const int pj = p0 + i / B;
         const double tau = (pj < np) ? tau1[(long)p0 * B + i] : 0.0;
-        for (int l = tid; l < i; l += 256) gc[l] = G[l * GB + i];
+        for (int l = tid; l < i; l += 256) {
+            double g = 0.0;
+            for (int ch = 0; ch < BT1_RS; ++ch) g += G[(long)ch * GB * GB + l * GB + i];
+            gc[l] = g;
+        }
         __syncthreads();
         if (tid < i) {
             double s = 0.0;
@@ -1311,7 +1324,8 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax);
     s += align_up(sizeof(double) * (size_t)nJ * Tmax * b * b);
-    s += 2 * align_up(sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_G * b * BT1_G * b + 8);
+    s += align_up(sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_RS * BT1_G * b * BT1_G * b + 8);
+    s += align_up(sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_G * b * BT1_G * b + 8);
     s += align_up(sizeof(double) * 2 * (size_t)BT1_G * b * kmax);
     s += 4 * align_up(sizeof(double) * (size_t)Nmax);
     s += align_up(sizeof(double) * 4 * BIS_SLICE);
@@ -1353,7 +1367,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.refl, sizeof(double) * (size_t)Nmax * w.Tmax * b},
         {(void **)&w.rtau, sizeof(double) * (size_t)Nmax * w.Tmax},
         {(void **)&w.T2, sizeof(double) * (size_t)w.nJmax * w.Tmax * b * b},
-        {(void **)&w.bt1_gram, sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_G * b * BT1_G * b + 8},
+        {(void **)&w.bt1_gram, sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_RS * BT1_G * b * BT1_G * b + 8},
         {(void **)&w.bt1_T, sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_G * b * BT1_G * b + 8},
         {(void **)&w.bt1_W, sizeof(double) * 2 * (size_t)BT1_G * b * kmax},
         {(void **)&w.d, sizeof(double) * (size_t)Nmax},
@@ -1646,11 +1660,11 @@ hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const do
     if (np > 0) {
         const int ngr = ceil_div(np, BT1_G), GB = BT1_G * b;
         if (b == 32) {
-            hipLaunchKernelGGL(bt1_gram_kernel<32>, dim3(ngr), dim3(256), 0, s, w.Vx, w.tau1, N, np, w.bt1_gram);
+            hipLaunchKernelGGL(bt1_gram_kernel<32>, dim3(ngr, BT1_RS), dim3(256), 0, s, w.Vx, N, np, w.bt1_gram);
             hipLaunchKernelGGL(bt1_tg_kernel<32>, dim3(ngr), dim3(256), sizeof(double) * (GB * (GB + 1) + GB), s,
                                w.bt1_gram, w.tau1, np, w.bt1_T);
         } else {
-            hipLaunchKernelGGL(bt1_gram_kernel<16>, dim3(ngr), dim3(256), 0, s, w.Vx, w.tau1, N, np, w.bt1_gram);
+            hipLaunchKernelGGL(bt1_gram_kernel<16>, dim3(ngr, BT1_RS), dim3(256), 0, s, w.Vx, N, np, w.bt1_gram);
             hipLaunchKernelGGL(bt1_tg_kernel<16>, dim3(ngr), dim3(256), sizeof(double) * (GB * (GB + 1) + GB), s,
                                w.bt1_gram, w.tau1, np, w.bt1_T);
         }
