@@ -63,9 +63,10 @@ struct EigWork {
     int *cstart = nullptr;     // kmax + 1 cluster offsets
     unsigned *err = nullptr;   // kernel error flags
     hipEvent_t *marks = nullptr;  // optional stage-boundary events (see MarkId)
-    // look-ahead: the next panel's QR runs on s2 while the trailing update runs on the caller's stream
+    // look-ahead: the update of the rest of the trailing matrix runs on s2 while the next
+    // panel's QR runs on the caller's stream
     hipStream_t s2 = nullptr;
-    hipEvent_t ev_cols = nullptr, ev_panel = nullptr;
+    hipEvent_t ev_cols = nullptr, ev_update = nullptr;
 };
 
 // Stage boundaries recorded when EigWork::marks is set (indices into marks).

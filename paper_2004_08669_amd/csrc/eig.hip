@@ -1398,7 +1398,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)tg_smem);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_cols, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_panel, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_update, hipEventDisableTiming);
     if (e != hipSuccess) {
         eig_free(w);
         return e;
@@ -1414,7 +1414,7 @@ void eig_free(EigWork &w)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w.ev_cols) (void)hipEventDestroy(w.ev_cols);
-    if (w.ev_panel) (void)hipEventDestroy(w.ev_panel);
+    if (w.ev_update) (void)hipEventDestroy(w.ev_update);
     if (w.s2) (void)hipStreamDestroy(w.s2);
     w = EigWork();
 }
@@ -1461,8 +1461,9 @@ static hipError_t panel_qr(EigWork &w, double *A, long lda, int N, int pi, hipSt
 }
 
 // Dense -> band.  Look-ahead: once the next panel's b columns have their
-// update, its QR (on w.s2) overlaps the update of the rest of the trailing
-// matrix (on s); s waits for it before the next product with the trailing matrix.
+// update, its QR (on s) overlaps the update of the rest of the trailing matrix
+// (on w.s2); s waits for that update before the next product with the trailing
+// matrix.
 static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
 {
     const int b = w.b;
@@ -1516,16 +1517,17 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
             e = gemm_mfma(GEMM_TALL, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, b, 2 * b,
                           s);
             if (e != hipSuccess) return e;
-            // ... then its QR on s2, overlapping the rest of the update on s
+            // ... then the rest of the update on s2, beside the next panel's QR on s (the QR is on
+            // the critical path; the update ends first, so the wait for it costs nothing)
             if ((e = hipEventRecord(w.ev_cols, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(w.s2, w.ev_cols, 0)) != hipSuccess) return e;
-            e = panel_qr(w, A, lda, N, pi + 1, w.s2);
-            if (e != hipSuccess) return e;
-            if ((e = hipEventRecord(w.ev_panel, w.s2)) != hipSuccess) return e;
             e = gemm_mfma_lower(A_RM{w.VW + (long)b * 2 * b, 2 * b}, B_T{w.WV + (long)b * 2 * b, 2 * b},
-                                EpiAxpbyLower{A22 + (long)b * lda + b, lda, -1.0, 1.0}, n - b, 2 * b, s);
+                                EpiAxpbyLower{A22 + (long)b * lda + b, lda, -1.0, 1.0}, n - b, 2 * b, w.s2);
             if (e != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(s, w.ev_panel, 0)) != hipSuccess) return e;
+            if ((e = hipEventRecord(w.ev_update, w.s2)) != hipSuccess) return e;
+            e = panel_qr(w, A, lda, N, pi + 1, s);
+            if (e != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, w.ev_update, 0)) != hipSuccess) return e;
         } else {
             e = gemm_mfma_lower(A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpbyLower{A22, lda, -1.0, 1.0}, n, 2 * b, s);
             if (e != hipSuccess) return e;
