@@ -304,13 +304,17 @@ __global__ void __launch_bounds__(1024) wy_small_kernel(const double *part, int 
     const int i = tid / b, j = tid - (tid / b) * b;
     const bool act = tid < b * b;
     if (act) {
-        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int g = 0;
-        for (; g + 8 <= nparts; g += 8)
+        // the partials' loads 32 at a time in flight (nparts <= VTY_WG), summed in a fixed order
+        double sum = 0.0;
+#pragma unroll 1
+        for (int g0 = 0; g0 < VTY_WG; g0 += 32) {
+            double v[32];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s[u] += part[(long)(g + u) * b * b + tid];
-        for (; g < nparts; ++g) s[0] += part[(long)g * b * b + tid];
-        M0[i][j] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+            for (int g = 0; g < 32; ++g) v[g] = g0 + g < nparts ? part[(long)(g0 + g) * b * b + tid] : 0.0;
+#pragma unroll
+            for (int g = 0; g < 32; ++g) sum += v[g];
+        }
+        M0[i][j] = sum;
         Ts[i][j] = T[tid];
     }
     __syncthreads();

@@ -357,7 +357,9 @@ reduce_items_kernel(const double *p1, const double *p2, int M, int N, int K, int
     const double *q2 = p2 + ((long)f2 * 128 + r) * N + j;
     const long step = 128L * N;
     double s = 0.0;
+#pragma unroll 8
     for (int u = 0; u < c1; ++u) s += q1[u * step];
+#pragma unroll 8
     for (int u = 0; u < c2; ++u) s += q2[u * step];
     Y[(long)i * ldy + j] = s;
 }
