@@ -127,6 +127,40 @@ def run_path(V, K, m, band, precision, gap_tol, warmup, steps):
     }
 
 
+EIGEN_STAGES = ["dense_to_band", "band_to_tridiag", "bisection", "select_cut_entropy", "inverse_iteration",
+                "orthonormalize", "backtransform_band", "backtransform_dense"]
+
+
+def eigh_comparison(V, K, m, band, warmup):
+    """Timed comparison only: the vendor dense symmetric eigensolver (torch.linalg on ROCm, hipSOLVER /
+    rocSOLVER syevd) on an extended corner C' of the same workload.  Not part of the CTMRG path."""
+    import torch
+    from paper_2004_08669_amd import ctmrg as ct
+
+    g = ct.CTMRG(V, K, m, band=band, precision="fp64")
+    g.step(warmup)
+    g.extend()
+    C = torch.from_numpy(g.get("cext")).cuda()
+    g.close()
+    try:
+        torch.backends.cuda.preferred_linalg_library("cusolver")
+    except Exception:
+        pass
+    lib = str(torch.backends.cuda.preferred_linalg_library())
+    out = {"n": int(C.shape[0]), "torch_linalg_library": lib}
+    for name, fn in (("values", torch.linalg.eigvalsh), ("values_and_vectors", torch.linalg.eigh)):
+        fn(C)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn(C)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"syevd_{name}_ms"] = e0.elapsed_time(e1)
+        print(f"# vendor eigensolver, {name}: {out[f'syevd_{name}_ms']:.1f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +175,8 @@ def main():
                     help="multiplet gap of the cut, the same on both paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=64)
+    ap.add_argument("--compare-eigh", action="store_true",
+                    help="also time the vendor syevd (torch.linalg.eigh on ROCm) on a C' of the same workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the CTMRG step of one (T, m) problem runs on a single MI355X "
@@ -243,6 +279,12 @@ def main():
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V, K, args.cpu_sample_m, m)
+    if args.compare_eigh:
+        r64 = runs.get("fp64", head)
+        cmp = eigh_comparison(V, K, m, args.band, args.warmup)
+        cmp["own_eigensolver_ms"] = sum(r64["stage_ms"][k] for k in EIGEN_STAGES)
+        cmp["own_eigensolver_computes"] = "all eigenvalues and the m leading eigenvectors"
+        out["eigh_comparison"] = cmp
     print(json.dumps(out), flush=True)
 
 
