@@ -375,6 +375,39 @@ CTMRG_DEVINL void lane_sync()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// A double moved across lanes by one DPP pattern (both halves with the same control).
+template <int CTRL>
+CTMRG_DEVINL double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// Sum over the 64 lanes of a wave, the same value in every lane: inside each row of
+// 16 lanes by DPP (partner lane xor 1, xor 2, then the mirror images within 8 and
+// within 16 lanes), then across the rows by two shuffles.  Every lane adds the same
+// two operands at every level, so all lanes hold bitwise the same sum.
+CTMRG_DEVINL double wave_sum_dpp(double v)
+{
+    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Sum of RPL products x[i] y[i] in four independent chains.
+template <int RPL>
+CTMRG_DEVINL double dot4(const double *x, const double *y)
+{
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) a[i & 3] = fma(x[i], y[i], a[i & 3]);
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
 template <int B>
 CTMRG_DEVINL double col_sum(double x)  // over the lanes sharing lane % B
 {
@@ -427,10 +460,12 @@ CTMRG_DEVINL void bulge_step_pre(double *band, int N, int j, int t, double *refl
     const double alpha = __shfl(L[0], 0, 64);
     double part = 0.0;
     if (c == 0) {
+        double Lm[RPL];
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) part += (rb + i >= 1) ? L[i] * L[i] : 0.0;
+        for (int i = 0; i < RPL; ++i) Lm[i] = (rb + i >= 1) ? L[i] : 0.0;
+        part = dot4<RPL>(Lm, Lm);
     }
-    const double xs = wave_sum(part);
+    const double xs = wave_sum_dpp(part);
     double beta, tau, scale;
     if (xs == 0.0) { beta = alpha; tau = 0.0; scale = 0.0; }
     else {
@@ -453,21 +488,21 @@ CTMRG_DEVINL void bulge_step_pre(double *band, int N, int j, int t, double *refl
     const double vc = vs[c];
     // left block, columns >= 1: L[:,c] -= tau v (v^T L[:,c])
     {
-        double sdot = 0.0;
+        double vl[RPL];
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) sdot += vs[rb + i] * L[i];
-        const double wc = tau * col_sum<B>(sdot);
+        for (int i = 0; i < RPL; ++i) vl[i] = vs[rb + i];
+        const double wc = tau * col_sum<B>(dot4<RPL>(vl, L));
         if (c >= 1) {
 #pragma unroll
             for (int i = 0; i < RPL; ++i) L[i] -= wc * vs[rb + i];
         }
     }
     // diagonal block: p = tau D v, k = tau v^T p / 2, w = p - k v, D -= v w^T + w v^T
-    double pd = 0.0;
+    double vr[RPL];
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) pd += D[i] * vs[rb + i];
-    const double pc = tau * col_sum<B>(pd);
-    const double kk = 0.5 * tau * wave_sum((h == 0 && c < len) ? vc * pc : 0.0);
+    for (int i = 0; i < RPL; ++i) vr[i] = vs[rb + i];
+    const double pc = tau * col_sum<B>(dot4<RPL>(D, vr));
+    const double kk = 0.5 * tau * wave_sum_dpp((h == 0 && c < len) ? vc * pc : 0.0);
     const double wc = pc - kk * vc;
     if (h == 0) ws[c] = (c < len) ? wc : 0.0;
     lane_sync();
@@ -476,10 +511,7 @@ CTMRG_DEVINL void bulge_step_pre(double *band, int N, int j, int t, double *refl
     // block below, held transposed (lane (c, h) has row c, columns rb..rb+RPL-1):
     // y = B v, B -= tau y v^T
     {
-        double yp = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) yp += Bm[i] * vs[rb + i];
-        const double ty = tau * col_sum<B>(yp);
+        const double ty = tau * col_sum<B>(dot4<RPL>(Bm, vr));
 #pragma unroll
         for (int i = 0; i < RPL; ++i) Bm[i] -= ty * vs[rb + i];
     }
