@@ -473,6 +473,10 @@ CTMRG_DEVINL void bulge_step_pre(double *band, int N, int j, int t, double *refl
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
     }
+    // Every band load has arrived before the first store of the step: the vector
+    // memory counter covers loads and stores alike, so a late wait for a load would
+    // also wait for the reflector stores issued before it.
+    __builtin_amdgcn_s_waitcnt(0);
     if (c == 0) {
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
