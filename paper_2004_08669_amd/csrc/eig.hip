@@ -863,13 +863,21 @@ post_eigen_kernel(const double *ev, int N, int m, double gap_tol, double rank_to
 // can converge to the same direction; cluster_orth_kernel separates them.
 constexpr int IV_CH = 16;
 
+// The vector memory counter covers loads and stores alike, so a wait for loads
+// issued after stores also waits for those stores.  The kernel keeps the two
+// apart: the factorization reads d and e from LDS (staged IV_LDS rows at a time,
+// one global wait per stage), and each chunk of a triangular solve issues its
+// loads before it stores the previous chunk's results (held in registers).
+constexpr int IV_LDS = 2048;
+
 __global__ void __launch_bounds__(64)
 invit_kernel(const double *d, const double *e, int N, const double *selval, int me, double *ZT, int ldz, double *lu,
              int *ipiv, const double *bounds, unsigned *err)
 {
+    __shared__ double sd[IV_LDS], se[IV_LDS + 1];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int nth = gridDim.x * blockDim.x;
-    if (c >= me) return;
+    const bool act = c < me;
     const double tn = bounds[3];
     const double pivmin = fmax(DBL_EPSILON * tn, DBL_MIN);
 #define DL(i) lu[((long)0 * N + (i)) * nth + c]
@@ -878,26 +886,23 @@ invit_kernel(const double *d, const double *e, int N, const double *selval, int 
 #define DU2(i) lu[((long)3 * N + (i)) * nth + c]
 #define X(i) lu[((long)4 * N + (i)) * nth + c]
 #define IP(i) ipiv[(long)(i) * nth + c]
-    const double lam = selval[c];
+    const double lam = act ? selval[c] : 0.0;
     // ---- LU with partial pivoting of T - lam I (rows i, i+1 swapped when |e_i| > |pivot|)
     double ddi = d[0] - lam, dui = (N > 1) ? e[0] : 0.0;
-    for (int i0 = 0; i0 < N - 1; i0 += IV_CH) {
-        const int nI = min(IV_CH, N - 1 - i0);
-        double ec[IV_CH], dc[IV_CH], en[IV_CH];
-#pragma unroll
-        for (int u = 0; u < IV_CH; ++u) {
-            const int i = i0 + (u < nI ? u : 0);
-            ec[u] = e[i];
-            dc[u] = d[i + 1];
-            en[u] = (i < N - 2) ? e[i + 1] : 0.0;
+    for (int base = 0; base < N - 1; base += IV_LDS) {
+        const int cnt = min(IV_LDS, N - 1 - base);
+        __syncthreads();
+        for (int u = threadIdx.x; u <= cnt; u += blockDim.x) {
+            if (u < cnt) sd[u] = d[base + u + 1];
+            se[u] = (base + u < N - 1) ? e[base + u] : 0.0;
         }
-#pragma unroll
-        for (int u = 0; u < IV_CH; ++u) {
-            if (u < nI) {
-                const int i = i0 + u;
-                const double li = ec[u];
-                const double dn = dc[u] - lam;
-                const double dun = en[u];
+        __syncthreads();
+        if (act) {
+            for (int u = 0; u < cnt; ++u) {
+                const int i = base + u;
+                const double li = se[u];
+                const double dn = sd[u] - lam;
+                const double dun = (i < N - 2) ? se[u + 1] : 0.0;
                 if (fabs(ddi) >= fabs(li)) {
                     const double piv = (fabs(ddi) < pivmin) ? (ddi < 0.0 ? -pivmin : pivmin) : ddi;
                     const double f = li / piv;
@@ -913,6 +918,7 @@ invit_kernel(const double *d, const double *e, int N, const double *selval, int 
             }
         }
     }
+    if (!act) return;
     if (fabs(ddi) < pivmin) ddi = (ddi < 0.0 ? -pivmin : pivmin);
     DD(N - 1) = ddi;
     // ---- start vector (counter-based random numbers)
@@ -926,22 +932,31 @@ invit_kernel(const double *d, const double *e, int N, const double *selval, int 
     for (int it = 0; it < 3; ++it) {
         // forward: unit lower factor with row interchanges, applied to sc * X
         double xi = X(0) * sc;
-        for (int i0 = 0; i0 < N - 1; i0 += IV_CH) {
-            const int nI = min(IV_CH, N - 1 - i0);
-            double xn[IV_CH], dl[IV_CH], out[IV_CH];
-            int ip[IV_CH];
+        {
+            double out[IV_CH];
+            int pend_i0 = -1, pend_n = 0;  // the previous chunk's results, not yet stored
+            for (int i0 = 0; i0 < N - 1; i0 += IV_CH) {
+                const int nI = min(IV_CH, N - 1 - i0);
+                double xn[IV_CH], dl[IV_CH];
+                int ip[IV_CH];
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) { xn[u] = X(i0 + u + 1) * sc; dl[u] = DL(i0 + u); ip[u] = IP(i0 + u); }
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < pend_n) X(pend_i0 + u) = out[u];
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) {
+                        if (ip[u] == 0) { out[u] = xi; xi = xn[u] - dl[u] * xi; }
+                        else { out[u] = xn[u]; xi = xi - dl[u] * xn[u]; }
+                    }
+                pend_i0 = i0;
+                pend_n = nI;
+            }
 #pragma unroll
             for (int u = 0; u < IV_CH; ++u)
-                if (u < nI) { xn[u] = X(i0 + u + 1) * sc; dl[u] = DL(i0 + u); ip[u] = IP(i0 + u); }
-#pragma unroll
-            for (int u = 0; u < IV_CH; ++u)
-                if (u < nI) {
-                    if (ip[u] == 0) { out[u] = xi; xi = xn[u] - dl[u] * xi; }
-                    else { out[u] = xn[u]; xi = xi - dl[u] * xn[u]; }
-                }
-#pragma unroll
-            for (int u = 0; u < IV_CH; ++u)
-                if (u < nI) X(i0 + u) = out[u];
+                if (u < pend_n) X(pend_i0 + u) = out[u];
         }
         X(N - 1) = xi;
         // backward: upper factor with two superdiagonals; accumulate the norm
@@ -956,24 +971,33 @@ invit_kernel(const double *d, const double *e, int N, const double *selval, int 
             x2 = x1;
             x1 = x0;
         }
-        for (int i0 = N - 3; i0 >= 0; i0 -= IV_CH) {
-            const int nI = min(IV_CH, i0 + 1);
-            double xv[IV_CH], du[IV_CH], du2[IV_CH], dd[IV_CH];
+        {
+            double res[IV_CH];
+            int pend_i0 = -1, pend_n = 0;
+            for (int i0 = N - 3; i0 >= 0; i0 -= IV_CH) {
+                const int nI = min(IV_CH, i0 + 1);
+                double xv[IV_CH], du[IV_CH], du2[IV_CH], dd[IV_CH];
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) { xv[u] = X(i0 - u); du[u] = DU(i0 - u); du2[u] = DU2(i0 - u); dd[u] = DD(i0 - u); }
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < pend_n) X(pend_i0 - u) = res[u];
+#pragma unroll
+                for (int u = 0; u < IV_CH; ++u)
+                    if (u < nI) {
+                        const double xnew = (xv[u] - du[u] * x1 - du2[u] * x2) / dd[u];
+                        x2 = x1;
+                        x1 = xnew;
+                        res[u] = xnew;
+                        nrm2 += xnew * xnew;
+                    }
+                pend_i0 = i0;
+                pend_n = nI;
+            }
 #pragma unroll
             for (int u = 0; u < IV_CH; ++u)
-                if (u < nI) { xv[u] = X(i0 - u); du[u] = DU(i0 - u); du2[u] = DU2(i0 - u); dd[u] = DD(i0 - u); }
-#pragma unroll
-            for (int u = 0; u < IV_CH; ++u)
-                if (u < nI) {
-                    const double xnew = (xv[u] - du[u] * x1 - du2[u] * x2) / dd[u];
-                    x2 = x1;
-                    x1 = xnew;
-                    xv[u] = xnew;
-                    nrm2 += xnew * xnew;
-                }
-#pragma unroll
-            for (int u = 0; u < IV_CH; ++u)
-                if (u < nI) X(i0 - u) = xv[u];
+                if (u < pend_n) X(pend_i0 - u) = res[u];
         }
         if (!(nrm2 > 0.0) || !isfinite(nrm2)) {
             raise_error(err, KERR_NONFINITE);
@@ -981,8 +1005,28 @@ invit_kernel(const double *d, const double *e, int N, const double *selval, int 
         }
         sc = 1.0 / sqrt(nrm2);
     }
-#pragma unroll 16
-    for (int i = 0; i < N; ++i) ZT[(long)i * ldz + c] = X(i) * sc;
+    {
+        double v[IV_CH];
+        int pend_i0 = -1, pend_n = 0;
+        for (int i0 = 0; i0 < N; i0 += IV_CH) {
+            const int nI = min(IV_CH, N - i0);
+            double xv[IV_CH];
+#pragma unroll
+            for (int u = 0; u < IV_CH; ++u)
+                if (u < nI) xv[u] = X(i0 + u);
+#pragma unroll
+            for (int u = 0; u < IV_CH; ++u)
+                if (u < pend_n) ZT[(long)(pend_i0 + u) * ldz + c] = v[u];
+#pragma unroll
+            for (int u = 0; u < IV_CH; ++u)
+                if (u < nI) v[u] = xv[u] * sc;
+            pend_i0 = i0;
+            pend_n = nI;
+        }
+#pragma unroll
+        for (int u = 0; u < IV_CH; ++u)
+            if (u < pend_n) ZT[(long)(pend_i0 + u) * ldz + c] = v[u];
+    }
 #undef DL
 #undef DD
 #undef DU
