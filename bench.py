@@ -168,7 +168,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--m", type=int, default=512)
     ap.add_argument("--T", type=float, default=0.4398)
-    ap.add_argument("--band", type=int, default=32)
+    ap.add_argument("--band", type=int, default=16)
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both",
                     help="both: time the mixed path (the headline value) and the FP64 path")
     ap.add_argument("--gap-tol", type=float, default=1e-6,

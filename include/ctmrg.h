@@ -73,7 +73,7 @@ typedef struct {
     int precision;        /* ctmrg_precision of the contractions; the eigensolver is always FP64 */
     int bc;               /* ctmrg_bc: fixed (all boundary spins = boundary_spin) or free      */
     int boundary_spin;    /* vertex index of the fixed boundary spin (the paper's s = 1)       */
-    int band;             /* eigensolver half-bandwidth: 16 or 32 (default)                    */
+    int band;             /* eigensolver half-bandwidth: 16 (default) or 32                    */
     double gap_tol;       /* multiplet gap, relative to |lambda_1| (default 1e-10; >= 1e-6 for FP32) */
     double rank_tol;      /* eigenvalues with |l| <= rank_tol |l_1| are never kept (1e-13)     */
     void *hip_stream;     /* hipStream_t to run on; NULL = a stream owned by the context       */
@@ -94,7 +94,7 @@ typedef struct {
 
 typedef struct ctmrg_ctx ctmrg_ctx;
 
-/* Defaults: FP64, fixed boundary, boundary_spin 0, band 32, gap_tol 1e-10, rank_tol 1e-13. */
+/* Defaults: FP64, fixed boundary, boundary_spin 0, band 16, gap_tol 1e-10, rank_tol 1e-13. */
 ctmrg_status ctmrg_default_options(ctmrg_options *opt);
 
 /* Create a context for q spins (vertex_vectors: q x dim row-major unit vectors,

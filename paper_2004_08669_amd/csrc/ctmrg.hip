@@ -270,7 +270,7 @@ ctmrg_status ctmrg_default_options(ctmrg_options *opt)
     opt->precision = CTMRG_FP64;
     opt->bc = CTMRG_BC_FIXED;
     opt->boundary_spin = 0;
-    opt->band = 32;
+    opt->band = 16;
     opt->gap_tol = 1e-10;
     opt->rank_tol = 1e-13;
     opt->hip_stream = nullptr;
@@ -598,7 +598,7 @@ ctmrg_status ctmrg_eigh_topk(int n, const double *A, int k, int band, double *ev
                              double *evecs)
 {
     if (n < 1 || k < 1 || k > n || !A || !evals || !kept_vals || !evecs) return CTMRG_E_INVALID_ARG;
-    if (band == 0) band = 32;
+    if (band == 0) band = 16;
     if (!valid_band(band)) return CTMRG_E_INVALID_ARG;
     ctmrg_ctx tmp;
     ctmrg_status st = check_device(&tmp);

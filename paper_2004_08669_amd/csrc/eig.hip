@@ -1552,6 +1552,7 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
 {
     const int b = w.b;
     const int np = num_panels(N, b);
+    const GemmShape tall = b == 16 ? GEMM_TALL16 : GEMM_TALL;  // products with b output columns
     hipError_t e;
     if (np == 0) return hipSuccess;
     e = panel_qr(w, A, lda, N, 0, s);
@@ -1574,12 +1575,24 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
             }
             if ((size_t)(n1 + n2) * 128 * b > w.splitk_elems) return hipErrorInvalidValue;
             double *p1 = w.splitk, *p2 = w.splitk + (long)n1 * 128 * b;
-            if (n1 > 0)
-                hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 32, 4, 1, A_LoItems, B_RM, EpiItems>), dim3(n1), dim3(256),
-                                   0, s, A_LoItems{{A22, lda}}, B_RM{Vp, b}, EpiItems{p1, b}, n, b, n, ch);
-            if (n2 > 0)
-                hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 32, 4, 1, A_SLoTItems, B_RM, EpiItems>), dim3(n2),
-                                   dim3(256), 0, s, A_SLoTItems{{A22, lda}}, B_RM{Vp, b}, EpiItems{p2, b}, n, b, n, ch);
+            // (the output tile is b columns wide: a wider one would only add matrix-core work)
+            if (b == 16) {
+                if (n1 > 0)
+                    hipLaunchKernelGGL((gemm_mfma_kernel<128, 16, 32, 4, 1, A_LoItems, B_RM, EpiItems>), dim3(n1),
+                                       dim3(256), 0, s, A_LoItems{{A22, lda}}, B_RM{Vp, b}, EpiItems{p1, b}, n, b, n, ch);
+                if (n2 > 0)
+                    hipLaunchKernelGGL((gemm_mfma_kernel<128, 16, 32, 4, 1, A_SLoTItems, B_RM, EpiItems>), dim3(n2),
+                                       dim3(256), 0, s, A_SLoTItems{{A22, lda}}, B_RM{Vp, b}, EpiItems{p2, b}, n, b, n,
+                                       ch);
+            } else {
+                if (n1 > 0)
+                    hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 32, 4, 1, A_LoItems, B_RM, EpiItems>), dim3(n1),
+                                       dim3(256), 0, s, A_LoItems{{A22, lda}}, B_RM{Vp, b}, EpiItems{p1, b}, n, b, n, ch);
+                if (n2 > 0)
+                    hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 32, 4, 1, A_SLoTItems, B_RM, EpiItems>), dim3(n2),
+                                       dim3(256), 0, s, A_SLoTItems{{A22, lda}}, B_RM{Vp, b}, EpiItems{p2, b}, n, b, n,
+                                       ch);
+            }
             hipLaunchKernelGGL((reduce_items_kernel<A_LoItems, A_SLoTItems>), dim3(ceil_div(128 * b, 256), nt),
                                dim3(256), 0, s, p1, p2, n, b, n, ch, w.Y, (long)b);
             if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1592,14 +1605,13 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
             else
                 hipLaunchKernelGGL(vty_partial_kernel<16>, dim3(gv), dim3(256), 0, s, Vp, w.Y, n, w.splitk);
             hipLaunchKernelGGL(wy_small_kernel, dim3(1), dim3(1024), 0, s, w.splitk, gv, Tp, b, w.sm);
-            e = gemm_mfma(GEMM_TALL, A_YV{w.Y, Vp, b}, B_RM{w.sm, b}, EpiVW{Vp, w.VW, w.WV, b}, n, b, 2 * b, s);
+            e = gemm_mfma(tall, A_YV{w.Y, Vp, b}, B_RM{w.sm, b}, EpiVW{Vp, w.VW, w.WV, b}, n, b, 2 * b, s);
             if (e != hipSuccess) return e;
         }
         // A22 -= [V|W] [W|V]^T on the lower triangle (the only part later read)
         if (pi + 1 < np) {
             // the next panel's columns first (rows 0..n-1, columns 0..b-1 of A22) ...
-            e = gemm_mfma(GEMM_TALL, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, b, 2 * b,
-                          s);
+            e = gemm_mfma(tall, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, b, 2 * b, s);
             if (e != hipSuccess) return e;
             // ... then the rest of the update on s2, beside the next panel's QR on s (the QR is on
             // the critical path; the update ends first, so the wait for it costs nothing)

@@ -133,6 +133,11 @@ struct EpiStoreF {  // C = alpha * acc, rounded to FP32
 struct EpiAxpbyLower {  // C = alpha * acc + beta * C on the tiles on or below the diagonal only
     double *p; long ld; double alpha, beta;
     static constexpr bool kLowerTiles = true;
+    // C is read before the K loop (the product's inner dimension is short, so a read
+    // issued in the epilogue would not overlap any matrix-core work)
+    static constexpr bool kPrefetchC = true;
+    __device__ double load(int i, int j) const { return p[(long)i * ld + j]; }
+    __device__ void store(int i, int j, double v, double c) const { p[(long)i * ld + j] = alpha * v + beta * c; }
     __device__ void operator()(int i, int j, double v, int) const
     {
         double *c = p + (long)i * ld + j;
@@ -158,6 +163,8 @@ template <class T, class = void> struct has_items : std::false_type {};
 template <class T> struct has_items<T, std::void_t<decltype(T::kItems)>> : std::true_type {};
 template <class T, class = void> struct lower_tiles : std::false_type {};
 template <class T> struct lower_tiles<T, std::void_t<decltype(T::kLowerTiles)>> : std::true_type {};
+template <class T, class = void> struct prefetch_c : std::false_type {};
+template <class T> struct prefetch_c<T, std::void_t<decltype(T::kPrefetchC)>> : std::true_type {};
 
 // ---------------------------------------------------------------- MFMA step per element type
 template <class T> struct Mfma;
@@ -230,6 +237,20 @@ gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = MF::zero();
+    // C of this lane's outputs, read ahead of the K loop when the epilogue asks for it
+    double cpre[prefetch_c<EPI>::value ? TM : 1][prefetch_c<EPI>::value ? TN : 1][4];
+    if constexpr (prefetch_c<EPI>::value) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + (wm * TM + i) * 16 + MF::row(lane, r);
+                    const int col = n0 + (wn * TN + j) * 16 + (lane & 15);
+                    cpre[i][j][r] = (row < M && col < N) ? epi.load(row, col) : 0.0;
+                }
+    }
 
     // Each thread holds its share of the next K slice in registers while the
     // matrix cores work on the current one from LDS (one slice of prefetch).
@@ -305,7 +326,10 @@ gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + (wm * TM + i) * 16 + MF::row(lane, r);
                 const int col = n0 + (wn * TN + j) * 16 + (lane & 15);
-                if (row < M && col < N) epi(row, col, (double)acc[i][j][r], split);
+                if (row < M && col < N) {
+                    if constexpr (prefetch_c<EPI>::value) epi.store(row, col, (double)acc[i][j][r], cpre[i][j][r]);
+                    else epi(row, col, (double)acc[i][j][r], split);
+                }
             }
 }
 
@@ -368,6 +392,7 @@ reduce_items_kernel(const double *p1, const double *p2, int M, int N, int K, int
 enum GemmShape {
     GEMM_LARGE,   // 128 x 128 tile, 2 x 2 waves
     GEMM_TALL,    // 128 x 32 tile, 4 x 1 waves (outputs with few columns)
+    GEMM_TALL16,  // 128 x 16 tile, 4 x 1 waves (outputs of 16 columns)
     GEMM_MIX,     // 80 x 128 tile, 1 x 4 waves (the q^2 = 400 rows of the W-mix)
     GEMM_SMALL,   // 64 x 64 tile, 2 x 2 waves
 };
@@ -384,6 +409,10 @@ hipError_t gemm_mfma(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K
     case GEMM_TALL:
         hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EPI>),
                            dim3(ceil_div(M, 128), ceil_div(N, 32), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
+        break;
+    case GEMM_TALL16:
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 16, 16, 4, 1, LA, LB, EPI>),
+                           dim3(ceil_div(M, 128), ceil_div(N, 16), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_MIX:
         hipLaunchKernelGGL((gemm_mfma_kernel<80, 128, 16, 1, 4, LA, LB, EPI>),

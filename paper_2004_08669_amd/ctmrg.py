@@ -140,7 +140,7 @@ def default_options() -> Options:
     return o
 
 
-def workspace_size(q: int, m: int, band: int = 32) -> int:
+def workspace_size(q: int, m: int, band: int = 16) -> int:
     o = default_options()
     o.band = band
     n = ctypes.c_size_t(0)
@@ -166,7 +166,7 @@ def eigh_topk(A: np.ndarray, k: int, band: int = 0):
 class CTMRG:
     """A CTMRG context on the current GPU (see include/ctmrg.h)."""
 
-    def __init__(self, V, K: float, m: int, bc: str = "fixed", boundary_spin: int = 0, band: int = 32,
+    def __init__(self, V, K: float, m: int, bc: str = "fixed", boundary_spin: int = 0, band: int = 16,
                  gap_tol: float | None = None, rank_tol: float = 1e-13, precision: str = "fp64", stream=None):
         lib = load()
         self._lib = lib

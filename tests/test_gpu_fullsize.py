@@ -1,4 +1,4 @@
-"""The FP64 path at the size the bench times: q = 20, m = 512 (C' 10240 x 10240), band 32.
+"""The FP64 path at the size the bench times: q = 20, m = 512 (C' 10240 x 10240), band 16.
 
 The oracle cannot run a step at this size in a test, so the checks are the outputs it can
 compute one by one and properties that hold at any size:

@@ -56,7 +56,8 @@ def test_extension_matches_oracle(m, seed):
 
 # --------------------------------------------------------------------------- eigensolver
 
-@pytest.mark.parametrize("n,k,band,seed", [(40, 12, 32, 0), (160, 24, 32, 1), (333, 40, 32, 2), (257, 30, 16, 3)])
+@pytest.mark.parametrize("n,k,band,seed", [(40, 12, 16, 0), (160, 24, 16, 1), (333, 40, 16, 2), (257, 30, 16, 3),
+                                         (160, 24, 32, 4), (333, 40, 32, 5)])
 def test_eigensolver_matches_jacobi(n, k, band, seed):
     ct = _lib()
     lam = I.graded_spectrum(seed, n, ratio=0.9)
