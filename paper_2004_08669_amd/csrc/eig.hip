@@ -1214,7 +1214,7 @@ bt2_apply_kernel(double *Z, int ldz, int N, int ncols, int Tmax, int nJ, int wav
 }
 
 // ============================================================================
-// Back-transform of stage 1: panels grouped BT1_G at a time
+// Back-transform of stage 1: panels grouped 128 columns (128 / b panels) at a time
 // ============================================================================
 //
 // Group k holds panels p = k G .. k G + G - 1 (fewer, or none, at the end); their
@@ -1222,19 +1222,19 @@ bt2_apply_kernel(double *Z, int ldz, int N, int ncols, int Tmax, int nJ, int wav
 // p + j starts j b rows below panel p) and T_G the compact-WY factor of the G b
 // reflectors in order: T[0:i, i] = -tau_i T[0:i, 0:i] (V_G^T V_G)[0:i, i].  One
 // group then costs one pass of three GEMMs over Z instead of G passes.
-constexpr int BT1_G = 4;
+__host__ __device__ constexpr int bt1_g(int b) { return 128 / b; }
 
 // V_G as a function of (row r from the first panel's first row, column c).
 template <int B>
 struct VGroup {
-    const double *V[BT1_G];  // explicit V of each panel (n_j x B, row-major), or null
+    const double *V[bt1_g(B)];  // explicit V of each panel (n_j x B, row-major), or null
     int n0;                  // rows of the first panel
     __device__ double at(int r, int c) const
     {
         const int j = c / B, lc = c % B, lr = r - j * B;
         const double *v = V[0];
 #pragma unroll
-        for (int u = 1; u < BT1_G; ++u)
+        for (int u = 1; u < bt1_g(B); ++u)
             if (j == u) v = V[u];
         return (v != nullptr && lr >= 0 && lr < n0 - j * B) ? v[(long)lr * B + lc] : 0.0;
     }
@@ -1263,12 +1263,12 @@ template <int B>
 __global__ void __launch_bounds__(256) bt1_gram_kernel(const double *Vx, int N, int np, double *gram)
 {
     using MF = Mfma<double>;
-    constexpr int GB = BT1_G * B, GT = GB / 16, TR = GT / 4, U = 4;
+    constexpr int GB = bt1_g(B) * B, GT = GB / 16, TR = GT / 4, U = 4;
     static_assert(TR * 4 == GT, "four waves");
-    const int grp = blockIdx.x, chunk = blockIdx.y, p0 = grp * BT1_G;
+    const int grp = blockIdx.x, chunk = blockIdx.y, p0 = grp * bt1_g(B);
     VGroup<B> vg;
     long off = panel_v_offset(N, B, p0);
-    for (int j = 0; j < BT1_G; ++j) {
+    for (int j = 0; j < bt1_g(B); ++j) {
         vg.V[j] = (p0 + j < np) ? Vx + off : nullptr;
         off += (long)(N - (p0 + j + 1) * B) * B;
     }
@@ -1317,11 +1317,11 @@ __global__ void __launch_bounds__(256) bt1_gram_kernel(const double *Vx, int N, 
 template <int B>
 __global__ void __launch_bounds__(256) bt1_tg_kernel(const double *gram, const double *tau1, int np, double *TG)
 {
-    constexpr int GB = BT1_G * B;
+    constexpr int GB = bt1_g(B) * B;
     extern __shared__ double sh[];
     double *T = sh;              // [GB][GB + 1]
     double *gc = T + GB * (GB + 1);  // [GB]
-    const int grp = blockIdx.x, p0 = grp * BT1_G;
+    const int grp = blockIdx.x, p0 = grp * bt1_g(B);
     const double *G = gram + (long)grp * BT1_RS * GB * GB;
     const int tid = threadIdx.x;
     for (int idx = tid; idx < GB * (GB + 1); idx += 256) T[idx] = 0.0;
@@ -1408,9 +1408,9 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax);
     s += align_up(sizeof(double) * (size_t)nJ * Tmax * b * b);
-    s += align_up(sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_RS * BT1_G * b * BT1_G * b + 8);
-    s += align_up(sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_G * b * BT1_G * b + 8);
-    s += align_up(sizeof(double) * 2 * (size_t)BT1_G * b * kmax);
+    s += align_up(sizeof(double) * (size_t)ceil_div(np, bt1_g(b)) * BT1_RS * bt1_g(b) * b * bt1_g(b) * b + 8);
+    s += align_up(sizeof(double) * (size_t)ceil_div(np, bt1_g(b)) * bt1_g(b) * b * bt1_g(b) * b + 8);
+    s += align_up(sizeof(double) * 2 * (size_t)bt1_g(b) * b * kmax);
     s += 4 * align_up(sizeof(double) * (size_t)Nmax);
     s += align_up(sizeof(double) * 4 * BIS_SLICE);
     s += 2 * align_up(sizeof(double) * (size_t)Nmax * kmax);
@@ -1451,9 +1451,9 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.refl, sizeof(double) * (size_t)Nmax * w.Tmax * b},
         {(void **)&w.rtau, sizeof(double) * (size_t)Nmax * w.Tmax},
         {(void **)&w.T2, sizeof(double) * (size_t)w.nJmax * w.Tmax * b * b},
-        {(void **)&w.bt1_gram, sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_RS * BT1_G * b * BT1_G * b + 8},
-        {(void **)&w.bt1_T, sizeof(double) * (size_t)ceil_div(np, BT1_G) * BT1_G * b * BT1_G * b + 8},
-        {(void **)&w.bt1_W, sizeof(double) * 2 * (size_t)BT1_G * b * kmax},
+        {(void **)&w.bt1_gram, sizeof(double) * (size_t)ceil_div(np, bt1_g(b)) * BT1_RS * bt1_g(b) * b * bt1_g(b) * b + 8},
+        {(void **)&w.bt1_T, sizeof(double) * (size_t)ceil_div(np, bt1_g(b)) * bt1_g(b) * b * bt1_g(b) * b + 8},
+        {(void **)&w.bt1_W, sizeof(double) * 2 * (size_t)bt1_g(b) * b * kmax},
         {(void **)&w.d, sizeof(double) * (size_t)Nmax},
         {(void **)&w.e, sizeof(double) * (size_t)Nmax},
         {(void **)&w.e2, sizeof(double) * (size_t)Nmax},
@@ -1477,7 +1477,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
     }
     (void)hipMemset(w.part, 0xFF, sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b)));  // all slots empty
     (void)hipMemset(w.err, 0, 64);
-    const size_t tg_smem = sizeof(double) * ((size_t)BT1_G * b * (BT1_G * b + 1) + BT1_G * b);
+    const size_t tg_smem = sizeof(double) * ((size_t)bt1_g(b) * b * (bt1_g(b) * b + 1) + bt1_g(b) * b);
     hipError_t e = hipFuncSetAttribute(b == 32 ? (const void *)bt1_tg_kernel<32> : (const void *)bt1_tg_kernel<16>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)tg_smem);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
@@ -1687,11 +1687,11 @@ hipError_t eig_post(EigWork &w, int N, int m, double gap_tol, double rank_tol, c
 template <int B>
 static hipError_t bt1_apply_group(EigWork &w, double *Z, int ldz, int N, int me, int np, int k, hipStream_t s)
 {
-    constexpr int GB = BT1_G * B;
-    const int p0 = k * BT1_G, r0 = p0 * B + B, n = N - r0;
+    constexpr int GB = bt1_g(B) * B;
+    const int p0 = k * bt1_g(B), r0 = p0 * B + B, n = N - r0;
     VGroup<B> vg;
     long off = panel_v_offset(N, B, p0);
-    for (int j = 0; j < BT1_G; ++j) {
+    for (int j = 0; j < bt1_g(B); ++j) {
         vg.V[j] = (p0 + j < np) ? w.Vx + off : nullptr;
         off += (long)(N - (p0 + j + 1) * B) * B;
     }
@@ -1753,10 +1753,10 @@ hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const do
         }
     }
     mark(w, MK_BT2, s);
-    // stage-1 back-transform, groups of BT1_G panels, last group first
+    // stage-1 back-transform, groups of bt1_g(b) panels, last group first
     const int np = num_panels(N, b);
     if (np > 0) {
-        const int ngr = ceil_div(np, BT1_G), GB = BT1_G * b;
+        const int ngr = ceil_div(np, bt1_g(b)), GB = bt1_g(b) * b;
         if (b == 32) {
             hipLaunchKernelGGL(bt1_gram_kernel<32>, dim3(ngr, BT1_RS), dim3(256), 0, s, w.Vx, N, np, w.bt1_gram);
             hipLaunchKernelGGL(bt1_tg_kernel<32>, dim3(ngr), dim3(256), sizeof(double) * (GB * (GB + 1) + GB), s,
