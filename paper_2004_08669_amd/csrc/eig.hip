@@ -1544,25 +1544,25 @@ static hipError_t panel_qr(EigWork &w, double *A, long lda, int N, int pi, hipSt
     return e;
 }
 
-// Y = A22 V in one pass over the lower triangle of A22.  The work items are those of
-// A_LoItems: row tile I (rows R = [128 I, 128 I + 128)) and a chunk [k0, k0 + ch) of
-// its K range [0, min(n, 128 I + 128)).  From each 128 x 32 slice of A in LDS an item
-// forms both its rows' part L[R, slice] V[slice] (accumulated over the chunk into P1,
-// 128 x B per item) and the mirrored part (A[R, slice] with i > k)^T V[R] of the
-// slice's rows (written to P2, ch x B per item).  Row r of Y is then the sum of the
-// P1 rows of its tile's items plus, for every tile I' >= tile(r), the P2 row of the
-// item (I', chunk of r) (ysym_reduce_kernel).
-template <int B>
+// Y = A22 V in one pass over the lower triangle of A22 (b = 16).  The work items are
+// those of A_LoItems: row tile I (rows R = [128 I, 128 I + 128)) and a chunk
+// [k0, k0 + ch) of its K range [0, min(n, 128 I + 128)).  From each 128 x 16 slice of
+// A in LDS an item forms both its rows' part L[R, slice] V[slice] (accumulated over the
+// chunk into P1, 128 x 16 per item) and the mirrored part (A[R, slice] with i > k)^T V[R]
+// of the slice's rows (written to P2, ch x 16 per item).  Row r of Y is then the sum of
+// the P1 rows of its tile's items plus, for every tile I' >= tile(r), the P2 row of the
+// item (I', chunk of r) (ysym_reduce_kernel).  Wave w forms P1 for tile rows
+// 32 w .. 32 w + 31 and the mirrored product over those same rows, whose V it keeps in
+// registers as matrix-core B fragments for the whole item.
 __global__ void __launch_bounds__(256)
 ysym_items_kernel(const double *A, long lda, const double *V, int n, int ch, double *P1, double *P2)
 {
     using MF = Mfma<double>;
-    constexpr int BM = 128, BK = 32, TN = B / 16;
-    constexpr int PA = BM * BK / 256, PB = (BK * B + 255) / 256;
-    __shared__ double As[BK][BM + 1];   // As[kk][mm] = A[m0 + mm][k0 + kk] where k <= i, else 0
-    __shared__ double Bs[BK][B + 1];    // V of the slice's rows
-    __shared__ double VI[BM][B + 1];    // V of the tile's rows
-    __shared__ double red[2][16][B + 1];
+    constexpr int B = 16, BM = 128, BK = 16;
+    constexpr int PA = BM * BK / 256;  // 8
+    __shared__ double As[BK][BM + 1];  // As[kk][mm] = A[m0 + mm][k0 + kk] where k <= i, else 0
+    __shared__ double Bs[BK][B];       // V of the slice's rows
+    __shared__ double red[3][16][B];   // mirrored partials of waves 1..3
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int item = blockIdx.x, I = 0;
@@ -1575,11 +1575,14 @@ ysym_items_kernel(const double *A, long lda, const double *V, int n, int ch, dou
     const int m0 = I * BM;
     const int kbeg = item * ch, kend = min(A_LoItems::k_hi(I, BM, n), kbeg + ch);
 
-    for (int idx = tid; idx < BM * B; idx += 256) {
-        const int mm = idx / B, j = idx - mm * B;
-        VI[mm][j] = (m0 + mm < n) ? V[(long)(m0 + mm) * B + j] : 0.0;
+    // k-step s of the mirrored product covers tile rows 32 w + 4 s .. + 3 (row 32 w + 4 s + lane / 16 in this lane)
+    double vf[8];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+        const int row = m0 + 32 * wave + 4 * st + (lane >> 4);
+        vf[st] = (row < n) ? V[(long)row * B + (lane & 15)] : 0.0;
     }
-    double ra[PA], rb[PB];
+    double ra[PA], rb;
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < PA; ++u) {
@@ -1587,19 +1590,12 @@ ysym_items_kernel(const double *A, long lda, const double *V, int n, int ch, dou
             const int gm = m0 + mm, gk = k0 + kk;
             ra[u] = (gm < n && gk < kend && gk <= gm) ? A[(long)gm * lda + gk] : 0.0;
         }
-#pragma unroll
-        for (int u = 0; u < PB; ++u) {
-            const int idx = tid + u * 256, kk = idx / B, j = idx - kk * B;
-            const int gk = k0 + kk;
-            rb[u] = (idx < BK * B && gk < kend) ? V[(long)gk * B + j] : 0.0;
-        }
+        const int kk = tid / B, j = tid - kk * B, gk = k0 + kk;
+        rb = (gk < kend) ? V[(long)gk * B + j] : 0.0;
     };
-    MF::acc_t acc1[2][TN];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc1[i][j] = MF::zero();
-    const int rb2 = wave & 1, kh = wave >> 1;  // P2: output rows 16 rb2 .. +16 of the slice, tile rows 64 kh .. +64
+    MF::acc_t acc1[2];
+    acc1[0] = MF::zero();
+    acc1[1] = MF::zero();
     fetch(kbeg);
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
@@ -1607,76 +1603,53 @@ ysym_items_kernel(const double *A, long lda, const double *V, int n, int ch, dou
             const int idx = tid + u * 256, mm = idx / BK, kk = idx - mm * BK;
             As[kk][mm] = ra[u];
         }
-#pragma unroll
-        for (int u = 0; u < PB; ++u) {
-            const int idx = tid + u * 256, kk = idx / B, j = idx - kk * B;
-            if (idx < BK * B) Bs[kk][j] = rb[u];
-        }
+        Bs[tid / B][tid % B] = rb;
         __syncthreads();
         if (k0 + BK < kend) fetch(k0 + BK);
-        // P1: wave w owns tile rows 32 w .. 32 w + 31
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            double a[2], bv[TN];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 4)][(wave * 2 + i) * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < TN; ++j) bv[j] = Bs[kk + (lane >> 4)][j * 16 + (lane & 15)];
+            const double bv = Bs[kk + (lane >> 4)][lane & 15];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j) acc1[i][j] = MF::mma(a[i], bv[j], acc1[i][j]);
+                acc1[i] = MF::mma(As[kk + (lane >> 4)][(wave * 2 + i) * 16 + (lane & 15)], bv, acc1[i]);
         }
-        // P2 of the slice: (As^T VI) rows 16 rb2 .. +16, summed over tile rows 64 kh .. +64
-        MF::acc_t acc2[TN];
+        MF::acc_t acc2 = MF::zero();
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc2[j] = MF::zero();
+        for (int st = 0; st < 8; ++st)
+            acc2 = MF::mma(As[lane & 15][32 * wave + 4 * st + (lane >> 4)], vf[st], acc2);
+        if (wave > 0) {
 #pragma unroll
-        for (int mb = 64 * kh; mb < 64 * kh + 64; mb += 4) {
-            const double a = As[16 * rb2 + (lane & 15)][mb + (lane >> 4)];
-#pragma unroll
-            for (int j = 0; j < TN; ++j) acc2[j] = MF::mma(a, VI[mb + (lane >> 4)][j * 16 + (lane & 15)], acc2[j]);
-        }
-        if (kh == 1) {
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) red[rb2][(lane >> 4) + 4 * r][j * 16 + (lane & 15)] = acc2[j][r];
+            for (int r = 0; r < 4; ++r) red[wave - 1][(lane >> 4) + 4 * r][lane & 15] = acc2[r];
         }
         __syncthreads();
-        if (kh == 0) {
+        if (wave == 0) {
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = (lane >> 4) + 4 * r, col = j * 16 + (lane & 15);
-                    const int kk = 16 * rb2 + row, k = k0 + kk;
-                    double v = acc2[j][r] + red[rb2][row][col];
-                    // the slice held the diagonal element A[k][k]; the mirrored part excludes it
-                    if (k >= m0 && k < m0 + BM) v -= As[kk][k - m0] * VI[k - m0][col];
-                    if (k < kend) P2[((long)blockIdx.x * ch + (k - kbeg)) * B + col] = v;
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int kk = (lane >> 4) + 4 * r, col = lane & 15, k = k0 + kk;
+                double v = acc2[r] + red[0][kk][col] + red[1][kk][col] + red[2][kk][col];
+                // the slice held the diagonal element A[k][k]; the mirrored part excludes it
+                if (k >= m0 && k < m0 + BM && k < kend) v -= As[kk][k - m0] * V[(long)k * B + col];
+                if (k < kend) P2[((long)blockIdx.x * ch + (k - kbeg)) * B + col] = v;
+            }
         }
         __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = (wave * 2 + i) * 16 + (lane >> 4) + 4 * r, col = j * 16 + (lane & 15);
-                P1[((long)blockIdx.x * BM + row) * B + col] = acc1[i][j][r];
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int row = (wave * 2 + i) * 16 + (lane >> 4) + 4 * r, col = lane & 15;
+            P1[((long)blockIdx.x * BM + row) * B + col] = acc1[i][r];
+        }
 }
 
-// Y (n x B) from the partials of ysym_items_kernel: blockIdx.y is the row tile K,
+// Y (n x 16) from the partials of ysym_items_kernel: blockIdx.y is the row tile K,
 // each thread one element; the tile's P1 rows, then the P2 rows of tiles K, K + 1, ...
-// are added in that order.  At most 1024 row tiles.
-template <int B>
+// are added in that order (loads issued eight at a time).  At most 1024 row tiles.
 __global__ void __launch_bounds__(256)
 ysym_reduce_kernel(const double *P1, const double *P2, int n, int ch, double *Y)
 {
+    constexpr int B = 16, U = 8;
     __shared__ int first[1025];  // first item of each row tile
     const int K = blockIdx.y, ntile = (n + 127) / 128;
     if (threadIdx.x == 0) {
@@ -1694,11 +1667,22 @@ ysym_reduce_kernel(const double *P1, const double *P2, int n, int ch, double *Y)
     double s = 0.0;
     const double *q1 = P1 + ((long)first[K] * 128 + r) * B + j;
     const int c1 = first[K + 1] - first[K];
-#pragma unroll 4
-    for (int u = 0; u < c1; ++u) s += q1[(long)u * 128 * B];
+    for (int u0 = 0; u0 < c1; u0 += U) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = (u0 + u < c1) ? q1[(long)(u0 + u) * 128 * B] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += t[u];
+    }
     const int c = row / ch, off = row - c * ch;
-#pragma unroll 4
-    for (int I = K; I < ntile; ++I) s += P2[((long)(first[I] + c) * ch + off) * B + j];
+    for (int I0 = K; I0 < ntile; I0 += U) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            t[u] = (I0 + u < ntile) ? P2[((long)(first[I0 + u] + c) * ch + off) * B + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += t[u];
+    }
     Y[(long)row * B + j] = s;
 }
 
@@ -1735,8 +1719,8 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
                 // one pass over the triangle (the form that pays at b = 16, where the two-pass
                 // products are bound by memory rather than by the matrix cores)
                 double *p1 = w.splitk, *p2 = w.splitk + (long)n1 * 128 * b;
-                hipLaunchKernelGGL(ysym_items_kernel<16>, dim3(n1), dim3(256), 0, s, A22, lda, Vp, n, ch, p1, p2);
-                hipLaunchKernelGGL(ysym_reduce_kernel<16>, dim3(ceil_div(128 * b, 256), nt), dim3(256), 0, s, p1, p2,
+                hipLaunchKernelGGL(ysym_items_kernel, dim3(n1), dim3(256), 0, s, A22, lda, Vp, n, ch, p1, p2);
+                hipLaunchKernelGGL(ysym_reduce_kernel, dim3(ceil_div(128 * b, 256), nt), dim3(256), 0, s, p1, p2,
                                    n, ch, w.Y);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
             } else {
