@@ -39,7 +39,7 @@ static int max_steps(int N, int b) { return N > 2 ? bulge_nsteps(N, b, 0) : 0; }
 
 // ============================================================================
 // Stage 1: Householder QR of one panel (cooperative).  Each workgroup holds a
-// slice of 4096 / B rows in registers, 16 elements per thread.  Per column, every
+// slice of 128 rows in registers, B / 2 elements per thread.  Per column, every
 // workgroup stores its partial products of that column with all columns into
 // exchange slots with device-coherent stores, and reads the slots of all the
 // others, waiting until none holds the empty marker any more.  There is no
@@ -55,7 +55,7 @@ static int max_steps(int N, int b) { return N > 2 ? bulge_nsteps(N, b, 0) : 0; }
 // an empty set.  Launches on one workspace run one after another.
 // ============================================================================
 
-static inline int pqr_rows(int b) { return 4096 / b; }
+static inline int pqr_rows(int) { return 128; }
 static inline int pqr_gmax(int Nmax, int b) { return (Nmax + pqr_rows(b) - 1) / pqr_rows(b); }
 __host__ __device__ inline size_t pqr_slot_set(int b, int Gmax) { return (size_t)b * Gmax * b + (size_t)b * b; }
 
@@ -91,8 +91,8 @@ panel_qr_kernel(double *A, long lda, int r0, int p, int n, double *Vx, double *t
                 double *slots, int Gmax, int parity, int Gprev, unsigned *err)
 {
     constexpr int RG = 256 / B;    // row groups
-    constexpr int KR = 16;         // rows per thread: local rows rg + RG k
-    constexpr int ROWS = RG * KR;  // 4096 / B
+    constexpr int KR = B / 2;      // rows per thread: local rows rg + RG k
+    constexpr int ROWS = RG * KR;  // 128
     __shared__ double red[4][B];
     __shared__ double rowl[B];
     __shared__ double red2[RG][B];
