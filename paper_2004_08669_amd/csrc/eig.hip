@@ -352,6 +352,94 @@ struct EpiVW {
     }
 };
 
+// b = 16: W = [Y | V] sm (sm = [T ; -1/2 S], 2b x b), the operands [V | W] and [W | V],
+// and, when cols is set, the update of the next panel's columns,
+// A22[:, 0:b] -= [V | W] [W | V][0:b, :]^T, in one launch.  Every workgroup forms W of
+// rows 0..b-1 itself (a b x 2b by 2b x b product), so no workgroup waits for another.
+// Workgroup: 128 rows, two threads per row (eight of the b columns each).
+__global__ void __launch_bounds__(256)
+vw_cols16_kernel(const double *Y, const double *V, const double *sm, int n, int cols, double *VW, double *WV,
+                 double *A22, long lda)
+{
+    constexpr int B = 16;
+    __shared__ double S[2 * B][B];
+    __shared__ double W0[B][B + 1];
+    __shared__ double V0[B][B + 1];
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < 2 * B * B; idx += 256) S[idx / B][idx % B] = sm[idx];
+    {
+        const int r = tid / B, c = tid % B;
+        V0[r][c] = (r < n) ? V[(long)r * B + c] : 0.0;
+    }
+    __syncthreads();
+    {
+        const int r = tid / B, c = tid % B;
+        double w = 0.0;
+        if (r < n) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) w += Y[(long)r * B + k] * S[k][c];
+#pragma unroll
+            for (int k = 0; k < B; ++k) w += V0[r][k] * S[B + k][c];
+        }
+        W0[r][c] = w;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * 128 + (tid >> 1), half = tid & 1, c0 = 8 * half;
+    const bool ok = i < n;
+    double v[B], w[8];
+#pragma unroll
+    for (int k = 0; k < B; ++k) v[k] = ok ? V[(long)i * B + k] : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) w[cc] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < B; ++k) {
+        const double yk = ok ? Y[(long)i * B + k] : 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) w[cc] += yk * S[k][c0 + cc];
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) w[cc] += v[k] * S[B + k][c0 + cc];
+    // the partner thread's eight columns of W, so that both hold the whole row
+    double wl[8], wh[8];
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+        const double o = __shfl_xor(w[cc], 1, 64);
+        wl[cc] = half ? o : w[cc];
+        wh[cc] = half ? w[cc] : o;
+    }
+    if (ok) {
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            VW[(long)i * 2 * B + B + c0 + cc] = w[cc];
+            WV[(long)i * 2 * B + c0 + cc] = w[cc];
+        }
+        // [V | .] and [. | V] of the row, V read again (cached) rather than picked from v by a
+        // lane-dependent index
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const double vc = V[(long)i * B + c0 + cc];
+            VW[(long)i * 2 * B + c0 + cc] = vc;
+            WV[(long)i * 2 * B + B + c0 + cc] = vc;
+        }
+        if (cols) {
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) {
+                const int c = c0 + cc;
+                double a = 0.0;
+#pragma unroll
+                for (int k = 0; k < B; ++k) a += v[k] * W0[c][k];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) a += wl[k] * V0[c][k];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) a += wh[k] * V0[c][8 + k];
+                A22[(long)i * lda + c] -= a;
+            }
+        }
+    }
+}
+
 // Lower band (r - c in [0, b]) of the stage-1 result into column-major band
 // storage with 2b diagonals (the upper b hold the bulges of stage 2).
 __global__ void extract_band_kernel(const double *A, long lda, int N, int b, double *band)
@@ -1757,14 +1845,24 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
             else
                 hipLaunchKernelGGL(vty_partial_kernel<16>, dim3(gv), dim3(256), 0, s, Vp, w.Y, n, w.splitk);
             hipLaunchKernelGGL(wy_small_kernel, dim3(1), dim3(1024), 0, s, w.splitk, gv, Tp, b, w.sm);
-            e = gemm_mfma(tall, A_YV{w.Y, Vp, b}, B_RM{w.sm, b}, EpiVW{Vp, w.VW, w.WV, b}, n, b, 2 * b, s);
+            if (b == 16) {
+                // with the next panel's columns (rows 0..n-1, columns 0..b-1 of A22) updated in the same launch
+                hipLaunchKernelGGL(vw_cols16_kernel, dim3(ceil_div(n, 128)), dim3(256), 0, s, w.Y, Vp, w.sm, n,
+                                   pi + 1 < np ? 1 : 0, w.VW, w.WV, A22, lda);
+                e = hipGetLastError();
+            } else {
+                e = gemm_mfma(tall, A_YV{w.Y, Vp, b}, B_RM{w.sm, b}, EpiVW{Vp, w.VW, w.WV, b}, n, b, 2 * b, s);
+            }
             if (e != hipSuccess) return e;
         }
         // A22 -= [V|W] [W|V]^T on the lower triangle (the only part later read)
         if (pi + 1 < np) {
             // the next panel's columns first (rows 0..n-1, columns 0..b-1 of A22) ...
-            e = gemm_mfma(tall, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, b, 2 * b, s);
-            if (e != hipSuccess) return e;
+            if (b != 16) {
+                e = gemm_mfma(tall, A_RM{w.VW, 2 * b}, B_T{w.WV, 2 * b}, EpiAxpby{A22, lda, -1.0, 1.0}, n, b, 2 * b,
+                              s);
+                if (e != hipSuccess) return e;
+            }
             // ... then the rest of the update on s2, beside the next panel's QR on s (the QR is on
             // the critical path; the update ends first, so the wait for it costs nothing)
             if ((e = hipEventRecord(w.ev_cols, s)) != hipSuccess) return e;
