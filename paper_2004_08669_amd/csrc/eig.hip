@@ -356,20 +356,26 @@ struct EpiVW {
 // and, when cols is set, the update of the next panel's columns,
 // A22[:, 0:b] -= [V | W] [W | V][0:b, :]^T, in one launch.  Every workgroup forms W of
 // rows 0..b-1 itself (a b x 2b by 2b x b product), so no workgroup waits for another.
-// Workgroup: 128 rows, two threads per row (eight of the b columns each).
+// Workgroup: 32 rows, two elements of each product per thread.
 __global__ void __launch_bounds__(256)
 vw_cols16_kernel(const double *Y, const double *V, const double *sm, int n, int cols, double *VW, double *WV,
                  double *A22, long lda)
 {
-    constexpr int B = 16;
+    constexpr int B = 16, TR = 32;
     __shared__ double S[2 * B][B];
     __shared__ double W0[B][B + 1];
     __shared__ double V0[B][B + 1];
-    const int tid = threadIdx.x;
+    __shared__ double Wt[TR][B + 1];
+    __shared__ double Vt[TR][B + 1];
+    const int tid = threadIdx.x, i0 = blockIdx.x * TR;
     for (int idx = tid; idx < 2 * B * B; idx += 256) S[idx / B][idx % B] = sm[idx];
     {
         const int r = tid / B, c = tid % B;
         V0[r][c] = (r < n) ? V[(long)r * B + c] : 0.0;
+    }
+    for (int idx = tid; idx < TR * B; idx += 256) {
+        const int r = idx / B, c = idx % B;
+        Vt[r][c] = (i0 + r < n) ? V[(long)(i0 + r) * B + c] : 0.0;
     }
     __syncthreads();
     {
@@ -383,59 +389,36 @@ vw_cols16_kernel(const double *Y, const double *V, const double *sm, int n, int 
         }
         W0[r][c] = w;
     }
+    // W of the tile's rows: thread (r, c) for r = tid / 16 and r + 16
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = tid / B + 16 * h, c = tid % B, i = i0 + r;
+        double w = 0.0;
+        if (i < n) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) w += Y[(long)i * B + k] * S[k][c];
+#pragma unroll
+            for (int k = 0; k < B; ++k) w += Vt[r][k] * S[B + k][c];
+            const double v = Vt[r][c];
+            VW[(long)i * 2 * B + c] = v;
+            VW[(long)i * 2 * B + B + c] = w;
+            WV[(long)i * 2 * B + c] = w;
+            WV[(long)i * 2 * B + B + c] = v;
+        }
+        Wt[r][c] = w;
+    }
+    if (!cols) return;
     __syncthreads();
-    const int i = blockIdx.x * 128 + (tid >> 1), half = tid & 1, c0 = 8 * half;
-    const bool ok = i < n;
-    double v[B], w[8];
 #pragma unroll
-    for (int k = 0; k < B; ++k) v[k] = ok ? V[(long)i * B + k] : 0.0;
+    for (int h = 0; h < 2; ++h) {
+        const int r = tid / B + 16 * h, c = tid % B, i = i0 + r;
+        if (i < n) {
+            double a = 0.0;
 #pragma unroll
-    for (int cc = 0; cc < 8; ++cc) w[cc] = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < B; ++k) {
-        const double yk = ok ? Y[(long)i * B + k] : 0.0;
+            for (int k = 0; k < B; ++k) a += Vt[r][k] * W0[c][k];
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) w[cc] += yk * S[k][c0 + cc];
-    }
-#pragma unroll
-    for (int k = 0; k < B; ++k)
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc) w[cc] += v[k] * S[B + k][c0 + cc];
-    // the partner thread's eight columns of W, so that both hold the whole row
-    double wl[8], wh[8];
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-        const double o = __shfl_xor(w[cc], 1, 64);
-        wl[cc] = half ? o : w[cc];
-        wh[cc] = half ? w[cc] : o;
-    }
-    if (ok) {
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-            VW[(long)i * 2 * B + B + c0 + cc] = w[cc];
-            WV[(long)i * 2 * B + c0 + cc] = w[cc];
-        }
-        // [V | .] and [. | V] of the row, V read again (cached) rather than picked from v by a
-        // lane-dependent index
-#pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-            const double vc = V[(long)i * B + c0 + cc];
-            VW[(long)i * 2 * B + c0 + cc] = vc;
-            WV[(long)i * 2 * B + B + c0 + cc] = vc;
-        }
-        if (cols) {
-#pragma unroll
-            for (int cc = 0; cc < 8; ++cc) {
-                const int c = c0 + cc;
-                double a = 0.0;
-#pragma unroll
-                for (int k = 0; k < B; ++k) a += v[k] * W0[c][k];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) a += wl[k] * V0[c][k];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) a += wh[k] * V0[c][8 + k];
-                A22[(long)i * lda + c] -= a;
-            }
+            for (int k = 0; k < B; ++k) a += Wt[r][k] * V0[c][k];
+            A22[(long)i * lda + c] -= a;
         }
     }
 }
@@ -1847,7 +1830,7 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
             hipLaunchKernelGGL(wy_small_kernel, dim3(1), dim3(1024), 0, s, w.splitk, gv, Tp, b, w.sm);
             if (b == 16) {
                 // with the next panel's columns (rows 0..n-1, columns 0..b-1 of A22) updated in the same launch
-                hipLaunchKernelGGL(vw_cols16_kernel, dim3(ceil_div(n, 128)), dim3(256), 0, s, w.Y, Vp, w.sm, n,
+                hipLaunchKernelGGL(vw_cols16_kernel, dim3(ceil_div(n, 32)), dim3(256), 0, s, w.Y, Vp, w.sm, n,
                                    pi + 1 < np ? 1 : 0, w.VW, w.WV, A22, lda);
                 e = hipGetLastError();
             } else {
