@@ -267,13 +267,17 @@ __global__ void __launch_bounds__(256) vty_partial_kernel(const double *V, const
 {
     using MF = Mfma<double>;
     constexpr int TB = B / 16;
+    // b = 32: wave w forms output block (w / 2, w % 2); b = 16: the one output block, each wave
+    // over its own rows (RS row streams per workgroup), the four sums added in LDS in wave order
+    constexpr int RS = TB == 1 ? 4 : 1;
+    __shared__ double red[RS][16][17];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (wave >= TB * TB) return;
-    const int I = wave / TB, J = wave % TB;
+    if (TB == 2 && wave >= TB * TB) return;
+    const int I = TB == 1 ? 0 : wave / TB, J = TB == 1 ? 0 : wave % TB;
     const int lr = lane >> 4, lc = lane & 15;
     MF::acc_t acc = MF::zero();
-    const int stride = gridDim.x * 4;
-    int r0 = blockIdx.x * 4;
+    const int stride = gridDim.x * 4 * RS;
+    int r0 = (blockIdx.x * RS + (RS == 1 ? 0 : wave)) * 4;
     for (; r0 + 7 * stride + 4 <= n; r0 += 8 * stride) {
         double a[8], y[8];
 #pragma unroll
@@ -292,8 +296,21 @@ __global__ void __launch_bounds__(256) vty_partial_kernel(const double *V, const
         acc = MF::mma(a, y, acc);
     }
     double *dst = part + (long)blockIdx.x * B * B;
+    if constexpr (RS == 1) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) dst[(16 * I + lr + 4 * j) * B + 16 * J + lc] = acc[j];
+        for (int j = 0; j < 4; ++j) dst[(16 * I + lr + 4 * j) * B + 16 * J + lc] = acc[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[wave][lr + 4 * j][lc] = acc[j];
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = lr + 4 * j;
+                dst[r * B + lc] = ((red[0][r][lc] + red[1][r][lc]) + red[2][r][lc]) + red[3][r][lc];
+            }
+        }
+    }
 }
 
 __global__ void __launch_bounds__(1024) wy_small_kernel(const double *part, int nparts, const double *T, int b,
@@ -1716,11 +1733,11 @@ ysym_items_kernel(const double *A, long lda, const double *V, int n, int ch, dou
 
 // Y (n x 16) from the partials of ysym_items_kernel: blockIdx.y is the row tile K,
 // each thread one element; the tile's P1 rows, then the P2 rows of tiles K, K + 1, ...
-// are added in that order (loads issued eight at a time).  At most 1024 row tiles.
+// are added in that order (loads issued sixteen at a time).  At most 1024 row tiles.
 __global__ void __launch_bounds__(256)
 ysym_reduce_kernel(const double *P1, const double *P2, int n, int ch, double *Y)
 {
-    constexpr int B = 16, U = 8;
+    constexpr int B = 16, U = 16;
     __shared__ int first[1025];  // first item of each row tile
     const int K = blockIdx.y, ntile = (n + 127) / 128;
     if (threadIdx.x == 0) {
