@@ -3,13 +3,13 @@
 // the m largest in magnitude.
 //
 //   stage 1  dense -> band (half-bandwidth b): blocked Householder QR of each
-//            b-column panel below the band (one cooperative kernel per panel;
-//            its workgroups exchange per-column partial sums through device-
-//            coherent slots) and a two-sided compact-WY update of
-//            the trailing matrix with GEMMs on the matrix cores; the matrix is
-//            held in its lower triangle (products with it read the lower
-//            triangle twice, once transposed; the update writes only tiles on
-//            or below the diagonal);
+//            b-column panel below the band (one kernel per panel whose
+//            workgroups, all resident, exchange per-column partial sums through
+//            device-coherent slots) and a two-sided compact-WY update of the
+//            trailing matrix with GEMMs on the matrix cores; the matrix is held
+//            in its lower triangle (the product with it reads the triangle once
+//            at b = 16, twice at b = 32; the update writes only tiles on or
+//            below the diagonal);
 //   stage 2  band -> tridiagonal: bulge chasing, one wave per step, one
 //            launch per wavefront of independent steps (a sweep trails its
 //            predecessor by three steps);
@@ -40,6 +40,7 @@ struct EigWork {
     double *part = nullptr;    // panel QR: exchange slots (two sets)
     unsigned long pqr_launches = 0;  // panel QR launches so far (the parity picks the slot set)
     int pqr_gprev = 0;         // workgroups of the previous panel QR launch
+    int pqr_cap = 0;           // panel QR workgroups the device holds at once
     double *splitk = nullptr;  // split-K partials
     size_t splitk_elems = 0;
     // stage 2

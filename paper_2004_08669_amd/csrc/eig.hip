@@ -38,7 +38,7 @@ __host__ __device__ inline int bulge_nsteps(int N, int b, int j) { return 1 + (N
 static int max_steps(int N, int b) { return N > 2 ? bulge_nsteps(N, b, 0) : 0; }
 
 // ============================================================================
-// Stage 1: Householder QR of one panel (cooperative).  Each workgroup holds a
+// Stage 1: Householder QR of one panel (all workgroups resident).  Each workgroup holds a
 // slice of 128 rows in registers, B / 2 elements per thread.  Per column, every
 // workgroup stores its partial products of that column with all columns into
 // exchange slots with device-coherent stores, and reads the slots of all the
@@ -1568,6 +1568,16 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
     const size_t tg_smem = sizeof(double) * ((size_t)bt1_g(b) * b * (bt1_g(b) * b + 1) + bt1_g(b) * b);
     hipError_t e = hipFuncSetAttribute(b == 32 ? (const void *)bt1_tg_kernel<32> : (const void *)bt1_tg_kernel<16>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)tg_smem);
+    {
+        // panel QR workgroups that the device holds at once
+        int per_cu = 0, dev = 0, cus = 0;
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, b == 32 ? (const void *)panel_qr_kernel<32> : (const void *)panel_qr_kernel<16>, 256, 0);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        w.pqr_cap = per_cu * cus;
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_cols, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_update, hipEventDisableTiming);
@@ -1606,10 +1616,6 @@ static int splits_for(long tiles, long K, int kmin)
     return (int)s;
 }
 
-static hipError_t launch_coop(const void *fn, dim3 grid, dim3 block, void **args, size_t smem, hipStream_t s)
-{
-    return hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)smem, s);
-}
 
 static hipError_t panel_qr(EigWork &w, double *A, long lda, int N, int pi, hipStream_t s)
 {
@@ -1622,9 +1628,15 @@ static hipError_t panel_qr(EigWork &w, double *A, long lda, int N, int pi, hipSt
     int G = (n + rows - 1) / rows;
     int Gmax = pqr_gmax(w.Nmax, b), parity = (int)(w.pqr_launches & 1), Gprev = w.pqr_gprev;
     if (G > Gmax) return hipErrorInvalidValue;
+    // The workgroups wait for each other's partial sums, so all of them must be able to be
+    // resident at once: the grid fits the device (checked against the occupancy at set-up),
+    // and the only kernels beside it (the trailing update on the second stream) wait on
+    // nothing, so they retire and leave room for any workgroup not yet started.  A plain
+    // launch is used: a cooperative launch costs about 13 us more per panel here.
+    if (G > w.pqr_cap) return hipErrorCooperativeLaunchTooLarge;
     void *args[] = {&A, &lda, (void *)&r0, (void *)&p, (void *)&n, &Vp, &taup, &Tp, &w.part, &Gmax, &parity, &Gprev, &w.err};
     const void *fn = b == 32 ? (const void *)panel_qr_kernel<32> : (const void *)panel_qr_kernel<16>;
-    hipError_t e = launch_coop(fn, dim3(G), dim3(256), args, 0, s);
+    hipError_t e = hipLaunchKernel(fn, dim3(G), dim3(256), args, 0, s);
     if (e == hipSuccess) {
         ++w.pqr_launches;
         w.pqr_gprev = G;
