@@ -41,6 +41,7 @@ struct EigWork {
     unsigned long pqr_launches = 0;  // panel QR launches so far (the parity picks the slot set)
     int pqr_gprev = 0;         // workgroups of the previous panel QR launch
     int pqr_cap = 0;           // panel QR workgroups the device holds at once
+    int ysym_cap = 0;          // single-pass Y workgroups the device holds at once
     double *splitk = nullptr;  // split-K partials
     size_t splitk_elems = 0;
     // stage 2

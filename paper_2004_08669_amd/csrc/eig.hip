@@ -1511,6 +1511,9 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     return s;
 }
 
+__global__ void __launch_bounds__(256)
+ysym_items_kernel(const double *A, long lda, const double *V, int n, int ch, double *P1, double *P2);
+
 hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
 {
     w.Nmax = Nmax;
@@ -1577,6 +1580,10 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         if (e == hipSuccess) e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         w.pqr_cap = per_cu * cus;
+        int ys_cu = 0;
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ys_cu, (const void *)ysym_items_kernel, 256, 0);
+        w.ysym_cap = std::max(1, ys_cu * cus);
     }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_cols, hipEventDisableTiming);
@@ -1815,13 +1822,29 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
                 n1 += tile_items<A_LoItems>(I, 128, n, ch);
                 n2 += tile_items<A_SLoTItems>(I, 128, n, ch);
             }
-            if (b == 16 && nt <= 1024 && (size_t)n1 * (128 + ch) * b <= w.splitk_elems) {
+            // single pass: the chunk length that puts the items through the device in the fewest
+            // rounds of equal work (rounds x chunk length; ties to the longer chunk)
+            int ych = ch, yn1 = n1;
+            if (b == 16) {
+                long best = -1;
+                for (int c = 128; c <= 2048; c += 128) {
+                    long it = 0;
+                    for (int I = 0; I < nt; ++I) it += tile_items<A_LoItems>(I, 128, n, c);
+                    const long cost = (it + w.ysym_cap - 1) / w.ysym_cap * c;
+                    if (best < 0 || cost <= best) {
+                        best = cost;
+                        ych = c;
+                        yn1 = (int)it;
+                    }
+                }
+            }
+            if (b == 16 && nt <= 1024 && (size_t)yn1 * (128 + ych) * b <= w.splitk_elems) {
                 // one pass over the triangle (the form that pays at b = 16, where the two-pass
                 // products are bound by memory rather than by the matrix cores)
-                double *p1 = w.splitk, *p2 = w.splitk + (long)n1 * 128 * b;
-                hipLaunchKernelGGL(ysym_items_kernel, dim3(n1), dim3(256), 0, s, A22, lda, Vp, n, ch, p1, p2);
+                double *p1 = w.splitk, *p2 = w.splitk + (long)yn1 * 128 * b;
+                hipLaunchKernelGGL(ysym_items_kernel, dim3(yn1), dim3(256), 0, s, A22, lda, Vp, n, ych, p1, p2);
                 hipLaunchKernelGGL(ysym_reduce_kernel, dim3(ceil_div(128 * b, 256), nt), dim3(256), 0, s, p1, p2,
-                                   n, ch, w.Y);
+                                   n, ych, w.Y);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
             } else {
                 if ((size_t)(n1 + n2) * 128 * b > w.splitk_elems) return hipErrorInvalidValue;
