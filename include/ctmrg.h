@@ -114,8 +114,12 @@ ctmrg_status ctmrg_step(ctmrg_ctx *ctx, int nsteps, double *delta_out);
  * Returns CTMRG_E_NOT_CONVERGED if max_steps is reached (the state is kept). */
 ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *ctx, double tol, int max_steps, int *steps_out, double *delta_out);
 
-/* Observables of the current state (needs >= 2 steps).  kept_spectrum (nullable,
- * m entries) receives omega (normalized kept eigenvalues, zero padded). */
+/* Observables of the current state (Sec. II: Eqs. 3-6 on the fixed-point
+ * matrices; the free energy from the normalization history).  Needs >= 1 step
+ * since init, set_K, set_state or import_state; f and ln_kappa_W need two and
+ * are NaN after one.  kept_spectrum (nullable, m entries) receives omega
+ * (normalized kept eigenvalues, zero padded).
+ * Errors: CTMRG_E_STATE before the first step. */
 ctmrg_status ctmrg_observables(ctmrg_ctx *ctx, ctmrg_observables_t *out, double *kept_spectrum);
 
 /* Derivatives of the free energy per site F = beta f at the fixed point with

@@ -21,7 +21,10 @@ group analysis of the two-dimensional dodecahedron model"):
 
 Library primitives used as single steps: numpy matmul/einsum/tensordot for the
 tensor contractions, numpy sort.  No blocking, fusion or reordering beyond what
-the formulas state.
+the formulas state.  The diagonalization is the oracle's own Jacobi solver by
+default; eig="lapack" takes numpy's symmetric eigensolver (LAPACK) as the
+single step instead, for long runs at N = q m >= 1280 where Jacobi takes
+minutes per step.  Both are pinned against prescribed spectra.
 
 Readings where the paper is silent or inconsistent (each is justified in the
 design notes of the repository and pinned by the tests):
@@ -240,13 +243,23 @@ def entropy(w: np.ndarray) -> float:
     return float(-np.sum(w4[nz] * np.log(w4[nz])))
 
 
+def eigh(A: np.ndarray, method: str = "jacobi"):
+    """Eigenvalues and eigenvectors of the symmetric A: the oracle's Jacobi solver, or
+    numpy's LAPACK driver as a single library step (method="lapack")."""
+    if method == "jacobi":
+        return jacobi(A)
+    if method == "lapack":
+        return np.linalg.eigh(A)
+    raise ValueError(method)
+
+
 def step(W: np.ndarray, P: np.ndarray, omega: np.ndarray, m: int, tau: float = 1e-10,
-         rank_tol: float = 1e-13, keep_cext: bool = False) -> StepResult:
+         rank_tol: float = 1e-13, keep_cext: bool = False, eig: str = "jacobi") -> StepResult:
     C = extend(W, P, omega)
     amax = np.abs(C).max()
     asym = float(np.abs(C - C.T).max() / amax) if amax > 0 else 0.0
     Cs = 0.5 * (C + C.T)
-    lam, vec = jacobi(Cs)
+    lam, vec = eigh(Cs, eig)
     order = sort_spectrum(lam)
     lam = lam[order]
     vec = vec[:, order]
@@ -289,6 +302,7 @@ class OracleCTMRG:
     s0: int = 0
     tau: float = 1e-10
     rank_tol: float = 1e-13
+    eig: str = "jacobi"
     P: np.ndarray = None
     omega: np.ndarray = None
     k: int = 0
@@ -317,7 +331,7 @@ class OracleCTMRG:
     def step(self, keep_cext: bool = False) -> StepResult:
         prev = np.zeros(self.m)
         prev[: len(self.omega)] = self.omega ** 4
-        r = step(self.W, self.P, self.omega, self.m, self.tau, self.rank_tol, keep_cext)
+        r = step(self.W, self.P, self.omega, self.m, self.tau, self.rank_tol, keep_cext, self.eig)
         # bookkeeping of the true scale (P_true = a P, C_true = b Omega)
         self.ln_b = self.ln_b + 2.0 * self.ln_a + np.log(r.n_C)
         self.ln_a = self.ln_a + np.log(r.n_P)
@@ -395,8 +409,8 @@ class OracleCTMRG:
 
 
 def run_fixed_point(V, K, m, bc="fixed", tol=1e-12, max_steps=3000, s0=0, tau=1e-10,
-                    rank_tol=1e-13):
-    o = OracleCTMRG(V, K, m, bc=bc, s0=s0, tau=tau, rank_tol=rank_tol)
+                    rank_tol=1e-13, eig="jacobi"):
+    o = OracleCTMRG(V, K, m, bc=bc, s0=s0, tau=tau, rank_tol=rank_tol, eig=eig)
     converged = o.run(tol, max_steps)
     obs = o.observables()
     obs["converged"] = converged

@@ -233,8 +233,12 @@ ctmrg_status one_step(ctmrg_ctx *c)
     HIPCHK(c, normalize_and_book(c->dPt, c->dA, q, m, c->dPart, c->dBook, &c->dPost->n_C, &c->dPost->S_E, s));
     HIPCHK(c, hipMemcpyAsync(c->dOmega, c->dOmNew, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
     mark(c->eig, MK_NORM, s);
+    // the eigenvector kernels raise their error flags after the mid-step check above:
+    // drain them before the step is reported as done
+    HIPCHK(c, hipStreamSynchronize(s));
+    st = check_kernel_errors(c);
+    if (st != CTMRG_OK) return st;
     if (c->profile) {
-        HIPCHK(c, hipStreamSynchronize(s));
         // stage i spans marks (from[i], to[i])
         static const int from[] = {MK_START, MK_EXT, MK_WMIX1, MK_STAGE1, MK_BULGE, MK_BISECT, MK_VEC_START, MK_INVIT,
                                    MK_NS, MK_BT2, MK_BT1, MK_HALF, MK_WMIX2, MK_PROJ};
@@ -401,7 +405,7 @@ ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *c, double tol, int max_steps, i
 ctmrg_status ctmrg_observables(ctmrg_ctx *c, ctmrg_observables_t *out, double *kept_spectrum)
 {
     if (!c || !out) return CTMRG_E_INVALID_ARG;
-    if (c->steps < 2 || !c->have_U) return fail(c, CTMRG_E_STATE, "observables need at least two steps");
+    if (c->steps < 1 || !c->have_U) return fail(c, CTMRG_E_STATE, "observables need at least one step");
     HIPCHK(c, observables(c->dA, c->dOmega, c->dU, c->dW, c->dWH, c->dV, c->dOA, c->dX, c->dH, c->dWork,
                           c->work_elems, c->q, c->dim, c->m, c->opt.bc, c->opt.boundary_spin, c->dObs, c->stream));
     double obs[8];
@@ -412,7 +416,8 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *c, ctmrg_observables_t *out, double *k
         HIPCHK(c, hipMemcpyAsync(kept_spectrum, c->dOmega, sizeof(double) * c->m, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const double T = 1.0 / c->K;
-    out->ln_kappa_W = log(bk.nP_prev) + 0.5 * log(bk.nC / bk.nC_prev);
+    // the free energy is a ratio of the normalizations of two consecutive steps
+    out->ln_kappa_W = c->steps >= 2 ? log(bk.nP_prev) + 0.5 * log(bk.nC / bk.nC_prev) : NAN;
     out->f = -0.5 * T * out->ln_kappa_W;
     out->ln_kappa_ratio = log(obs[2]) + log(obs[0]) - 2.0 * log(obs[1]);
     out->E = 0.5 * obs[3] / obs[2];

@@ -1478,6 +1478,14 @@ sign_fix_copy_kernel(const double *Z, int ldz, int N, int me, double *U, int ldu
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Split-K and work-item partials.  The stage-1 products take at most 64 Nmax max(b, 64)
+// doubles; a split-K product whose splits come from splits_for() has tiles * splits < 1024
+// and at most 64 x 64 outputs per tile, so it never needs more than 1024 * 64 * 64.
+static size_t splitk_elems_for(int Nmax, int b)
+{
+    return std::max<size_t>((size_t)64 * Nmax * std::max(b, 64), (size_t)1024 * 64 * 64);
+}
+
 size_t eig_bytes(int Nmax, int kmax, int b)
 {
     const int np = num_panels(Nmax, b);
@@ -1491,7 +1499,7 @@ size_t eig_bytes(int Nmax, int kmax, int b)
     s += 2 * align_up(sizeof(double) * (size_t)Nmax * b);
     s += align_up(sizeof(double) * 4 * b * b);
     s += align_up(sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b)));
-    s += align_up(sizeof(double) * (size_t)std::max<size_t>((size_t)64 * Nmax * std::max(b, 64), (size_t)64 * kmax * kmax + 64 * 64 * 64));
+    s += align_up(sizeof(double) * splitk_elems_for(Nmax, b));
     s += align_up(sizeof(double) * (size_t)Nmax * 2 * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax * b);
     s += align_up(sizeof(double) * (size_t)Nmax * Tmax);
@@ -1523,7 +1531,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
     w.nJmax = (Nmax + b - 1) / b;
     const int np = num_panels(Nmax, b);
     const size_t kpad = ((size_t)kmax + 63) / 64 * 64;  // threads of invit_kernel
-    w.splitk_elems = std::max<size_t>((size_t)64 * Nmax * std::max(b, 64), (size_t)64 * kmax * kmax + 64 * 64 * 64);
+    w.splitk_elems = splitk_elems_for(Nmax, b);
     struct Req { void **p; size_t bytes; };
     double *bounds_unused = nullptr;
     (void)bounds_unused;
@@ -2011,7 +2019,8 @@ hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const do
     double *Z = w.ZT, *Zo = w.Ztmp;
     for (int it = 0; it < 3; ++it) {
         const long tiles = (long)ceil_div(me, 64) * ceil_div(me, 64);
-        const int sp = splits_for(tiles, N, 256);
+        int sp = splits_for(tiles, N, 256);
+        while (sp > 1 && (size_t)sp * me * me > w.splitk_elems) sp /= 2;
         e = gemm_mfma_splitk(A_T{Z, ldz}, B_RM{Z, ldz}, EpiStore{w.G, me, 1.0}, me, me, N, sp, w.splitk, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(ns_matrix_kernel, dim3(std::max(1, std::min(1024, ceil_div((long)me * me, 256)))), dim3(256), 0,

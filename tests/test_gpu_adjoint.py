@@ -8,6 +8,8 @@ References that do not come from the GPU path:
     energy at the same m (equal to dF/dK at an exact fixed point), and the central difference
     of that energy for d2F/dK2 (accurate to about 1e-7).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -53,18 +55,13 @@ def test_derivative_ising_onsager(T, m):
     assert abs(r["d2F_dK2"] - d2) <= 1e-5 * abs(d2)
 
 
-def _oracle_fixed_point(V, K, m, tol=1e-13, max_steps=5000, start=None):
-    o = O.OracleCTMRG(V, K, m)
-    if start is not None:
-        o.import_state(start.P, start.omega, k=1)
-    for i in range(max_steps):
-        o.step()
-        if i >= 2 and o.delta < tol:
-            break
-        if i % 50 == 49:
-            say(f"  oracle K={K:.8f} step {i + 1} delta {o.delta:.2e}")
-    assert o.delta < tol
-    return o
+def _golden(name):
+    """Stored oracle values (tests/golden/, written by make_golden.py from the oracle alone)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    if not os.path.exists(path):
+        pytest.fail(f"missing golden file {name}: run tests/golden/make_golden.py")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
 
 
 def test_derivative_dodecahedron_m12():
@@ -72,25 +69,22 @@ def test_derivative_dodecahedron_m12():
     V = I.dodecahedron()
     T, m = 0.40, 12
     K = 1.0 / T
+    ref = _golden(f"derivative_q20_m{m}_T{T:.2f}.npz")
+    h = float(ref["h"])
     say(f"[derivative dodecahedron] T={T} m={m}")
     g = _converged(ct, V, K, m)
     obs = g.observables()
     r = g.fixed_point_derivative(second_order=True)
     g.close()
     say(f"  {r}")
-    o = _oracle_fixed_point(V, K, m)
-    oo = o.observables()
-    h = 1e-4
-    op = _oracle_fixed_point(V, K + h, m, start=o).observables()
-    om = _oracle_fixed_point(V, K - h, m, start=o).observables()
-    fd = -(op["minus_beta_f"] - om["minus_beta_f"]) / (2 * h)
-    d2 = (op["E"] - om["E"]) / (2 * h)
-    F0 = -oo["minus_beta_f"]
-    say(f"  dF/dK {r['dF_dK']:.13f}  oracle FD {fd:.13f}  oracle E_imp {oo['E']:.13f}  gpu E_imp {obs['E']:.13f}")
+    fd = (float(ref["F_p"]) - float(ref["F_m"])) / (2 * h)
+    d2 = (float(ref["E_p"]) - float(ref["E_m"])) / (2 * h)
+    F0, E0 = float(ref["F_0"]), float(ref["E_0"])
+    say(f"  dF/dK {r['dF_dK']:.13f}  oracle FD {fd:.13f}  oracle E_imp {E0:.13f}  gpu E_imp {obs['E']:.13f}")
     say(f"  d2F/dK2 {r['d2F_dK2']:.9f}  oracle central difference of E_imp {d2:.9f}")
     assert abs(r["F"] - F0) <= 1e-11 * abs(F0)
     assert abs(r["dF_dK"] - fd) <= 1e-7
-    assert abs(r["dF_dK"] - oo["E"]) <= 1e-9
+    assert abs(r["dF_dK"] - E0) <= 1e-9
     assert abs(r["dF_dK"] - obs["E"]) <= 1e-9
     assert abs(r["d2F_dK2"] - d2) <= 1e-5 * abs(d2)
 

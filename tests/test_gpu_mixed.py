@@ -12,6 +12,7 @@ Tolerances are derived from FP32 rounding (u = 2^-24):
     E within 1e-5 absolute (the accuracy the mixed path is specified to reach).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -110,43 +111,36 @@ def test_mixed_ising_fixed_point(T, m):
     assert abs(ob["M"] - E.ising_magnetization(K)) <= 1e-5
 
 
-def _oracle_fixed_point(V, K, m, tol, max_steps, tau):
-    o = O.OracleCTMRG(V, K, m, tau=tau)
-    for i in range(max_steps):
-        o.step()
-        if i >= 2 and o.delta < tol:
-            break
-        if i % 100 == 99:
-            say(f"  oracle step {i + 1} delta {o.delta:.2e}")
-    return o
-
-
 @pytest.mark.parametrize("T", [0.40])
 def test_mixed_dodecahedron_fixed_point_m16(T):
     """q = 20, m = 16: the mixed path's fixed point against the FP64 oracle's, both with the
-    same multiplet gap tolerance.  The oracle iterates until its spectrum changes by less
-    than 1e-12; the mixed path until it changes by less than 1e-6 (its steps carry FP32
-    noise of about 1e-7 in w^4, so the change stalls there)."""
+    same multiplet gap tolerance 1e-6.  The oracle iterated until its spectrum changed by
+    less than 1e-12 (stored in tests/golden/ by make_golden.py); the mixed path runs until
+    it changes by less than 1e-6 (its steps carry FP32 noise of about 1e-7 in w^4, so the
+    change stalls there)."""
     ct = _lib()
     V = I.dodecahedron()
     K = 1.0 / T
     m, gap = 16, 1e-6
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"fixedpoint_q20_m16_T{T:.2f}_tau1e-06.npz")
+    if not os.path.exists(path):
+        pytest.fail("missing golden file: run tests/golden/make_golden.py")
+    with np.load(path, allow_pickle=False) as z:
+        oo = {k: z[k] for k in z.files}
+    assert bool(oo["converged"]) and float(oo["tau"]) == gap
     say(f"[mixed fixed point] q=20 m={m} T={T}")
     g = ct.CTMRG(V, K, m, precision="fp32", gap_tol=gap)
     ks, d, conv = g.run_to_fixed_point(1e-6, 1500)
     og = g.observables()
     g.close()
-    say(f"  gpu: steps {ks} delta {d:.2e} m_eff {og['m_eff']}")
+    say(f"  gpu: steps {ks} delta {d:.2e} m_eff {og['m_eff']}; oracle steps {int(oo['steps'])} m_eff {int(oo['m_eff'])}")
     assert conv
-    o = _oracle_fixed_point(V, K, m, 1e-12, 1500, gap)
-    assert o.delta < 1e-12
-    oo = o.observables()
-    say(f"  oracle: steps {len(o.nC)} m_eff {oo['m_eff']}")
-    say(f"  f {og['f']:.12f} vs {oo['f']:.12f}; E {og['E']:.9f} vs {oo['E']:.9f}; M {og['M']:.9f} vs {oo['M']:.9f}")
-    assert og["m_eff"] == oo["m_eff"]
-    assert abs(og["f"] - oo["f"]) <= 1e-6 * abs(oo["f"])
-    assert abs(og["E"] - oo["E"]) <= 1e-5
-    assert abs(og["M"] - oo["M"]) <= 1e-5
+    of, oE, oM = float(oo["f"]), float(oo["E"]), float(oo["M"])
+    say(f"  f {og['f']:.12f} vs {of:.12f}; E {og['E']:.9f} vs {oE:.9f}; M {og['M']:.9f} vs {oM:.9f}")
+    assert og["m_eff"] == int(oo["m_eff"])
+    assert abs(og["f"] - of) <= 1e-6 * abs(of)
+    assert abs(og["E"] - oE) <= 1e-5
+    assert abs(og["M"] - oM) <= 1e-5
 
 
 def test_mixed_vs_fp64_one_step_m512():

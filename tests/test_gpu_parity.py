@@ -8,6 +8,7 @@ rotations inside degenerate multiplets, so they are compared through
 projectors and residuals.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -30,6 +31,18 @@ def _lib():
 
 def say(*a):
     print(*a, flush=True)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    """Stored oracle values (tests/golden/, written by make_golden.py from the oracle alone)."""
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail(f"missing golden file {name}: run tests/golden/make_golden.py")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
 
 
 # --------------------------------------------------------------------------- extension
@@ -253,32 +266,25 @@ def test_dodecahedron_free_boundary_m8_500_steps():
 def test_dodecahedron_fixed_boundary_m16(T, tol):
     """Fixed points reached independently by the GPU and the oracle (each iterated until
     Delta < tol); the trajectories may differ transiently (a level crossing at the cut
-    amplifies rounding differences) but the fixed point is the same."""
+    amplifies rounding differences) but the fixed point is the same.  The oracle's fixed
+    point is stored in tests/golden/ (written by make_golden.py from the oracle alone)."""
     ct = _lib()
     V = I.dodecahedron()
     K, m = 1.0 / T, 16
-    say(f"[fixed point] dodecahedron m=16 T={T} fixed")
+    ref = _golden(f"fixedpoint_q20_m16_T{T:.2f}.npz")
+    assert bool(ref["converged"]) and float(ref["tol"]) == tol
+    say(f"[fixed point] dodecahedron m=16 T={T} fixed; oracle converged in {int(ref['steps'])} steps")
     g = ct.CTMRG(V, K, m)
     ks, dg, conv = g.run_to_fixed_point(tol, 1500)
     assert conv
     og = g.observables()
-    say(f"  gpu converged in {ks} steps")
-    o = O.OracleCTMRG(V, K, m)
-    i = 0
-    while i < 1500:
-        o.step()
-        i += 1
-        if i % 100 == 0:
-            say(f"  oracle step {i} delta={o.delta:.2e}")
-        if i >= 2 and o.delta < tol:
-            break
-    assert o.delta < tol
-    oo = o.observables()
-    assert og["m_eff"] == oo["m_eff"]
-    assert abs(og["f"] - oo["f"]) <= 1e-10 * abs(oo["f"])
-    assert abs(og["E"] - oo["E"]) <= 1e-8
-    assert abs(og["M"] - oo["M"]) <= 1e-8
     g.close()
+    say(f"  gpu converged in {ks} steps: f {og['f']!r} ({float(ref['f'])!r}) E {og['E']!r} ({float(ref['E'])!r}) "
+        f"M {og['M']!r} ({float(ref['M'])!r})")
+    assert og["m_eff"] == int(ref["m_eff"])
+    assert abs(og["f"] - float(ref["f"])) <= 1e-10 * abs(float(ref["f"]))
+    assert abs(og["E"] - float(ref["E"])) <= 1e-8
+    assert abs(og["M"] - float(ref["M"])) <= 1e-8
 
 
 def test_checkpoint_resume_bitwise():

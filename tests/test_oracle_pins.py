@@ -261,3 +261,96 @@ def test_free_and_fixed_boundary_agree_above_tc():
     b = O.run_fixed_point(I.ising(), K, 16, bc="free", tol=1e-13)[1]
     assert abs(a["f"] - b["f"]) <= 1e-11 * abs(a["f"])
     assert abs(b["M"]) < 1e-8
+
+
+# --------------------------------------------------------------------------- entanglement entropy (Eq. 6)
+
+def _two_state_entropy(K):
+    """First step of the fixed-boundary Ising run by hand: with P = [1] on the boundary spin,
+    C'[(s'),(sigma')] = exp(K (1 + v_sigma' + v_sigma' v_s' + v_s')) = [[e^{4K}, 1], [1, 1]].
+    Its eigenvalues solve l^2 - (a + 1) l + (a - 1) = 0, a = e^{4K}; rho = C'^4 / Tr C'^4
+    has the two weights p = l_+^4 / (l_+^4 + l_-^4) and 1 - p."""
+    a = math.exp(4.0 * K)
+    r = math.sqrt((a - 1.0) ** 2 + 4.0)
+    lp, lm = 0.5 * (a + 1.0 + r), 0.5 * (a + 1.0 - r)
+    p = lp ** 4 / (lp ** 4 + lm ** 4)
+    return -p * math.log(p) - (1.0 - p) * math.log(1.0 - p)
+
+
+@pytest.mark.parametrize("K", [0.2, 0.45])
+def test_entropy_first_step_closed_form(K):
+    o = O.OracleCTMRG(I.ising(), K, 4)
+    r = o.step()
+    assert r.lam.shape == (2,)
+    assert abs(r.S_E - _two_state_entropy(K)) <= 1e-14
+
+
+@pytest.mark.parametrize("T", [2.0, 1.5])
+def test_entropy_ising_fixed_point_free_fermions(T):
+    """At the Ising fixed point rho = C^4/Tr C^4 is Baxter's free-fermion corner density
+    matrix: levels -ln(rho_j/rho_1) are sums of distinct 2 j eps, and S_E = -Tr rho ln rho is
+    the sum over modes of ln(1+e^{-e_j}) + e_j/(e^{e_j}+1) (closed form in tests/exact.py)."""
+    K = 1.0 / T
+    o, obs = O.run_fixed_point(I.ising(), K, 32, tol=1e-14)
+    assert abs(obs["S_E"] - E.ising_ctm_entropy(K)) <= 1e-12
+    w4 = np.sort(o.last.w ** 4)[::-1]
+    levels = -np.log(w4[:6] / w4[0])
+    assert np.abs(levels - E.ising_ctm_levels(K, 6)).max() <= 1e-7
+
+
+@pytest.mark.parametrize("V,K,m,steps", [(I.tetrahedron(), 0.5, 16, 2), (I.dodecahedron(), 2.0, 8, 1),
+                                         (I.cube(), 1.0, 8, 2)])
+def test_entropy_is_von_neumann_of_rho(V, K, m, steps):
+    """Eq. 6 by a different route: rho = C'^4 / Tr C'^4 formed as a matrix and
+    S = -Tr(rho logm(rho)) with the matrix logarithm, on the step's own extended corner."""
+    from scipy import linalg
+    import warnings
+    o = O.OracleCTMRG(V, K, m)
+    for _ in range(steps):
+        r = o.step(keep_cext=True)
+    C = 0.5 * (r.cext + r.cext.T)
+    C4 = np.linalg.matrix_power(C, 4)
+    rho = C4 / np.trace(C4)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        S = -float(np.trace(rho @ linalg.logm(rho)).real)
+    assert abs(r.S_E - S) <= 1e-13
+
+
+def test_entropy_maximal_for_equal_weights():
+    """The bound of Algorithm 3 is attained by a flat spectrum: n equal |omega| give ln n."""
+    for n in (1, 2, 7, 160):
+        w = np.full(n, n ** -0.25)
+        w[::3] *= -1.0
+        assert abs(O.entropy(w) - math.log(n)) <= 1e-13 * max(1.0, math.log(n))
+
+
+@pytest.mark.parametrize("planted", ["ln_w", "w_squared"])
+def test_planted_entropy_mistakes(monkeypatch, planted):
+    """-sum w^4 ln w (a factor 4 off) and -sum w^2 ln w^4 fail the closed forms above."""
+    def ln_w(w):
+        w4 = w ** 4
+        nz = w4 > 0
+        return float(-np.sum(w4[nz] * np.log(np.abs(w[nz]))))
+
+    def w_squared(w):
+        w2 = w ** 2
+        nz = w2 > 0
+        return float(-np.sum(w2[nz] * np.log(w2[nz] ** 2)))
+
+    monkeypatch.setattr(O, "entropy", {"ln_w": ln_w, "w_squared": w_squared}[planted])
+    o = O.OracleCTMRG(I.ising(), 0.45, 4)
+    r = o.step()
+    assert abs(r.S_E - _two_state_entropy(0.45)) > 1e-3
+    o, obs = O.run_fixed_point(I.ising(), 0.5, 32, tol=1e-14)
+    assert abs(obs["S_E"] - E.ising_ctm_entropy(0.5)) > 1e-4
+
+
+def test_fix_signs_hand_values():
+    """The gauge convention: each column is negated when its entry of largest magnitude (the
+    first one among equals) is negative; columns are otherwise unchanged."""
+    U = np.array([[0.6, -0.8, 0.5], [-0.8, 0.6, -0.5], [0.0, 0.0, 0.0]])
+    F = O.fix_signs(U)
+    assert np.array_equal(F[:, 0], [-0.6, 0.8, 0.0])
+    assert np.array_equal(F[:, 1], [0.8, -0.6, 0.0])
+    assert np.array_equal(F[:, 2], [0.5, -0.5, 0.0])
