@@ -211,6 +211,23 @@ ctmrg_status ctmrg_extend(ctmrg_ctx *ctx);
 ctmrg_status ctmrg_eigh_topk(int n, const double *A, int k, int band, double *evals, double *kept_vals,
                              double *evecs);
 
+/* The same computation as ctmrg_eigh_topk, for callers that cannot allocate device
+ * memory (code that runs under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): no hipMalloc, hipFree, stream creation or allocating
+ * library call.  Every device buffer of the call is carved from one file-scope
+ * device array of CTMRG_NOALLOC_BYTES that each GPU the library runs on holds
+ * until the process ends.  Sizes: n <= CTMRG_NOALLOC_NMAX, k <= CTMRG_NOALLOC_KMAX
+ * (larger sizes return CTMRG_E_INVALID_ARG without touching the device).  Runs
+ * on the null stream of the current device and returns when the outputs are in
+ * host memory.  All calls on one GPU share that GPU's array: calls that overlap
+ * on one GPU (from several host threads) race and must be serialized by the
+ * caller.  Arguments, outputs and the other errors as ctmrg_eigh_topk. */
+#define CTMRG_NOALLOC_NMAX 1024
+#define CTMRG_NOALLOC_KMAX 128
+#define CTMRG_NOALLOC_BYTES (96u << 20)
+ctmrg_status ctmrg_eigh_topk_noalloc(int n, const double *A, int k, int band, double *evals, double *kept_vals,
+                                     double *evecs);
+
 /* Stage timing with HIP events on the context's stream.  While enabled, each
  * step synchronizes once more at its end and accumulates the device time of
  * its stages (milliseconds, summed over the steps since enabling):

@@ -69,6 +69,8 @@ struct EigWork {
     // panel's QR runs on the caller's stream
     hipStream_t s2 = nullptr;
     hipEvent_t ev_cols = nullptr, ev_update = nullptr;
+    // false when the buffers were carved from caller memory (eig_carve): eig_free then frees nothing
+    bool owned = true;
 };
 
 // Stage boundaries recorded when EigWork::marks is set (indices into marks).
@@ -96,6 +98,10 @@ struct PostOut {
 };
 
 hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b);
+// The same buffers laid out in caller memory [base, base + bytes) (at least eig_bytes(Nmax, kmax, b),
+// 256-byte aligned); no allocation, no second stream (the look-ahead of stage 1 then runs in order on
+// the caller's stream).  The exchange slots and error flags are reset by fill kernels on s.
+hipError_t eig_carve(EigWork &w, void *base, size_t bytes, int Nmax, int kmax, int b, hipStream_t s);
 void eig_free(EigWork &w);
 size_t eig_bytes(int Nmax, int kmax, int b);
 

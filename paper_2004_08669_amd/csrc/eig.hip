@@ -1486,56 +1486,30 @@ static size_t splitk_elems_for(int Nmax, int b)
     return std::max<size_t>((size_t)64 * Nmax * std::max(b, 64), (size_t)1024 * 64 * 64);
 }
 
-size_t eig_bytes(int Nmax, int kmax, int b)
-{
-    const int np = num_panels(Nmax, b);
-    const int Tmax = max_steps(Nmax, b) + 1;
-    const int nJ = (Nmax + b - 1) / b;
-    size_t s = 0;
-    s += align_up(sizeof(double) * (size_t)panel_v_offset(Nmax, b, np) + 8);
-    s += align_up(sizeof(double) * (size_t)np * b * b + 8);
-    s += align_up(sizeof(double) * (size_t)np * b + 8);
-    s += 2 * align_up(sizeof(double) * (size_t)Nmax * 2 * b);
-    s += 2 * align_up(sizeof(double) * (size_t)Nmax * b);
-    s += align_up(sizeof(double) * 4 * b * b);
-    s += align_up(sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b)));
-    s += align_up(sizeof(double) * splitk_elems_for(Nmax, b));
-    s += align_up(sizeof(double) * (size_t)Nmax * 2 * b);
-    s += align_up(sizeof(double) * (size_t)Nmax * Tmax * b);
-    s += align_up(sizeof(double) * (size_t)Nmax * Tmax);
-    s += align_up(sizeof(double) * (size_t)nJ * Tmax * b * b);
-    s += align_up(sizeof(double) * (size_t)ceil_div(np, bt1_g(b)) * BT1_RS * bt1_g(b) * b * bt1_g(b) * b + 8);
-    s += align_up(sizeof(double) * (size_t)ceil_div(np, bt1_g(b)) * bt1_g(b) * b * bt1_g(b) * b + 8);
-    s += align_up(sizeof(double) * 2 * (size_t)bt1_g(b) * b * kmax);
-    s += 4 * align_up(sizeof(double) * (size_t)Nmax);
-    s += align_up(sizeof(double) * 4 * BIS_SLICE);
-    s += 2 * align_up(sizeof(double) * (size_t)Nmax * kmax);
-    s += align_up(sizeof(double) * (size_t)kmax * kmax);
-    const size_t kpad = ((size_t)kmax + 63) / 64 * 64;
-    s += align_up(sizeof(double) * 5 * (size_t)Nmax * kpad);
-    s += align_up(sizeof(int) * (size_t)Nmax * kpad);
-    s += 2 * align_up(sizeof(int) * (size_t)(kmax + 2));
-    s += align_up(sizeof(double) * 8) + align_up(64);
-    return s;
-}
-
 __global__ void __launch_bounds__(256)
 ysym_items_kernel(const double *A, long lda, const double *V, int n, int ch, double *P1, double *P2);
 
-hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
+namespace {
+struct EigReq {
+    void **p;
+    size_t bytes;
+};
+}  // namespace
+
+// Sizes, in the order the buffers are laid out; every entry is rounded to 256 bytes when carved.
+static std::vector<EigReq> eig_requests(EigWork &w, int Nmax, int kmax, int b)
 {
+    const int np = num_panels(Nmax, b);
+    const size_t kpad = ((size_t)kmax + 63) / 64 * 64;  // threads of invit_kernel
     w.Nmax = Nmax;
     w.kmax = kmax;
     w.b = b;
     w.Tmax = max_steps(Nmax, b) + 1;
     w.nJmax = (Nmax + b - 1) / b;
-    const int np = num_panels(Nmax, b);
-    const size_t kpad = ((size_t)kmax + 63) / 64 * 64;  // threads of invit_kernel
     w.splitk_elems = splitk_elems_for(Nmax, b);
-    struct Req { void **p; size_t bytes; };
-    double *bounds_unused = nullptr;
-    (void)bounds_unused;
-    std::vector<Req> reqs = {
+    return {
+        {(void **)&w.part, sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b))},
+        {(void **)&w.err, 64},
         {(void **)&w.Vx, sizeof(double) * (size_t)panel_v_offset(Nmax, b, np) + 8},
         {(void **)&w.Tp, sizeof(double) * (size_t)np * b * b + 8},
         {(void **)&w.tau1, sizeof(double) * (size_t)np * b + 8},
@@ -1544,7 +1518,6 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.Y, sizeof(double) * (size_t)Nmax * b},
         {(void **)&w.X, sizeof(double) * (size_t)Nmax * b},
         {(void **)&w.sm, sizeof(double) * 4 * b * b},
-        {(void **)&w.part, sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b))},
         {(void **)&w.splitk, sizeof(double) * w.splitk_elems},
         {(void **)&w.band, sizeof(double) * (size_t)Nmax * 2 * b},
         {(void **)&w.refl, sizeof(double) * (size_t)Nmax * w.Tmax * b},
@@ -1565,9 +1538,58 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.ipiv, sizeof(int) * (size_t)Nmax * kpad},
         {(void **)&w.clist, sizeof(int) * (size_t)(kmax + 2) * 2},
         {(void **)&w.cstart, sizeof(int) * (size_t)(kmax + 2)},
-        {(void **)&w.err, 64},
     };
-    for (auto &r : reqs) {
+}
+
+size_t eig_bytes(int Nmax, int kmax, int b)
+{
+    EigWork w;
+    size_t s = 0;
+    for (const EigReq &r : eig_requests(w, Nmax, kmax, b)) s += align_up(r.bytes);
+    return s;
+}
+
+// Occupancy-derived limits and the kernel attributes the solver needs (no allocation).
+static hipError_t eig_setup_limits(EigWork &w, int b)
+{
+    const size_t tg_smem = sizeof(double) * ((size_t)bt1_g(b) * b * (bt1_g(b) * b + 1) + bt1_g(b) * b);
+    hipError_t e = hipFuncSetAttribute(b == 32 ? (const void *)bt1_tg_kernel<32> : (const void *)bt1_tg_kernel<16>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)tg_smem);
+    // panel QR workgroups that the device holds at once
+    int per_cu = 0, dev = 0, cus = 0;
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, b == 32 ? (const void *)panel_qr_kernel<32> : (const void *)panel_qr_kernel<16>, 256, 0);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    w.pqr_cap = per_cu * cus;
+    int ys_cu = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ys_cu, (const void *)ysym_items_kernel, 256, 0);
+    w.ysym_cap = std::max(1, ys_cu * cus);
+    return e;
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, size_t n, unsigned long long v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// The panel-QR exchange slots to the empty marker, the error flags to zero (fill kernels on s).
+static hipError_t eig_reset_flags(EigWork &w, hipStream_t s)
+{
+    const size_t nslot = 2 * pqr_slot_set(w.b, pqr_gmax(w.Nmax, w.b));
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(std::min<size_t>(1024, (nslot + 255) / 256)), dim3(256), 0, s,
+                       (unsigned long long *)w.part, nslot, ~0ull);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, s, (unsigned long long *)w.err, (size_t)8, 0ull);
+    w.pqr_launches = 0;
+    w.pqr_gprev = 0;
+    return hipGetLastError();
+}
+
+hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
+{
+    w.owned = true;
+    for (const EigReq &r : eig_requests(w, Nmax, kmax, b)) {
         hipError_t e = hipMalloc(r.p, r.bytes);
         if (e != hipSuccess) {
             eig_free(w);
@@ -1576,23 +1598,7 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
     }
     (void)hipMemset(w.part, 0xFF, sizeof(double) * 2 * pqr_slot_set(b, pqr_gmax(Nmax, b)));  // all slots empty
     (void)hipMemset(w.err, 0, 64);
-    const size_t tg_smem = sizeof(double) * ((size_t)bt1_g(b) * b * (bt1_g(b) * b + 1) + bt1_g(b) * b);
-    hipError_t e = hipFuncSetAttribute(b == 32 ? (const void *)bt1_tg_kernel<32> : (const void *)bt1_tg_kernel<16>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)tg_smem);
-    {
-        // panel QR workgroups that the device holds at once
-        int per_cu = 0, dev = 0, cus = 0;
-        if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, b == 32 ? (const void *)panel_qr_kernel<32> : (const void *)panel_qr_kernel<16>, 256, 0);
-        if (e == hipSuccess) e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        w.pqr_cap = per_cu * cus;
-        int ys_cu = 0;
-        if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ys_cu, (const void *)ysym_items_kernel, 256, 0);
-        w.ysym_cap = std::max(1, ys_cu * cus);
-    }
+    hipError_t e = eig_setup_limits(w, b);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_cols, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_update, hipEventDisableTiming);
@@ -1603,13 +1609,31 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b)
     return hipSuccess;
 }
 
+hipError_t eig_carve(EigWork &w, void *base, size_t bytes, int Nmax, int kmax, int b, hipStream_t s)
+{
+    w = EigWork();
+    w.owned = false;
+    char *p = static_cast<char *>(base);
+    size_t used = 0;
+    for (const EigReq &r : eig_requests(w, Nmax, kmax, b)) {
+        const size_t sz = align_up(r.bytes);
+        if (used + sz > bytes) return hipErrorInvalidValue;
+        *r.p = p + used;
+        used += sz;
+    }
+    hipError_t e = eig_setup_limits(w, b);
+    if (e == hipSuccess) e = eig_reset_flags(w, s);
+    return e;
+}
+
 void eig_free(EigWork &w)
 {
     void *ptrs[] = {w.Vx, w.Tp, w.tau1, w.VW, w.WV, w.Y, w.X, w.sm, w.part, w.splitk, w.band, w.refl, w.rtau,
                     w.T2, w.bt1_gram, w.bt1_T, w.bt1_W, w.d, w.e, w.e2, w.evals, w.slices, w.ZT, w.Ztmp, w.G, w.lu, w.ipiv, w.clist,
                     w.cstart, w.err};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    if (w.owned)
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
     if (w.ev_cols) (void)hipEventDestroy(w.ev_cols);
     if (w.ev_update) (void)hipEventDestroy(w.ev_update);
     if (w.s2) (void)hipStreamDestroy(w.s2);
@@ -1907,7 +1931,15 @@ static hipError_t stage1(EigWork &w, double *A, long lda, int N, hipStream_t s)
                 if (e != hipSuccess) return e;
             }
             // ... then the rest of the update on s2, beside the next panel's QR on s (the QR is on
-            // the critical path; the update ends first, so the wait for it costs nothing)
+            // the critical path; the update ends first, so the wait for it costs nothing).  Without a
+            // second stream (carved workspace) the two run in order on s.
+            if (!w.s2) {
+                e = gemm_mfma_lower(A_RM{w.VW + (long)b * 2 * b, 2 * b}, B_T{w.WV + (long)b * 2 * b, 2 * b},
+                                    EpiAxpbyLower{A22 + (long)b * lda + b, lda, -1.0, 1.0}, n - b, 2 * b, s);
+                if (e == hipSuccess) e = panel_qr(w, A, lda, N, pi + 1, s);
+                if (e != hipSuccess) return e;
+                continue;
+            }
             if ((e = hipEventRecord(w.ev_cols, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(w.s2, w.ev_cols, 0)) != hipSuccess) return e;
             e = gemm_mfma_lower(A_RM{w.VW + (long)b * 2 * b, 2 * b}, B_T{w.WV + (long)b * 2 * b, 2 * b},

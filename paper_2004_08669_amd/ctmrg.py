@@ -113,6 +113,7 @@ def load():
         "ctmrg_get_buffer": ([_vp, ctypes.c_int, _dp, ctypes.c_size_t], ctypes.c_int),
         "ctmrg_extend": ([_vp], ctypes.c_int),
         "ctmrg_eigh_topk": ([ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp], ctypes.c_int),
+        "ctmrg_eigh_topk_noalloc": ([ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp], ctypes.c_int),
         "ctmrg_set_profiling": ([_vp, ctypes.c_int], ctypes.c_int),
         "ctmrg_get_stage_times": ([_vp, _dp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "ctmrg_last_error": ([_vp], ctypes.c_char_p),
@@ -160,6 +161,19 @@ def eigh_topk(A: np.ndarray, k: int, band: int = 0):
     st = load().ctmrg_eigh_topk(n, _p(A), k, band, _p(ev), _p(kept), _p(vec))
     if st != CTMRG_OK:
         raise CTMRGError(st, "ctmrg_eigh_topk")
+    return ev, kept, vec
+
+
+def eigh_topk_noalloc(A: np.ndarray, k: int, band: int = 0):
+    """ctmrg_eigh_topk_noalloc: the same outputs as eigh_topk, computed without device allocation."""
+    A = _f64(A)
+    n = A.shape[0]
+    ev = np.empty(n)
+    kept = np.empty(k)
+    vec = np.empty((n, k))
+    st = load().ctmrg_eigh_topk_noalloc(n, _p(A), k, band, _p(ev), _p(kept), _p(vec))
+    if st != CTMRG_OK:
+        raise CTMRGError(st, "ctmrg_eigh_topk_noalloc")
     return ev, kept, vec
 
 
