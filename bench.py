@@ -133,33 +133,115 @@ def cpu_baseline(q_vectors, K, m_sample, m_target):
     }
 
 
-def run_path(V, K, m, band, precision, gap_tol, warmup, steps):
-    """Warm up, then time `steps` CTMRG steps of one context; per-stage HIP-event times."""
+def run_path(V, K, m, band, precision, gap_tol, warmup, steps, eig="two_stage"):
+    """Warm up, then time `steps` CTMRG steps of one context; per-stage HIP-event times, and for
+    the warm-started eigensolver its counters over the timed steps and the HIP-event times of
+    its products C' V."""
     import torch
     from paper_2004_08669_amd import ctmrg
-    g = ctmrg.CTMRG(V, K, m, band=band, precision=precision, gap_tol=gap_tol)
+    g = ctmrg.CTMRG(V, K, m, band=band, precision=precision, gap_tol=gap_tol, eig=eig)
+    tag = f"{precision}/{eig}"
     for i in range(warmup):
         g.step(1)
-        print(f"# {precision} warmup step {i + 1}/{warmup}", file=sys.stderr, flush=True)
+        print(f"# {tag} warmup step {i + 1}/{warmup}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     g.set_profiling(True)
+    before = g.eig_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         g.step(1)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    print(f"# {precision}: {steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
+    print(f"# {tag}: {steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
     stages, nsteps = g.stage_times()
+    after = g.eig_stats()
     obs = g.observables()
     g.close()
     dt = t1 - t0
-    return {
+    out = {
         "steps_per_s": steps / dt,
         "ms_per_step": 1000.0 * dt / steps,
         "stage_ms": {k: v / max(1, nsteps) for k, v in stages.items()},
         "obs": obs,
     }
+    if eig == "warm":
+        ws = after["warm_steps"] - before["warm_steps"]
+        fb = after["fallback_steps"] - before["fallback_steps"]
+        out["warm"] = {
+            "timed_steps": steps,
+            "warm_steps": ws,
+            "fallback_steps": fb,
+            "fallback_rate": fb / max(1, ws + fb),
+            "passes_per_step": (after["passes"] - before["passes"]) / steps,
+            "products_per_step": (after["products"] - before["products"]) / steps,
+            "tail_bound_last": after["tail_bound_last"],
+            "last_residual": after["last_residual"],
+            "product_ms": after["product_ms"],
+            "product_flops": after["product_flops"],
+            "product_launches": after["product_launches"],
+        }
+    return out
+
+
+def time_to_fixed_point(V, T, m, tol, max_steps, band):
+    """Wall time of whole runs to the fixed point (spectral change below tol) at q=20, m=64,
+    from the fixed boundary, on three routes: FP64 with the two-stage eigensolver, FP64 with
+    the warm-started one, and the mixed path (warm-started) to its FP32 noise floor followed
+    by FP64 polishing steps (counted).  f, E, M and S_E are compared with the oracle's fixed
+    point stored in tests/golden (same m, T and tolerance)."""
+    import numpy as np
+    import torch
+    from paper_2004_08669_amd import ctmrg
+    K = 1.0 / T
+    path = os.path.join(ROOT, "tests", "golden", f"fixedpoint_q20_m{m}_T{T:.2f}.npz")
+    ref = None
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            ref = {k: z[k] for k in z.files}
+
+    def errs(ob):
+        if ref is None:
+            return None
+        return {"f_rel": abs(ob["f"] - float(ref["f"])) / abs(float(ref["f"])),
+                "E_abs": abs(ob["E"] - float(ref["E"])), "M_abs": abs(ob["M"] - float(ref["M"])),
+                "S_E_abs": abs(ob["S_E"] - float(ref["S_E"])), "m_eff": [ob["m_eff"], int(ref["m_eff"])]}
+
+    out = {"m": m, "T": T, "tol": tol, "max_steps": max_steps,
+           "reference": (f"oracle fixed point (FP64, Jacobi / LAPACK eigensolver), {int(ref['steps'])} steps"
+                         if ref is not None else None)}
+    for name, prec, eig in (("fp64_two_stage", "fp64", "two_stage"), ("fp64_warm", "fp64", "warm")):
+        g = ctmrg.CTMRG(V, K, m, band=band, precision=prec, eig=eig)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ks, d, conv = g.run_to_fixed_point(tol, max_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ob = g.observables()
+        st = g.eig_stats()
+        g.close()
+        out[name] = {"seconds": dt, "steps": ks, "delta": d, "converged": bool(conv), "vs_oracle": errs(ob)}
+        if eig == "warm":
+            out[name]["fallback_steps"] = st["fallback_steps"]
+        print(f"# time to fixed point {name}: {ks} steps, {dt:.2f} s", file=sys.stderr, flush=True)
+    # mixed to its noise floor (gap tolerance 1e-6, change below 1e-6), then FP64 polishing
+    g = ctmrg.CTMRG(V, K, m, band=band, precision="fp32", gap_tol=1e-6, eig="warm")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k1, d1, c1 = g.run_to_fixed_point(1e-6, max_steps)
+    st = g.export_state()
+    g.close()
+    h = ctmrg.CTMRG(V, K, m, band=band, precision="fp64", eig="warm")
+    h.import_state(st)
+    k2, d2, c2 = h.run_to_fixed_point(tol, max_steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ob = h.observables()
+    h.close()
+    out["mixed_then_fp64_warm"] = {"seconds": dt, "steps": k1 + k2, "mixed_steps": k1, "fp64_steps": k2,
+                                   "delta": d2, "converged": bool(c1 and c2), "vs_oracle": errs(ob)}
+    print(f"# time to fixed point mixed+polish: {k1}+{k2} steps, {dt:.2f} s", file=sys.stderr, flush=True)
+    return out
 
 
 EIGEN_STAGES = ["dense_to_band", "band_to_tridiag", "bisection", "select_cut_entropy", "inverse_iteration",
@@ -200,7 +282,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=16,
+                    help="untimed steps; the kept dimension settles at m after about 12 steps from the boundary")
     ap.add_argument("--m", type=int, default=512)
     ap.add_argument("--T", type=float, default=0.4398)
     ap.add_argument("--band", type=int, default=16)
@@ -208,6 +291,9 @@ def main():
                     help="both: time the mixed path (the headline value) and the FP64 path")
     ap.add_argument("--gap-tol", type=float, default=1e-6,
                     help="multiplet gap of the cut, the same on both paths")
+    ap.add_argument("--eig", choices=["both", "two_stage", "warm"], default="both",
+                    help="both: the headline with the two-stage eigensolver, and the warm-started one beside it")
+    ap.add_argument("--no-fixed-point", action="store_true", help="skip the time-to-fixed-point runs (m=64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=128)
     ap.add_argument("--compare-eigh", action="store_true",
@@ -226,10 +312,16 @@ def main():
     V = I.dodecahedron()
     q, m, K = len(V), args.m, 1.0 / args.T
     print(f"# bench: q={q} m={m} T={args.T} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
-    runs = {}
+    runs, wruns = {}, {}
     order = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
-    for prec in order:
-        runs[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps)
+    if args.eig != "warm":
+        for prec in order:
+            runs[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps)
+    if args.eig != "two_stage":
+        for prec in order:
+            wruns[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps, eig="warm")
+    if not runs:
+        runs = wruns
     head_prec = order[0]
     head = runs[head_prec]
     stage_ms = head["stage_ms"]
@@ -272,6 +364,9 @@ def main():
         "avg_launch_ms": stage_ms[dom],
     }
     desc = {"fp32": "mixed (FP32 contractions, FP64 eigensolver and state)", "fp64": "FP64"}
+    head_eig = "warm" if args.eig == "warm" else "two_stage"
+    edesc = {"two_stage": "two-stage eigensolver (all eigenvalues)",
+             "warm": "warm-started top-m eigensolver (bounded spectral tail)"}
     out = {
         "metric": "CTMRG steps/s at q=20 m=512 (mixed vs FP64, same error); % MFMA peak",
         "value": head["steps_per_s"],
@@ -287,8 +382,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"CTMRG step, q=20 dodecahedron, m={m} (C' {q * m}x{q * m}), T={args.T}, fixed boundary, "
-                         f"{desc[head_prec]}"),
+                         f"{desc[head_prec]}, {edesc[head_eig]}"),
             "q": q, "m": m, "T": args.T, "precision": head_prec, "band": args.band, "gap_tol": args.gap_tol,
+            "eigensolver": head_eig,
         },
         "roofline": roofline,
         "contraction_roofline": contraction_roofline,
@@ -312,6 +408,41 @@ def main():
             "S_E_abs": abs(obs["S_E"] - o64["S_E"]),
             "m_eff": [obs["m_eff"], o64["m_eff"]],
         }
+    if wruns and runs is not wruns:
+        f1 = {}
+        for prec, r in wruns.items():
+            w = r["warm"]
+            ent = {"steps_per_s": r["steps_per_s"], "ms_per_step": r["ms_per_step"],
+                   "speedup_vs_two_stage": r["steps_per_s"] / runs[prec]["steps_per_s"] if prec in runs else None}
+            ent.update({k: w[k] for k in ("fallback_steps", "warm_steps", "fallback_rate", "passes_per_step",
+                                          "products_per_step", "tail_bound_last", "last_residual")})
+            ent["stages_ms"] = {k: round(v, 4) for k, v in r["stage_ms"].items() if v > 0}
+            if prec in runs:
+                ow, ot = r["obs"], runs[prec]["obs"]
+                ent["vs_two_stage_after_run"] = {
+                    "f_rel": abs(ow["f"] - ot["f"]) / abs(ot["f"]), "E_abs": abs(ow["E"] - ot["E"]),
+                    "M_abs": abs(ow["M"] - ot["M"]), "S_E_abs": abs(ow["S_E"] - ot["S_E"]),
+                    "m_eff": [ow["m_eff"], ot["m_eff"]]}
+            f1[prec] = ent
+        if "fp32" in wruns and "fp64" in wruns:
+            f1["mixed_over_fp64"] = wruns["fp32"]["steps_per_s"] / wruns["fp64"]["steps_per_s"]
+            if "fp64" in runs:
+                f1["mixed_warm_over_fp64_two_stage"] = wruns["fp32"]["steps_per_s"] / runs["fp64"]["steps_per_s"]
+        # the products C' V of the warm solver (split-K MFMA GEMM and its partial-sum kernel),
+        # each bracketed by HIP events on the stream that runs it
+        w = wruns[head_prec]["warm"]
+        if w["product_launches"] > 0:
+            avg_s = w["product_ms"] * 1e-3 / w["product_launches"]
+            fl = w["product_flops"] / w["product_launches"]
+            ach = fl / avg_s / 1e12
+            f1["product_roofline"] = {
+                "kernel": "C' V products (gemm_mfma split-K + partial sum)", "bound": "mfma",
+                "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
+                "algorithmic_flops_per_launch": fl, "avg_launch_ms": avg_s * 1e3,
+                "launches": w["product_launches"]}
+        out["f1_warm_eigensolver"] = f1
+    if not args.no_fixed_point:
+        out["time_to_fixed_point"] = time_to_fixed_point(V, 0.40, 64, 1e-12, 3000, args.band)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V, K, args.cpu_sample_m, m)
     if args.compare_eigh:

@@ -69,6 +69,31 @@ typedef enum {
 typedef enum { CTMRG_FP64 = 0, CTMRG_FP32 = 1 } ctmrg_precision;
 typedef enum { CTMRG_BC_FIXED = 0, CTMRG_BC_FREE = 1 } ctmrg_bc;
 
+/* Eigensolver of step 3.
+ *   CTMRG_EIG_TWO_STAGE: every step reduces C' to band and tridiagonal form
+ *     (all q m eigenvalues exactly; eigenvectors of the m largest |lambda|).
+ *   CTMRG_EIG_WARM: from the third step on, the leading k = m + warm_guard
+ *     eigenpairs of C' from the previous step's (Chebyshev-filtered subspace
+ *     iteration with Rayleigh-Ritz, all FP64; the kept eigenvectors of every
+ *     step rotated inside each multiplet to match the step before, so that the
+ *     renormalized basis stays in one gauge).  A step whose kept residuals do
+ *     not fall below warm_tol |lambda_1| within the pass limit runs the
+ *     two-stage solver instead.  The products use the lower triangle of C'
+ *     (mirrored into the upper one first), the part the two-stage solver reads.
+ *     n_C and S_E (Eq. 6) then come from the k Ritz values plus the part of
+ *     sum lambda^4 beyond them (see ctmrg_warm_tail), and the spectrum buffer
+ *     holds the k Ritz values ascending followed by NaN. */
+typedef enum { CTMRG_EIG_TWO_STAGE = 0, CTMRG_EIG_WARM = 1 } ctmrg_eig_solver;
+
+/* The part of sum lambda^4 beyond the Ritz block of the warm solver.
+ *   CTMRG_WARM_TAIL_EXACT: sum lambda^4 = ||C'^2||_F^2, from one product C' C'
+ *     (the tiles on and below the diagonal), so n_C is exact to rounding; the
+ *     tail's share of S_E lies within a bound (ctmrg_get_eig_stats).
+ *   CTMRG_WARM_TAIL_BOUND: no product; sum lambda^2 beyond the block is
+ *     ||C'||_F^2 - sum theta^2, each |lambda| is at most |theta_k|, and the
+ *     midpoint of the resulting interval for sum lambda^4 is taken. */
+typedef enum { CTMRG_WARM_TAIL_EXACT = 0, CTMRG_WARM_TAIL_BOUND = 1 } ctmrg_warm_tail;
+
 typedef struct {
     int precision;        /* ctmrg_precision of the contractions; the eigensolver is always FP64 */
     int bc;               /* ctmrg_bc: fixed (all boundary spins = boundary_spin) or free      */
@@ -77,24 +102,42 @@ typedef struct {
     double gap_tol;       /* multiplet gap, relative to |lambda_1| (default 1e-10; >= 1e-6 for FP32) */
     double rank_tol;      /* eigenvalues with |l| <= rank_tol |l_1| are never kept (1e-13)     */
     void *hip_stream;     /* hipStream_t to run on; NULL = a stream owned by the context       */
+    int eig_solver;       /* ctmrg_eig_solver (default CTMRG_EIG_TWO_STAGE)                    */
+    int warm_guard;       /* CTMRG_EIG_WARM: guard vectors below the kept ones (0 = max(8, m/4)) */
+    int warm_degree;      /* CTMRG_EIG_WARM: largest Chebyshev degree per pass, 1..8 (0 = 8)   */
+    double warm_tol;      /* CTMRG_EIG_WARM: kept residuals below warm_tol |lambda_1|
+                             (0 = 1e-12 for FP64 contractions, 1e-9 for FP32)                  */
+    int warm_tail;        /* CTMRG_EIG_WARM: ctmrg_warm_tail (default CTMRG_WARM_TAIL_EXACT)   */
 } ctmrg_options;
 
 typedef struct {
     double f;              /* free energy per site, -(T/2) ln kappa_W                            */
     double E;              /* energy per site from the central plaquette, (1/2) <h_4>           */
     double M;              /* magnetization, Eq. 5 (fixed BC: v_{s0}.v_s; free BC: |<v_s>|)      */
-    double S_E;            /* entanglement entropy of the last step, Eq. 6                      */
+    double S_E;            /* entanglement entropy of the last step, Eq. 6, over all q m eigenvalues
+                              of its C' (after a warm-solved step they are computed here)        */
     double ln_kappa_W;     /* ln of the partition function per vertex from the normalizations  */
     double ln_kappa_ratio; /* the same from Z_d Z_b / Z_h^2 on the current state                 */
     double delta;          /* convergence measure of the last step                              */
     double c_paper;        /* |1 - S_E(k)/S_E(k-1)|, the paper's stopping quantity              */
     int m_eff;             /* kept dimension of the last step                                   */
     int steps;             /* steps taken since init / import                                   */
+    /* Effective correlation length (Sec. II, last paragraph) from the renormalized
+     * row-to-row transfer matrix T = sum_s P_s (x) P_s (m^2 x m^2, the stored P):
+     * its two eigenvalues of largest modulus by Lanczos, xi_e = 1 / ln|l1 / l2|
+     * in rows of vertices (0 if l2 = 0). */
+    double xi_e;
+    double tm_lambda1;     /* leading eigenvalue of T                                            */
+    double tm_lambda2;     /* second eigenvalue by modulus                                       */
+    double tm_residual;    /* max ||T y - l y|| / |l1| of the two Ritz pairs                     */
+    int tm_iterations;     /* Lanczos iterations                                                 */
+    int tm_converged;      /* 1 if both residual estimates fell below 1e-11 |l1|                 */
 } ctmrg_observables_t;
 
 typedef struct ctmrg_ctx ctmrg_ctx;
 
-/* Defaults: FP64, fixed boundary, boundary_spin 0, band 16, gap_tol 1e-10, rank_tol 1e-13. */
+/* Defaults: FP64, fixed boundary, boundary_spin 0, band 16, gap_tol 1e-10, rank_tol 1e-13,
+ * two-stage eigensolver. */
 ctmrg_status ctmrg_default_options(ctmrg_options *opt);
 
 /* Create a context for q spins (vertex_vectors: q x dim row-major unit vectors,
@@ -118,7 +161,10 @@ ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *ctx, double tol, int max_steps,
  * matrices; the free energy from the normalization history).  Needs >= 1 step
  * since init, set_K, set_state or import_state; f and ln_kappa_W need two and
  * are NaN after one.  kept_spectrum (nullable, m entries) receives omega
- * (normalized kept eigenvalues, zero padded).
+ * (normalized kept eigenvalues, zero padded).  After a step solved by the warm
+ * eigensolver, whose C' warm mode keeps, S_E is computed here from all
+ * eigenvalues of that C' (the two-stage reduction, eigenvalues only), which
+ * then also fill the spectrum buffer.
  * Errors: CTMRG_E_STATE before the first step. */
 ctmrg_status ctmrg_observables(ctmrg_ctx *ctx, ctmrg_observables_t *out, double *kept_spectrum);
 
@@ -181,6 +227,15 @@ ctmrg_status ctmrg_set_state(ctmrg_ctx *ctx, int d, const double *P, const doubl
 /* Device bytes a context with these sizes allocates. */
 ctmrg_status ctmrg_workspace_size(int q, int m, const ctmrg_options *opt, size_t *bytes);
 
+/* Device bytes a context allocates later, on first use (each once, kept until
+ * ctmrg_destroy): *observables_bytes by ctmrg_observables (the Lanczos vectors of
+ * xi_e, min(400, m^2) + 1 vectors of m^2 doubles, and the products' buffers), and
+ * *derivative_bytes by ctmrg_fixed_point_derivative / ctmrg_backward (the tangent
+ * solve's 12 (q m)^2 + 13 q m^2 doubles and an eigensolver workspace for all q m
+ * eigenvectors), both at their largest (m_eff = m).  Either pointer may be NULL. */
+ctmrg_status ctmrg_extra_workspace_size(int q, int m, const ctmrg_options *opt, size_t *observables_bytes,
+                                        size_t *derivative_bytes);
+
 /* Inspection of device buffers (host copies), for tests and checkpoints:
  *  CTMRG_BUF_P        m x (q m)  current P in the A layout above
  *  CTMRG_BUF_OMEGA    m          current omega (zero padded)
@@ -236,10 +291,27 @@ ctmrg_status ctmrg_eigh_topk_noalloc(int n, const double *A, int k, int band, do
  *   6 inverse iteration           7 orthonormalization        8 back-transform (band)
  *   9 back-transform (dense)     10 half-row products Y      11 W-mix of Y
  *  12 projection U^T Z           13 normalization            14 whole step
+ *  15 warm eigensolver (CTMRG_EIG_WARM; a step that falls back counts its
+ *     attempt here and its two-stage solve in stages 2-9)
  * Enabling resets the sums. */
-#define CTMRG_NUM_STAGES 15
+#define CTMRG_NUM_STAGES 16
 ctmrg_status ctmrg_set_profiling(ctmrg_ctx *ctx, int enable);
 ctmrg_status ctmrg_get_stage_times(ctmrg_ctx *ctx, double *ms, int *nsteps);
+
+/* Counters of the warm eigensolver since ctmrg_init: out[0] steps solved warm, out[1] steps that fell back to the
+ * two-stage solver after a warm attempt, out[2] passes, out[3] products C' V of
+ * the filter and the Rayleigh-Ritz step, out[4] the largest and out[5] the last
+ * share of sum w^4 beyond the Ritz block (exact with CTMRG_WARM_TAIL_EXACT, a
+ * bound otherwise; the entropy of that share is known within tail ln(N/tail)), out[6] how the last warm
+ * attempt ended (0 converged, 1 no warm start, 2 Gram matrix not positive
+ * definite, 3 Rayleigh-Ritz solver error, 4 non-finite residual, 5 pass limit)
+ * and out[7] its largest kept residual over |lambda_1|.  While stage timing is
+ * enabled (ctmrg_set_profiling, which resets them), out[8] sums the device
+ * milliseconds of the solver's products C' V (HIP events around each launch),
+ * out[9] their algorithmic flops (2 (q m)^2 columns each) and out[10] counts them.
+ * out[11] is S_E as the last warm-solved step gave it (Ritz values plus the
+ * bounded tail; ctmrg_observables computes it over all eigenvalues). */
+ctmrg_status ctmrg_get_eig_stats(ctmrg_ctx *ctx, double out[12]);
 
 const char *ctmrg_last_error(const ctmrg_ctx *ctx);
 void ctmrg_destroy(ctmrg_ctx *ctx);

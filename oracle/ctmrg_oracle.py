@@ -408,6 +408,55 @@ class OracleCTMRG:
         }
 
 
+# ----------------------------------------------------------------------------
+# Effective correlation length (Sec. II, last paragraph)
+# ----------------------------------------------------------------------------
+
+def row_transfer_matrix(P: np.ndarray) -> np.ndarray:
+    """The renormalized row-to-row transfer matrix T = sum_s P_s (x) P_s (d^2 x d^2).
+
+    A full row of vertices is two half-rows, the left one P_s and its mirror image
+    (equal to P_s, since W is invariant under reflection), joined at their common
+    inner end spin s, which is summed.  Rows (alpha, alpha') index the upper legs of
+    the left and right halves, columns (beta, beta') the lower legs."""
+    q, d, _ = P.shape
+    T = np.zeros((d * d, d * d))
+    for s in range(q):
+        T += np.kron(P[s], P[s])
+    return T
+
+
+def row_transfer_apply(P: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """T applied to a d x d matrix X (the vector of T, row-major): sum_s P_s X P_s^t."""
+    return sum(P[s] @ X @ P[s].T for s in range(P.shape[0]))
+
+
+def correlation_length(P: np.ndarray, method: str = "dense", count: int = 2):
+    """The `count` eigenvalues of T of largest modulus (descending |lambda|, zero padded
+    when T has fewer) and the effective correlation length xi_e = 1 / ln(|lambda_1| /
+    |lambda_2|), in rows of vertices (0 when lambda_2 = 0).
+
+    method "dense": all eigenvalues of T (LAPACK), for d^2 up to a few thousand;
+    "arpack": the leading ones of the operator X -> sum_s P_s X P_s^t by ARPACK's
+    implicitly restarted Lanczos (scipy), a single library step."""
+    q, d, _ = P.shape
+    if method == "dense":
+        lam = np.linalg.eigvalsh(row_transfer_matrix(P))
+    elif method == "arpack":
+        from scipy.sparse.linalg import LinearOperator, eigsh
+        op = LinearOperator((d * d, d * d), dtype=np.float64,
+                            matvec=lambda x: row_transfer_apply(P, x.reshape(d, d)).ravel())
+        lam = eigsh(op, k=max(count, 4), which="LM", tol=1e-14, return_eigenvectors=False)
+    else:
+        raise ValueError(method)
+    lam = lam[np.argsort(-np.abs(lam), kind="stable")][:count]
+    if lam.size < count:  # d = 1: T is 1 x 1
+        lam = np.concatenate([lam, np.zeros(count - lam.size)])
+    # a single state (lambda_2 = 0) correlates nothing beyond its row: xi_e = 0
+    xi = 1.0 / np.log(abs(lam[0]) / abs(lam[1])) if abs(lam[1]) > 0 else 0.0
+    return lam, float(xi)
+
+
 def run_fixed_point(V, K, m, bc="fixed", tol=1e-12, max_steps=3000, s0=0, tau=1e-10,
                     rank_tol=1e-13, eig="jacobi"):
     o = OracleCTMRG(V, K, m, bc=bc, s0=s0, tau=tau, rank_tol=rank_tol, eig=eig)

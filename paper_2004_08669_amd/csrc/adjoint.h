@@ -71,6 +71,7 @@ struct AdjWork {
 };
 
 hipError_t adj_alloc(AdjWork &w, int q, int d, int band);
+size_t adj_bytes(int q, int d, int band);  // what adj_alloc allocates
 void adj_free(AdjWork &w);
 
 // Returns 0 on success; otherwise a ctmrg_status value with a message in *msg.

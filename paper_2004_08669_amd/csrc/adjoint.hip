@@ -2,6 +2,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "adjoint.h"
 #include "blocks.h"
@@ -303,15 +304,15 @@ hipError_t align_to(AdjWork &w, double *U, int ldu, const double *lamk, double g
 
 // ---------------------------------------------------------------- allocation
 
-hipError_t adj_alloc(AdjWork &w, int q, int d, int band)
+namespace {
+
+struct AdjReq { double **p; size_t n; };
+
+// The device buffers of the derivative (element counts), for n = q d.
+std::vector<AdjReq> adj_requests(AdjWork &w, int q, int d)
 {
-    w.q = q;
-    w.d = d;
-    w.n = q * d;
-    w.band = band;
-    const size_t n = (size_t)w.n, dd = (size_t)d;
-    struct Req { double **p; size_t n; };
-    Req reqs[] = {
+    const size_t n = (size_t)q * d, dd = (size_t)d;
+    return {
         {&w.A, dd * n}, {&w.OA, dd * n}, {&w.Pt, dd * n}, {&w.om, n + 8}, {&w.omn, n + 8}, {&w.zero, n + 8},
         {&w.Ucur, n * dd}, {&w.Uprev, n * dd}, {&w.Mov, dd * dd},
         {&w.X, n * n}, {&w.C, n * n}, {&w.Y, n * n}, {&w.Z, n * n}, {&w.Cb, n * n}, {&w.Zb, n * n},
@@ -321,7 +322,27 @@ hipError_t adj_alloc(AdjWork &w, int q, int d, int band)
         {&w.T1, n * dd}, {&w.Bm, n * dd}, {&w.R, n * dd}, {&w.dU, n * dd},
         {&w.part, 1024}, {&w.scal, NSCAL + n + 8},
     };
-    for (auto &r : reqs) {
+}
+
+}  // namespace
+
+size_t adj_bytes(int q, int d, int band)
+{
+    AdjWork w;
+    size_t s = 0;
+    for (const AdjReq &r : adj_requests(w, q, d)) s += sizeof(double) * std::max<size_t>(r.n, 1);
+    s += sizeof(PostOut) + sizeof(unsigned) * 4;
+    return s + eig_bytes(q * d, q * d, band);
+}
+
+hipError_t adj_alloc(AdjWork &w, int q, int d, int band)
+{
+    w.q = q;
+    w.d = d;
+    w.n = q * d;
+    w.band = band;
+    const size_t n = (size_t)w.n;
+    for (auto &r : adj_requests(w, q, d)) {
         hipError_t e = hipMalloc((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
         if (e != hipSuccess) return e;
     }

@@ -12,6 +12,8 @@
 #include "contract.h"
 #include "ctmrg.h"
 #include "eig.h"
+#include "warm.h"
+#include "xi.h"
 
 using namespace ctm;
 
@@ -37,6 +39,17 @@ struct ctmrg_ctx {
     PostOut *dPost = nullptr;
     PostOut *hPost = nullptr;
     EigWork eig;
+    // warm-started eigensolver: its workspace, the top-k selection of a fallback step
+    WarmWork warm;
+    int warm_p = 0, warm_k = 0;
+    double *dSelK = nullptr, *dOmK = nullptr;
+    PostOut *dPostK = nullptr, *hPostK = nullptr;
+    int m_eff_prev2 = 0;  // kept dimension of the step before the last
+    // N x N: the half-row Z of a warm-mode step, which leaves that step's C' in dC
+    double *dZ = nullptr;
+    bool last_warm = false;
+    // effective correlation length (Lanczos on the row-to-row transfer matrix), allocated on first use
+    XiWork xi;  // the last step was solved warm (its C' is intact in dC)
     // fixed-point derivative: its workspace and the weight at K +- dK
     AdjWork adj;
     double *dWd = nullptr, *dWHd = nullptr;
@@ -53,6 +66,8 @@ struct ctmrg_ctx {
     hipEvent_t ev[MK_COUNT] = {};
     double stage_ms[MK_COUNT] = {};
     int timed_steps = 0;
+    double warm_last_tail = 0.0;
+    double warm_last_SE = 0.0;        // S_E as the last warm step gave it (bounded tail)
     std::string err;
 };
 
@@ -87,6 +102,14 @@ ctmrg_status hip_fail(ctmrg_ctx *c, hipError_t e, const char *where)
 
 bool valid_band(int b) { return b == 16 || b == 32; }
 
+bool valid_eig_options(const ctmrg_options &o)
+{
+    if (o.eig_solver != CTMRG_EIG_TWO_STAGE && o.eig_solver != CTMRG_EIG_WARM) return false;
+    if (o.warm_guard < 0 || o.warm_degree < 0 || o.warm_degree > WARM_DMAX || !(o.warm_tol >= 0.0)) return false;
+    if (o.warm_tail != CTMRG_WARM_TAIL_EXACT && o.warm_tail != CTMRG_WARM_TAIL_BOUND) return false;
+    return true;
+}
+
 ctmrg_status check_device(ctmrg_ctx *c)
 {
     int dev = 0;
@@ -101,8 +124,9 @@ ctmrg_status check_device(ctmrg_ctx *c)
 
 void free_all(ctmrg_ctx *c)
 {
+    xi_free(c->xi);
     double *bufs[] = {c->dV, c->dW, c->dWH, c->dA, c->dOA, c->dPt, c->dOmega, c->dOmNew, c->dSel,
-                      c->dX, c->dC, c->dU, c->dPart, c->dObs, c->dH, c->dWork};
+                      c->dX, c->dC, c->dU, c->dPart, c->dObs, c->dH, c->dWork, c->dZ};
     for (double *p : bufs)
         if (p) (void)hipFree(p);
     float *fbufs[] = {c->dW32, c->dA32, c->dOA32, c->dU32};
@@ -111,6 +135,11 @@ void free_all(ctmrg_ctx *c)
     if (c->dBook) (void)hipFree(c->dBook);
     if (c->dPost) (void)hipFree(c->dPost);
     if (c->hPost) (void)hipHostFree(c->hPost);
+    if (c->dSelK) (void)hipFree(c->dSelK);
+    if (c->dOmK) (void)hipFree(c->dOmK);
+    if (c->dPostK) (void)hipFree(c->dPostK);
+    if (c->hPostK) (void)hipHostFree(c->hPostK);
+    warm_free(c->warm);
     eig_free(c->eig);
     adj_free(c->adj);
     if (c->dWd) (void)hipFree(c->dWd);
@@ -120,7 +149,9 @@ void free_all(ctmrg_ctx *c)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
 }
 
-size_t context_bytes(int q, int m, int band, int precision)
+int warm_guard(const ctmrg_options &o, int m) { return o.warm_guard > 0 ? o.warm_guard : std::max(8, m / 4); }
+
+size_t context_bytes(int q, int m, int band, int precision, const ctmrg_options &o)
 {
     const size_t N = (size_t)q * m;
     const size_t q4 = (size_t)q * q * q * q;
@@ -132,7 +163,14 @@ size_t context_bytes(int q, int m, int band, int precision)
     s += sizeof(double) * N * m;
     s += sizeof(double) * (4096 + 64 + q + q4 + 64 * q4);
     s += sizeof(Book) + sizeof(PostOut);
-    s += eig_bytes((int)N, m, band);
+    if (o.eig_solver == CTMRG_EIG_WARM) {
+        const int p = warm_guard(o, m), k = (int)std::min<size_t>(N, (size_t)m + p);
+        s += eig_bytes((int)N, k, band) + warm_bytes((int)N, m, p);
+        s += sizeof(double) * (2 * (size_t)k + 16) + sizeof(PostOut);
+        s += sizeof(double) * N * N;  // dZ
+    } else {
+        s += eig_bytes((int)N, m, band);
+    }
     if (precision == CTMRG_FP32) s += sizeof(float) * (q4 + 3 * (size_t)m * N);
     return s;
 }
@@ -148,6 +186,9 @@ ctmrg_status reset_state(ctmrg_ctx *c)
     c->S_last = 0.0;
     c->have_U = false;
     c->cext_valid = false;
+    c->warm.kcur = 0;
+    c->m_eff_prev2 = 0;
+    c->last_warm = false;
     return CTMRG_OK;
 }
 
@@ -200,22 +241,72 @@ ctmrg_status one_step(ctmrg_ctx *c)
     HIPCHK(c, extend_corner(c));
     mark(c->eig, MK_WMIX1, s);
     c->cext_valid = false;
-    // eigenvalues, selection, normalization, entropy, convergence
-    HIPCHK(c, eig_values(c->eig, c->dC, N, N, s));
-    HIPCHK(c, eig_post(c->eig, N, m, c->opt.gap_tol, c->opt.rank_tol, c->dOmega, c->dOmNew, c->dSel, c->dPost, s));
-    mark(c->eig, MK_POST, s);
-    HIPCHK(c, hipMemcpyAsync(c->hPost, c->dPost, sizeof(PostOut), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    const bool warm_mode = c->opt.eig_solver == CTMRG_EIG_WARM;
+    const int m_eff_prev = c->have_U ? c->m_eff : 0;
+    // warm-started solve when the last two steps kept the same dimension
+    int warm_done = 0;
+    if (warm_mode && c->warm.kcur > 0 && c->have_U && c->m_eff == c->m_eff_prev2) {
+        WarmParams prm;
+        prm.gap_tol = c->opt.gap_tol;
+        prm.rank_tol = c->opt.rank_tol;
+        prm.degree = c->opt.warm_degree > 0 ? c->opt.warm_degree : 8;
+        prm.tol = c->opt.warm_tol > 0.0 ? c->opt.warm_tol : (c->opt.precision == CTMRG_FP32 ? 1e-9 : 1e-12);
+        prm.profile = c->profile;
+        std::string why;
+        const long attempts = c->warm.steps;
+        // dX (N x N) is free between the extension and the half-row products
+        HIPCHK(c, warm_symmetrize(c->dC, N, s));
+        double *sq = (c->opt.warm_tail == CTMRG_WARM_TAIL_EXACT) ? c->dX : nullptr;
+        HIPCHK(c, warm_solve(c->warm, c->dC, N, m, prm, c->dOmega, c->dOmNew, c->dSel, c->dPost, c->dU, m_eff_prev,
+                             c->eig.evals, sq, s, &warm_done, &why));
+        if (!warm_done && c->warm.steps > attempts) c->warm.fallbacks += 1;
+    }
+    mark(c->eig, MK_WARM_END, s);
+    if (warm_done) {
+        // the two-stage stages take no time in this step
+        static const int skipped[] = {MK_STAGE1, MK_BULGE, MK_BISECT, MK_POST, MK_VEC_START, MK_INVIT, MK_NS,
+                                      MK_BT2, MK_BT1};
+        for (int id : skipped) mark(c->eig, id, s);
+        HIPCHK(c, hipMemcpyAsync(c->hPost, c->dPost, sizeof(PostOut), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    } else {
+        // eigenvalues, selection, normalization, entropy, convergence
+        HIPCHK(c, eig_values(c->eig, c->dC, N, N, s));
+        HIPCHK(c, eig_post(c->eig, N, m, c->opt.gap_tol, c->opt.rank_tol, c->dOmega, c->dOmNew, c->dSel, c->dPost, s));
+        // warm mode: the top k = m + p as well (the next step's start), into separate outputs
+        if (warm_mode)
+            HIPCHK(c, eig_post(c->eig, N, c->warm_k, c->opt.gap_tol, c->opt.rank_tol, c->warm.zero, c->dOmK, c->dSelK,
+                               c->dPostK, s));
+        mark(c->eig, MK_POST, s);
+        HIPCHK(c, hipMemcpyAsync(c->hPost, c->dPost, sizeof(PostOut), hipMemcpyDeviceToHost, s));
+        if (warm_mode) HIPCHK(c, hipMemcpyAsync(c->hPostK, c->dPostK, sizeof(PostOut), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
     ctmrg_status st = check_kernel_errors(c);
     if (st != CTMRG_OK) return st;
     const PostOut po = *c->hPost;
     if (!std::isfinite(po.n_C) || !(po.n_C > 0.0) || !std::isfinite(po.S_E))
         return fail(c, CTMRG_E_NUMERICAL, "non-finite spectrum of the extended corner");
-    // eigenvectors of the kept states
-    HIPCHK(c, eig_vectors(c->eig, nullptr, 0, N, po.m_eff, c->dSel, po.nclusters, c->dU, m, s));
+    if (warm_done) {
+        c->warm.tail_bound_max = std::max(c->warm.tail_bound_max, po.tail_bound);
+        c->warm_last_tail = po.tail_bound;
+        c->warm_last_SE = po.S_E;
+    } else if (warm_mode) {
+        // eigenvectors of the top k (kept first), kept ones aligned with the previous step's
+        const PostOut pk = *c->hPostK;
+        HIPCHK(c, eig_vectors(c->eig, nullptr, 0, N, pk.m_eff, c->dSelK, pk.nclusters, c->warm.V, c->warm.kmax, s));
+        HIPCHK(c, warm_seed(c->warm, N, m, po.m_eff, pk.m_eff, c->dSelK, c->dU, m_eff_prev, c->opt.gap_tol, s));
+        c->warm_last_tail = 0.0;
+    } else {
+        // eigenvectors of the kept states
+        HIPCHK(c, eig_vectors(c->eig, nullptr, 0, N, po.m_eff, c->dSel, po.nclusters, c->dU, m, s));
+    }
     // half-row: Y = A^T U~, Z = W-mix(Y), P~ = U^T Z
+    // warm mode keeps this step's C' (for the exact S_E of ctmrg_observables): Z goes to dZ
+    double *Zb = warm_mode ? c->dZ : c->dC;
+    c->last_warm = warm_done != 0;
     if (c->opt.precision == CTMRG_FP32) {
-        float *Y32 = reinterpret_cast<float *>(c->dX), *Z32 = reinterpret_cast<float *>(c->dC);
+        float *Y32 = reinterpret_cast<float *>(c->dX), *Z32 = reinterpret_cast<float *>(Zb);
         HIPCHK(c, vectors_to_f32(c->dU, c->dU32, q, m, s));
         HIPCHK(c, halfrow_products_f32(c->dA32, c->dU32, Y32, q, m, s));
         mark(c->eig, MK_HALF, s);
@@ -225,9 +316,9 @@ ctmrg_status one_step(ctmrg_ctx *c)
     } else {
         HIPCHK(c, halfrow_products(c->dA, c->dU, c->dX, q, m, s));
         mark(c->eig, MK_HALF, s);
-        HIPCHK(c, weight_mix(c->dW, c->dX, c->dC, q, m, s));
+        HIPCHK(c, weight_mix(c->dW, c->dX, Zb, q, m, s));
         mark(c->eig, MK_WMIX2, s);
-        HIPCHK(c, projection(c->dU, c->dC, c->dPt, q, m, s));
+        HIPCHK(c, projection(c->dU, Zb, c->dPt, q, m, s));
     }
     mark(c->eig, MK_PROJ, s);
     HIPCHK(c, normalize_and_book(c->dPt, c->dA, q, m, c->dPart, c->dBook, &c->dPost->n_C, &c->dPost->S_E, s));
@@ -240,8 +331,8 @@ ctmrg_status one_step(ctmrg_ctx *c)
     if (st != CTMRG_OK) return st;
     if (c->profile) {
         // stage i spans marks (from[i], to[i])
-        static const int from[] = {MK_START, MK_EXT, MK_WMIX1, MK_STAGE1, MK_BULGE, MK_BISECT, MK_VEC_START, MK_INVIT,
-                                   MK_NS, MK_BT2, MK_BT1, MK_HALF, MK_WMIX2, MK_PROJ};
+        static const int from[] = {MK_START, MK_EXT, MK_WARM_END, MK_STAGE1, MK_BULGE, MK_BISECT, MK_VEC_START,
+                                   MK_INVIT, MK_NS, MK_BT2, MK_BT1, MK_HALF, MK_WMIX2, MK_PROJ};
         static const int to[] = {MK_EXT, MK_WMIX1, MK_STAGE1, MK_BULGE, MK_BISECT, MK_POST, MK_INVIT, MK_NS,
                                  MK_BT2, MK_BT1, MK_HALF, MK_WMIX2, MK_PROJ, MK_NORM};
         for (int i = 0; i < 14; ++i) {
@@ -249,14 +340,17 @@ ctmrg_status one_step(ctmrg_ctx *c)
             HIPCHK(c, hipEventElapsedTime(&ms, c->ev[from[i]], c->ev[to[i]]));
             c->stage_ms[i] += ms;
         }
-        float tot = 0.f;
+        float tot = 0.f, wm = 0.f;
         HIPCHK(c, hipEventElapsedTime(&tot, c->ev[MK_START], c->ev[MK_NORM]));
+        HIPCHK(c, hipEventElapsedTime(&wm, c->ev[MK_WMIX1], c->ev[MK_WARM_END]));
         c->stage_ms[14] += tot;
+        c->stage_ms[15] += wm;
         c->timed_steps += 1;
     }
     c->eig.marks = nullptr;
     c->c_paper = (c->steps > 0 && c->S_last != 0.0) ? fabs(1.0 - po.S_E / c->S_last) : INFINITY;
     c->S_last = po.S_E;
+    c->m_eff_prev2 = c->m_eff;
     c->m_eff = po.m_eff;
     c->delta = po.delta;
     c->have_U = true;
@@ -278,6 +372,24 @@ ctmrg_status ctmrg_default_options(ctmrg_options *opt)
     opt->gap_tol = 1e-10;
     opt->rank_tol = 1e-13;
     opt->hip_stream = nullptr;
+    opt->eig_solver = CTMRG_EIG_TWO_STAGE;
+    opt->warm_guard = 0;
+    opt->warm_degree = 0;
+    opt->warm_tol = 0.0;
+    opt->warm_tail = CTMRG_WARM_TAIL_EXACT;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_extra_workspace_size(int q, int m, const ctmrg_options *opt, size_t *observables_bytes,
+                                        size_t *derivative_bytes)
+{
+    if (q < 2 || m < 1) return CTMRG_E_INVALID_ARG;
+    ctmrg_options o;
+    ctmrg_default_options(&o);
+    if (opt) o = *opt;
+    if (!valid_band(o.band)) return CTMRG_E_INVALID_ARG;
+    if (observables_bytes) *observables_bytes = xi_bytes(q, m, (int)std::min<long>(400, (long)m * m));
+    if (derivative_bytes) *derivative_bytes = adj_bytes(q, m, o.band);
     return CTMRG_OK;
 }
 
@@ -289,7 +401,8 @@ ctmrg_status ctmrg_workspace_size(int q, int m, const ctmrg_options *opt, size_t
     if (opt) o = *opt;
     if (!valid_band(o.band)) return CTMRG_E_INVALID_ARG;
     if (o.precision != CTMRG_FP64 && o.precision != CTMRG_FP32) return CTMRG_E_INVALID_ARG;
-    *bytes = context_bytes(q, m, o.band, o.precision);
+    if (!valid_eig_options(o)) return CTMRG_E_INVALID_ARG;
+    *bytes = context_bytes(q, m, o.band, o.precision, o);
     return CTMRG_OK;
 }
 
@@ -311,6 +424,7 @@ ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, 
     if (!valid_band(o.band) || o.boundary_spin < 0 || o.boundary_spin >= q || (o.bc != 0 && o.bc != 1))
         return CTMRG_E_INVALID_ARG;
     if (o.precision != CTMRG_FP64 && o.precision != CTMRG_FP32) return CTMRG_E_INVALID_ARG;
+    if (!valid_eig_options(o)) return CTMRG_E_INVALID_ARG;
     const long N = (long)q * m;
     if (N > 65536) return CTMRG_E_INVALID_ARG;
 
@@ -354,7 +468,19 @@ ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, 
     hipError_t e = hipMalloc((void **)&c->dBook, sizeof(Book));
     if (e == hipSuccess) e = hipMalloc((void **)&c->dPost, sizeof(PostOut));
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->hPost, sizeof(PostOut), hipHostMallocDefault);
-    if (e == hipSuccess) e = eig_alloc(c->eig, (int)N, m, o.band);
+    if (o.eig_solver == CTMRG_EIG_WARM) {
+        c->warm_p = warm_guard(o, m);
+        c->warm_k = (int)std::min<long>(N, (long)m + c->warm_p);
+        if (e == hipSuccess) e = eig_alloc(c->eig, (int)N, c->warm_k, o.band);
+        if (e == hipSuccess) e = warm_alloc(c->warm, (int)N, m, c->warm_p);
+        if (e == hipSuccess) e = hipMalloc((void **)&c->dSelK, sizeof(double) * ((size_t)c->warm_k + 8));
+        if (e == hipSuccess) e = hipMalloc((void **)&c->dOmK, sizeof(double) * ((size_t)c->warm_k + 8));
+        if (e == hipSuccess) e = hipMalloc((void **)&c->dPostK, sizeof(PostOut));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&c->hPostK, sizeof(PostOut), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void **)&c->dZ, sizeof(double) * (size_t)N * N);
+    } else if (e == hipSuccess) {
+        e = eig_alloc(c->eig, (int)N, m, o.band);
+    }
     if (e != hipSuccess) { *out = c; return hip_fail(c, e, "allocation"); }
     e = hipMemcpy(c->dV, c->V.data(), sizeof(double) * q * dim, hipMemcpyHostToDevice);
     if (e != hipSuccess) { *out = c; return hip_fail(c, e, "hipMemcpy"); }
@@ -406,6 +532,18 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *c, ctmrg_observables_t *out, double *k
 {
     if (!c || !out) return CTMRG_E_INVALID_ARG;
     if (c->steps < 1 || !c->have_U) return fail(c, CTMRG_E_STATE, "observables need at least one step");
+    if (c->last_warm) {
+        // S_E (Eq. 6) over all eigenvalues of the last step's C' (left in dC by a warm step)
+        const size_t n2 = (size_t)c->N * c->N;
+        HIPCHK(c, hipMemcpyAsync(c->dX, c->dC, sizeof(double) * n2, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, eig_values(c->eig, c->dX, c->N, c->N, c->stream));
+        HIPCHK(c, eig_post(c->eig, c->N, c->warm_k, c->opt.gap_tol, c->opt.rank_tol, c->warm.zero, c->dOmK, c->dSelK,
+                           c->dPostK, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->hPostK, c->dPostK, sizeof(PostOut), hipMemcpyDeviceToHost, c->stream));
+    }
+    if (!c->xi.V) HIPCHK(c, xi_alloc(c->xi, c->q, c->m, (int)std::min<long>(400, (long)c->m * c->m)));
+    XiResult xr;
+    HIPCHK(c, xi_solve(c->xi, c->dA, c->q, c->m, 1e-11, c->stream, &xr));
     HIPCHK(c, observables(c->dA, c->dOmega, c->dU, c->dW, c->dWH, c->dV, c->dOA, c->dX, c->dH, c->dWork,
                           c->work_elems, c->q, c->dim, c->m, c->opt.bc, c->opt.boundary_spin, c->dObs, c->stream));
     double obs[8];
@@ -415,6 +553,10 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *c, ctmrg_observables_t *out, double *k
     if (kept_spectrum)
         HIPCHK(c, hipMemcpyAsync(kept_spectrum, c->dOmega, sizeof(double) * c->m, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->last_warm) {
+        const ctmrg_status st = check_kernel_errors(c);
+        if (st != CTMRG_OK) return st;
+    }
     const double T = 1.0 / c->K;
     // the free energy is a ratio of the normalizations of two consecutive steps
     out->ln_kappa_W = c->steps >= 2 ? log(bk.nP_prev) + 0.5 * log(bk.nC / bk.nC_prev) : NAN;
@@ -422,11 +564,17 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *c, ctmrg_observables_t *out, double *k
     out->ln_kappa_ratio = log(obs[2]) + log(obs[0]) - 2.0 * log(obs[1]);
     out->E = 0.5 * obs[3] / obs[2];
     out->M = obs[5] / obs[6];
-    out->S_E = bk.S;
+    out->S_E = c->last_warm ? c->hPostK->S_E : bk.S;
     out->delta = c->delta;
     out->c_paper = (bk.S_prev != 0.0) ? fabs(1.0 - bk.S / bk.S_prev) : INFINITY;
     out->m_eff = c->m_eff;
     out->steps = c->steps;
+    out->xi_e = xr.xi;
+    out->tm_lambda1 = xr.lambda1;
+    out->tm_lambda2 = xr.lambda2;
+    out->tm_residual = xr.residual;
+    out->tm_iterations = xr.iterations;
+    out->tm_converged = xr.converged ? 1 : 0;
     return CTMRG_OK;
 }
 
@@ -541,6 +689,9 @@ ctmrg_status ctmrg_import_state(ctmrg_ctx *c, const void *host_buf, size_t bytes
     c->m_eff = h.m_eff; c->steps = h.steps; c->delta = h.delta; c->c_paper = h.c_paper;
     c->have_U = false;
     c->cext_valid = false;
+    c->warm.kcur = 0;
+    c->m_eff_prev2 = 0;
+    c->last_warm = false;
     return CTMRG_OK;
 }
 
@@ -562,6 +713,7 @@ ctmrg_status ctmrg_set_state(ctmrg_ctx *c, int d, const double *P, const double 
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->m_eff = d; c->steps = 0; c->delta = INFINITY; c->c_paper = INFINITY;
     c->have_U = false; c->cext_valid = false;
+    c->warm.kcur = 0; c->m_eff_prev2 = 0; c->last_warm = false;
     return CTMRG_OK;
 }
 
@@ -571,6 +723,7 @@ ctmrg_status ctmrg_extend(ctmrg_ctx *c)
     HIPCHK(c, extend_corner(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cext_valid = true;
+    c->last_warm = false;
     return CTMRG_OK;
 }
 
@@ -650,6 +803,8 @@ ctmrg_status ctmrg_set_profiling(ctmrg_ctx *c, int enable)
         for (int i = 0; i < MK_COUNT; ++i) HIPCHK(c, hipEventCreate(&c->ev[i]));
     }
     c->profile = enable != 0;
+    c->warm.product_ms = c->warm.product_flops = 0.0;
+    c->warm.product_launches = 0;
     for (int i = 0; i < MK_COUNT; ++i) c->stage_ms[i] = 0.0;
     c->timed_steps = 0;
     return CTMRG_OK;
@@ -660,6 +815,24 @@ ctmrg_status ctmrg_get_stage_times(ctmrg_ctx *c, double *ms, int *nsteps)
     if (!c || !ms || !nsteps) return CTMRG_E_INVALID_ARG;
     for (int i = 0; i < CTMRG_NUM_STAGES; ++i) ms[i] = c->stage_ms[i];
     *nsteps = c->timed_steps;
+    return CTMRG_OK;
+}
+
+ctmrg_status ctmrg_get_eig_stats(ctmrg_ctx *c, double *out)
+{
+    if (!c || !out) return CTMRG_E_INVALID_ARG;
+    out[0] = (double)(c->warm.steps - c->warm.fallbacks);
+    out[1] = (double)c->warm.fallbacks;
+    out[2] = (double)c->warm.passes;
+    out[3] = (double)c->warm.products;
+    out[4] = c->warm.tail_bound_max;
+    out[5] = c->warm_last_tail;
+    out[6] = (double)c->warm.last_reason;
+    out[7] = c->warm.last_rmax;
+    out[11] = c->warm_last_SE;
+    out[8] = c->warm.product_ms;
+    out[9] = c->warm.product_flops;
+    out[10] = (double)c->warm.product_launches;
     return CTMRG_OK;
 }
 

@@ -77,7 +77,7 @@ struct EigWork {
 enum MarkId {
     MK_START = 0, MK_EXT = 1, MK_WMIX1 = 2, MK_STAGE1 = 3, MK_BULGE = 4, MK_BISECT = 5, MK_POST = 6,
     MK_INVIT = 7, MK_NS = 8, MK_BT2 = 9, MK_BT1 = 10, MK_HALF = 11, MK_WMIX2 = 12, MK_PROJ = 13,
-    MK_NORM = 14, MK_VEC_START = 15, MK_COUNT = 16
+    MK_NORM = 14, MK_VEC_START = 15, MK_WARM_END = 16, MK_COUNT = 17
 };
 inline void mark(const EigWork &w, int id, hipStream_t s)
 {
@@ -95,6 +95,7 @@ struct PostOut {
     double delta;
     double lam1;
     double sum_w4_kept;
+    double tail_bound;  // warm solver: bound on the part of sum w^4 beyond its block (0: all eigenvalues known)
 };
 
 hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b);

@@ -932,6 +932,7 @@ post_eigen_kernel(const double *ev, int N, int m, double gap_tol, double rank_to
         out->delta = dl;
         out->rank = (int)rk;
         out->sum_w4_kept = kept4;
+        out->tail_bound = 0.0;
     }
 }
 

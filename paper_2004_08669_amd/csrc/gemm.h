@@ -438,8 +438,21 @@ hipError_t gemm_mfma_lower(LA la, LB lb, EpiAxpbyLower epi, int N, int K, hipStr
     return hipGetLastError();
 }
 
+// C = A B through EPI (an epilogue with kLowerTiles) on the 128 x 128 tiles of a square C
+// (M = N) on or below the diagonal; the tiles above it are not touched.
+template <class LA, class LB, class EPI>
+hipError_t gemm_mfma_lower_large(LA la, LB lb, EPI epi, int N, int K, hipStream_t s)
+{
+    static_assert(lower_tiles<EPI>::value, "lower-tile epilogue");
+    if (N <= 0) return hipSuccess;
+    const long T = ceil_div(N, 128);
+    hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EPI>), dim3((unsigned)(T * (T + 1) / 2), 1, 1),
+                       dim3(256), 0, s, la, lb, epi, N, N, K, K);
+    return hipGetLastError();
+}
+
 // Split-K GEMM: partials go to `work` (splits * M * N doubles), then reduced.
-// shape GEMM_SMALL (64 x 64 tiles) or GEMM_TALL (128 x 32 tiles, narrow outputs).
+// shape GEMM_SMALL (64 x 64 tiles), GEMM_TALL (128 x 32 tiles, narrow outputs) or GEMM_LARGE.
 template <class LA, class LB, class EPI>
 hipError_t gemm_mfma_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int splits, double *work, hipStream_t s,
                            GemmShape shape = GEMM_SMALL)
@@ -449,7 +462,11 @@ hipError_t gemm_mfma_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int spli
     int kchunk = ceil_div(ceil_div(K, splits), 16) * 16;
     splits = ceil_div(K, kchunk);
     EpiPartial part{work, M, N};
-    if (shape == GEMM_TALL)
+    if (shape == GEMM_LARGE)
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EpiPartial>),
+                           dim3(ceil_div(M, 128), ceil_div(N, 128), splits), dim3(256), 0, s, la, lb, part, M, N, K,
+                           kchunk);
+    else if (shape == GEMM_TALL)
         hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EpiPartial>),
                            dim3(ceil_div(M, 128), ceil_div(N, 32), splits), dim3(256), 0, s, la, lb, part, M, N, K,
                            kchunk);

@@ -28,7 +28,9 @@ STATUS = {
 BUF = {"P": 0, "omega": 1, "spectrum": 2, "U": 3, "cext": 4, "W": 5}
 STAGES = ["extension", "wmix_C", "dense_to_band", "band_to_tridiag", "bisection", "select_cut_entropy",
           "inverse_iteration", "orthonormalize", "backtransform_band", "backtransform_dense", "halfrow",
-          "wmix_Z", "projection", "normalize", "step"]
+          "wmix_Z", "projection", "normalize", "step", "warm_topk"]
+EIG_SOLVERS = {"two_stage": 0, "warm": 1}
+WARM_TAILS = {"exact": 0, "bound": 1}
 
 
 class CTMRGError(RuntimeError):
@@ -46,6 +48,11 @@ class Options(ctypes.Structure):
         ("gap_tol", ctypes.c_double),
         ("rank_tol", ctypes.c_double),
         ("hip_stream", ctypes.c_void_p),
+        ("eig_solver", ctypes.c_int),
+        ("warm_guard", ctypes.c_int),
+        ("warm_degree", ctypes.c_int),
+        ("warm_tol", ctypes.c_double),
+        ("warm_tail", ctypes.c_int),
     ]
 
 
@@ -61,6 +68,12 @@ class Observables(ctypes.Structure):
         ("c_paper", ctypes.c_double),
         ("m_eff", ctypes.c_int),
         ("steps", ctypes.c_int),
+        ("xi_e", ctypes.c_double),
+        ("tm_lambda1", ctypes.c_double),
+        ("tm_lambda2", ctypes.c_double),
+        ("tm_residual", ctypes.c_double),
+        ("tm_iterations", ctypes.c_int),
+        ("tm_converged", ctypes.c_int),
     ]
 
 
@@ -110,12 +123,15 @@ def load():
         "ctmrg_set_state": ([_vp, ctypes.c_int, _dp, _dp], ctypes.c_int),
         "ctmrg_workspace_size": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options),
                                   ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ctmrg_extra_workspace_size": ([ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options),
+                                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ctmrg_get_buffer": ([_vp, ctypes.c_int, _dp, ctypes.c_size_t], ctypes.c_int),
         "ctmrg_extend": ([_vp], ctypes.c_int),
         "ctmrg_eigh_topk": ([ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp], ctypes.c_int),
         "ctmrg_eigh_topk_noalloc": ([ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp], ctypes.c_int),
         "ctmrg_set_profiling": ([_vp, ctypes.c_int], ctypes.c_int),
         "ctmrg_get_stage_times": ([_vp, _dp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "ctmrg_get_eig_stats": ([_vp, _dp], ctypes.c_int),
         "ctmrg_last_error": ([_vp], ctypes.c_char_p),
         "ctmrg_destroy": ([_vp], None),
     }
@@ -151,6 +167,17 @@ def workspace_size(q: int, m: int, band: int = 16) -> int:
     return int(n.value)
 
 
+def extra_workspace_size(q: int, m: int, band: int = 16):
+    """Device bytes allocated on first use: (by ctmrg_observables, by the fixed-point derivative)."""
+    o = default_options()
+    o.band = band
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    st = load().ctmrg_extra_workspace_size(q, m, ctypes.byref(o), ctypes.byref(a), ctypes.byref(b))
+    if st != CTMRG_OK:
+        raise CTMRGError(st)
+    return int(a.value), int(b.value)
+
+
 def eigh_topk(A: np.ndarray, k: int, band: int = 0):
     """All eigenvalues (ascending) and the k eigenpairs of largest |lambda| of a symmetric matrix."""
     A = _f64(A)
@@ -181,7 +208,9 @@ class CTMRG:
     """A CTMRG context on the current GPU (see include/ctmrg.h)."""
 
     def __init__(self, V, K: float, m: int, bc: str = "fixed", boundary_spin: int = 0, band: int = 16,
-                 gap_tol: float | None = None, rank_tol: float = 1e-13, precision: str = "fp64", stream=None):
+                 gap_tol: float | None = None, rank_tol: float = 1e-13, precision: str = "fp64", stream=None,
+                 eig: str = "two_stage", warm_guard: int = 0, warm_degree: int = 0, warm_tol: float = 0.0,
+                 warm_tail: str = "exact"):
         lib = load()
         self._lib = lib
         self.V = _f64(V)
@@ -197,6 +226,11 @@ class CTMRG:
         o.rank_tol = rank_tol
         o.precision = {"fp64": 0, "fp32": 1}[precision]
         o.hip_stream = stream
+        o.eig_solver = EIG_SOLVERS[eig]
+        o.warm_guard = warm_guard
+        o.warm_degree = warm_degree
+        o.warm_tol = warm_tol
+        o.warm_tail = WARM_TAILS[warm_tail]
         h = _vp()
         st = lib.ctmrg_init(self.q, self.dim, _p(self.V), float(K), self.m, ctypes.byref(o), ctypes.byref(h))
         self._h = h
@@ -303,6 +337,15 @@ class CTMRG:
         n = ctypes.c_int(0)
         self._check(self._lib.ctmrg_get_stage_times(self._h, _p(ms), ctypes.byref(n)))
         return dict(zip(STAGES, ms.tolist())), n.value
+
+    def eig_stats(self) -> dict:
+        """Counters of the warm eigensolver (see ctmrg_get_eig_stats)."""
+        out = np.zeros(12)
+        self._check(self._lib.ctmrg_get_eig_stats(self._h, _p(out)))
+        return {"warm_steps": int(out[0]), "fallback_steps": int(out[1]), "passes": int(out[2]),
+                "products": int(out[3]), "tail_bound_max": float(out[4]), "tail_bound_last": float(out[5]),
+                "last_reason": int(out[6]), "last_residual": float(out[7]), "product_ms": float(out[8]),
+                "product_flops": float(out[9]), "product_launches": int(out[10]), "last_step_S_E": float(out[11])}
 
     def P_slices(self) -> np.ndarray:
         """The current P as q slices P_s (m x m)."""

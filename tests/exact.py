@@ -215,3 +215,33 @@ def _distinct_partitions(n: int) -> int:
         for t in range(n, part - 1, -1):
             p[t] += p[t - part]
     return p[n]
+
+
+def row_transfer_bruteforce(V, K, s0, n):
+    """The row-to-row transfer matrix of a straight row of n vertices with both outer
+    horizontal spins fixed to s0, by direct enumeration of the row from Eqs. 1-2.
+
+    Vertex i of the row has its horizontal spins h_{i-1} (left) and h_i (right) on
+    opposite corners and its legs l_i (lower) and u_i (upper) on the other two; around
+    the vertex the corners run left, lower, right, upper, and the vertex weight is
+    exp(K (v_left.v_lower + v_lower.v_right + v_right.v_upper + v_upper.v_left)).
+    T[(u_1..u_n), (l_1..l_n)] = sum over h_1..h_{n-1} of the product of the n weights
+    (h_0 = h_n = s0), the legs in row order with u_1 / l_1 most significant."""
+    V = np.asarray(V, dtype=np.float64)
+    q = len(V)
+    G = V @ V.T
+    w = np.empty((q, q, q, q))  # w[left, lower, upper, right]
+    for a in range(q):
+        for b in range(q):
+            for c in range(q):
+                for d in range(q):
+                    w[a, b, c, d] = math.exp(K * (G[a, b] + G[b, d] + G[d, c] + G[c, a]))
+    # M[h][U, L]: the first i vertices with their right spin h, legs U (upper) and L (lower)
+    M = np.zeros((q, 1, 1))
+    M[s0, 0, 0] = 1.0
+    for _ in range(n):
+        R = M.shape[1]
+        # new legs are the least significant: index (U, u) and (L, l)
+        Mn = np.einsum("hUL,hluk->kUuLl", M, w)
+        M = Mn.reshape(q, R * q, R * q)
+    return M[s0]

@@ -14,8 +14,9 @@ seeded inputs of ctmrg_inputs.py.  Usage (from the repository root):
   python tests/golden/make_golden.py fixedpoint --m 64 --T 0.40
       The fixed-boundary run from the initial state of Algorithm 3 until the kept spectrum
       changes by less than 1e-12 (or 3000 steps), with numpy's LAPACK eigensolver as the
-      diagonalization step.  Stores f, E, M, S_E, m_eff, the kept spectrum and the number of
-      steps.  --eig jacobi uses the oracle's own solver (small m).
+      diagonalization step.  Stores f, E, M, S_E, m_eff, the kept spectrum, the number of
+      steps, and the effective correlation length xi_e with |lambda_2 / lambda_1| of the
+      row-to-row transfer matrix (Sec. II).  --eig jacobi uses the oracle's own solver (small m).
 
   python tests/golden/make_golden.py derivative --m 12 --T 0.40
       References of the fixed-point derivative: F = beta f, the impurity energy E and the
@@ -93,10 +94,12 @@ def fixedpoint(args):
             converged = True
             break
     obs = o.observables()
+    # effective correlation length of the fixed point (gauge invariant: the spectrum of T)
+    lam_t, xi = O.correlation_length(o.P, "dense" if o.P.shape[1] <= 40 else "arpack")
     out = {"q": 20, "m": args.m, "T": args.T, "tol": args.tol, "tau": args.tau, "converged": converged, "steps": o.k,
            "delta": o.delta, "f": obs["f"], "E": obs["E"], "M": obs["M"], "S_E": obs["S_E"],
            "m_eff": obs["m_eff"], "ln_kappa_ratio": obs["ln_kappa_ratio"], "omega": o.omega,
-           "lam": o.last.lam}
+           "lam": o.last.lam, "xi_e": xi, "tm_ratio": abs(lam_t[1] / lam_t[0])}
     tag = "" if args.tau == 1e-10 else f"_tau{args.tau:.0e}"
     name = f"fixedpoint_q20_m{args.m}_T{args.T:.2f}{tag}.npz"
     np.savez(os.path.join(HERE, name), **{k: np.asarray(v) for k, v in out.items()})

@@ -285,6 +285,9 @@ def test_dodecahedron_fixed_boundary_m16(T, tol):
     assert abs(og["f"] - float(ref["f"])) <= 1e-10 * abs(float(ref["f"]))
     assert abs(og["E"] - float(ref["E"])) <= 1e-8
     assert abs(og["M"] - float(ref["M"])) <= 1e-8
+    # xi_e (Sec. II) of the two fixed points: gauge invariant
+    assert abs(og["xi_e"] - float(ref["xi_e"])) <= 1e-8 * float(ref["xi_e"])
+    assert abs(abs(og["tm_lambda2"] / og["tm_lambda1"]) - float(ref["tm_ratio"])) <= 1e-9
 
 
 def test_checkpoint_resume_bitwise():

@@ -354,3 +354,83 @@ def test_fix_signs_hand_values():
     assert np.array_equal(F[:, 0], [-0.6, 0.8, 0.0])
     assert np.array_equal(F[:, 1], [0.8, -0.6, 0.0])
     assert np.array_equal(F[:, 2], [0.5, -0.5, 0.0])
+
+
+# --------------------------------------------------------------------------- xi_e (Sec. II, last paragraph)
+
+def _untruncated(V, K, steps):
+    """The oracle's state after `steps` steps from the fixed boundary with m large enough that
+    nothing is cut (m = q^steps)."""
+    q = len(V)
+    o = O.OracleCTMRG(V, K, q ** steps, eig="lapack")
+    for _ in range(steps):
+        o.step()
+    assert o.P.shape[1] == q ** steps
+    return o
+
+
+@pytest.mark.parametrize("name,T,steps", [("ising", 2.5, 1), ("ising", 2.0, 2), ("ising", 3.0, 3),
+                                          ("ising", 1.7, 4), ("tetrahedron", 1.0, 2),
+                                          ("dodecahedron", 0.44, 1)])
+def test_row_transfer_matrix_brute_force(name, T, steps):
+    """After k untruncated steps, sum_s P_s (x) P_s -- built from the rotated, normalized
+    half-rows of the iteration -- has the spectrum (up to one scale) of the straight row of
+    2k vertices with fixed ends, enumerated directly from the weights."""
+    V = I.vertices(name)
+    K = 1.0 / T
+    o = _untruncated(V, K, steps)
+    Tg = O.row_transfer_matrix(o.P)
+    Tb = E.row_transfer_bruteforce(V, K, 0, 2 * steps)
+    assert Tg.shape == Tb.shape
+    a = np.linalg.eigvalsh(Tg)
+    b = np.linalg.eigvalsh(Tb)
+    a = a[np.argsort(-np.abs(a), kind="stable")]
+    b = b[np.argsort(-np.abs(b), kind="stable")]
+    a, b = a / a[0], b / b[0]
+    assert np.abs(np.sort(a) - np.sort(b)).max() <= 1e-12
+    # the operator form and the explicit matrix agree; ARPACK finds the same leading pair
+    X = np.random.default_rng(7).standard_normal((o.P.shape[1],) * 2)
+    assert np.allclose(O.row_transfer_apply(o.P, X).ravel(), Tg @ X.ravel(), rtol=0, atol=1e-13 * np.abs(Tg).max() * X.size)
+    if Tg.shape[0] >= 16:
+        lam_d, xi_d = O.correlation_length(o.P, "dense")
+        lam_a, xi_a = O.correlation_length(o.P, "arpack")
+        assert np.allclose(lam_a, lam_d, rtol=1e-11, atol=0)
+
+
+def test_planted_row_transfer_mistakes():
+    """A row made of two unrelated half-rows (no shared end spin), or of the boundary spin's
+    half-row alone, fails the brute force."""
+    V = I.ising()
+    K = 1.0 / 2.0
+    o = _untruncated(V, K, 3)
+    P = o.P
+    b = np.linalg.eigvalsh(E.row_transfer_bruteforce(V, K, 0, 6))
+    b = np.sort(b / b[np.argmax(np.abs(b))])
+    for bad in (sum(np.kron(P[s], P[t]) for s in range(2) for t in range(2)), np.kron(P[0], P[0])):
+        a = np.linalg.eigvalsh(bad)
+        a = np.sort(a / a[np.argmax(np.abs(a))])
+        assert np.abs(a - b).max() > 1e-3
+
+
+@pytest.mark.parametrize("T,ordered", [(4.0, False), (3.0, False), (1.8, True)])
+def test_ising_correlation_length_closed_form(T, ordered):
+    """q = 2: |lambda_2 / lambda_1| of the row-to-row transfer matrix tends, as m grows, to
+    the exact value of the infinite lattice.  A row of vertices runs along a diagonal of the
+    spin lattice, so the ratio is sinh^2(2K) above T_c (one free fermion at the bottom of its
+    band) and sinh^-4(2K) below (two; the fixed boundary selects one ordered state).  The
+    finite-m band of the transfer matrix starts above the exact edge, so the ratio approaches
+    from below."""
+    K = 1.0 / T
+    exact = math.sinh(2 * K) ** (-4) if ordered else math.sinh(2 * K) ** 2
+    prev = 0.0
+    errs = []
+    for m in (8, 16, 32):
+        o, _ = O.run_fixed_point(I.ising(), K, m, tol=1e-13, max_steps=4000, eig="lapack")
+        lam, xi = O.correlation_length(o.P)
+        r = abs(lam[1] / lam[0])
+        assert abs(xi - 1.0 / math.log(1.0 / r)) <= 1e-12 * xi
+        errs.append(r / exact - 1.0)
+        assert prev < r < exact
+        prev = r
+    assert abs(errs[-1]) <= (0.04 if ordered else 0.01)
+    assert abs(errs[-1]) < abs(errs[0]) / 2.5
