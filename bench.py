@@ -2,23 +2,27 @@
 """Throughput of the CTMRG step (Sec. 3, Algorithm 3) for the q=20 dodecahedron model on one MI355X.
 
 A step is one full pass of the method on the GPU: extension products and W-mix
-(the extended corner C', (q m) x (q m)), the FP64 eigensolver (all eigenvalues,
-the m leading eigenvectors), the multiplet-preserving cut, the half-row
-products, W-mix and projection, and the normalizations.  Every step works on
-the full padded size N = q m, so the timed steps after the warmup all do the
-full-size work.  Inputs are the dodecahedron spin vectors and K = 1/T; the
-state is whatever the iteration produces from the fixed boundary (synthetic,
-deterministic).
+(the extended corner C', (q m) x (q m)), the FP64 diagonalization (the m leading
+eigenpairs and the normalization n_C over the whole spectrum), the
+multiplet-preserving cut, the half-row products, W-mix and projection, and the
+normalizations.  Every step works on the full padded size N = q m.  Inputs are
+the dodecahedron spin vectors and K = 1/T; the state is whatever the iteration
+produces from the fixed boundary (synthetic, deterministic).
 
-By default two paths are timed one after the other from the same initial
-state: the mixed path (FP32 contractions on the matrix cores, FP64 eigensolver
-and state), whose steps/s is the headline `value`, and the FP64 path
-(`fp64`, `mixed_over_fp64`); `mixed_vs_fp64_after_run` gives how far their
-observables are apart after the same steps.  `roofline` is the dominant kernel
-(the wavefront bulge-chasing kernel, whose time per launch is its stage's
-HIP-event time over its launches), `contraction_roofline` the largest
-contraction kernel, and `cpu_baseline` the oracle's step time on the host.
-Prints one JSON line.
+Four paths are timed one after the other from the same initial state: FP32 or
+FP64 contractions (the mixed path keeps the eigensolver, the state and every
+normalization in FP64), each with the two-stage eigensolver (all eigenvalues
+every step) and with the warm-started one (the leading m + p eigenpairs from the
+previous step's, n_C from ||C'^2||_F where the bounded tail could matter).  The
+headline `value` is the mixed path with the warm-started eigensolver;
+`mixed_over_fp64` divides it by the plain FP64 path (two-stage), and
+`mixed_vs_fp64_after_run` gives how far their observables are apart after the
+same steps.  `paths` holds all four, `roofline` the dominant kernel of the
+headline path (the products C' V, timed by HIP events around each launch),
+`two_stage_roofline` the dominant kernel of the two-stage path (the wavefront
+bulge chasing), `contraction_roofline` the largest contraction kernel,
+`time_to_fixed_point` whole runs at m = 64 against the oracle's fixed point, and
+`cpu_baseline` the oracle's step time on the host.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -175,6 +179,7 @@ def run_path(V, K, m, band, precision, gap_tol, warmup, steps, eig="two_stage"):
             "fallback_rate": fb / max(1, ws + fb),
             "passes_per_step": (after["passes"] - before["passes"]) / steps,
             "products_per_step": (after["products"] - before["products"]) / steps,
+            "exact_tail_steps": after["exact_tails"] - before["exact_tails"],
             "tail_bound_last": after["tail_bound_last"],
             "last_residual": after["last_residual"],
             "product_ms": after["product_ms"],
@@ -292,7 +297,7 @@ def main():
     ap.add_argument("--gap-tol", type=float, default=1e-6,
                     help="multiplet gap of the cut, the same on both paths")
     ap.add_argument("--eig", choices=["both", "two_stage", "warm"], default="both",
-                    help="both: the headline with the two-stage eigensolver, and the warm-started one beside it")
+                    help="both: the two-stage and the warm-started eigensolver (the headline is the warm one)")
     ap.add_argument("--no-fixed-point", action="store_true", help="skip the time-to-fixed-point runs (m=64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=128)
@@ -312,42 +317,52 @@ def main():
     V = I.dodecahedron()
     q, m, K = len(V), args.m, 1.0 / args.T
     print(f"# bench: q={q} m={m} T={args.T} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
-    runs, wruns = {}, {}
     order = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
+    ts, wm = {}, {}
     if args.eig != "warm":
         for prec in order:
-            runs[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps)
+            ts[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps)
     if args.eig != "two_stage":
         for prec in order:
-            wruns[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps, eig="warm")
-    if not runs:
-        runs = wruns
+            wm[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps, eig="warm")
+    # the headline: the mixed path (the first precision) with the warm-started eigensolver when it ran
+    head_eig = "warm" if wm else "two_stage"
     head_prec = order[0]
-    head = runs[head_prec]
+    head = (wm if wm else ts)[head_prec]
     stage_ms = head["stage_ms"]
     obs = head["obs"]
 
     flops = stage_flops(q, m)
-    # Dominant kernel of the step: the wavefront bulge-chasing kernel (band -> tridiagonal).
-    # Its stage is timed with HIP events on the stream it is launched on; the stage holds
-    # the launches plus one band extraction kernel of a few microseconds.
-    N = q * m
-    launches, bulge_bytes = bulge_chasing_bytes(N, args.band)
-    avg_launch_s = stage_ms["band_to_tridiag"] * 1e-3 / launches
-    per_launch = bulge_bytes / launches
-    achieved = per_launch / avg_launch_s / 1e9
-    roofline = {
-        "kernel": f"bulge_front_kernel<{args.band}>",
-        "bound": "hbm",
-        "achieved": achieved,
-        "peak": PEAK_HBM_GBS,
-        "unit": "GB/s",
-        "frac": achieved / PEAK_HBM_GBS,
-        "traffic": None,
-        "algorithmic_bytes_per_launch": per_launch,
-        "launches_per_step": launches,
-        "avg_launch_us": avg_launch_s * 1e6,
-    }
+
+    def product_roofline(w):
+        """The warm solver's products C' V (split-K gemm_mfma_kernel<128, 128> and its partial
+        sum), each bracketed by HIP events on the stream that runs it."""
+        if w["product_launches"] <= 0:
+            return None
+        avg_s = w["product_ms"] * 1e-3 / w["product_launches"]
+        fl = w["product_flops"] / w["product_launches"]
+        ach = fl / avg_s / 1e12
+        return {"kernel": "gemm_mfma_kernel<128, 128, 16, 2, 2, A_RM<double>, B_RM<double>, EpiPartial> + partial sum "
+                          "(products C' V of the warm solver)",
+                "bound": "mfma", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64_TFLOPS, "traffic": None, "algorithmic_flops_per_launch": fl,
+                "avg_launch_ms": avg_s * 1e3, "launches": w["product_launches"]}
+
+    def bulge_roofline(st):
+        """The wavefront bulge-chasing kernel (band -> tridiagonal) of the two-stage solver: its
+        stage's HIP-event time (the launches plus one band extraction of a few microseconds) over
+        its launches."""
+        N = q * m
+        launches, bulge_bytes = bulge_chasing_bytes(N, args.band)
+        avg_launch_s = st["band_to_tridiag"] * 1e-3 / launches
+        per_launch = bulge_bytes / launches
+        achieved = per_launch / avg_launch_s / 1e9
+        return {"kernel": f"bulge_front_kernel<{args.band}>", "bound": "hbm", "achieved": achieved,
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "algorithmic_bytes_per_launch": per_launch, "launches_per_step": launches,
+                "avg_launch_us": avg_launch_s * 1e6}
+
+    roofline = product_roofline(head["warm"]) if head_eig == "warm" else bulge_roofline(stage_ms)
     # The largest contraction kernel, against the matrix-core peak of its precision.
     kernel_stages = ["extension", "wmix_C", "halfrow", "wmix_Z", "projection"]
     dom = max(kernel_stages, key=lambda k: stage_ms[k])
@@ -362,11 +377,12 @@ def main():
         "frac": c_ach / c_peak,
         "algorithmic_flops_per_launch": flops[dom],
         "avg_launch_ms": stage_ms[dom],
+        "all": {k: round(flops[k] / (stage_ms[k] * 1e-3) / 1e12 / c_peak, 4) for k in kernel_stages
+                if stage_ms[k] > 0},
     }
     desc = {"fp32": "mixed (FP32 contractions, FP64 eigensolver and state)", "fp64": "FP64"}
-    head_eig = "warm" if args.eig == "warm" else "two_stage"
-    edesc = {"two_stage": "two-stage eigensolver (all eigenvalues)",
-             "warm": "warm-started top-m eigensolver (bounded spectral tail)"}
+    edesc = {"two_stage": "two-stage eigensolver (all eigenvalues every step)",
+             "warm": "warm-started top-m eigensolver (two-stage solver in the first steps and as fallback)"}
     out = {
         "metric": "CTMRG steps/s at q=20 m=512 (mixed vs FP64, same error); % MFMA peak",
         "value": head["steps_per_s"],
@@ -389,64 +405,47 @@ def main():
         "roofline": roofline,
         "contraction_roofline": contraction_roofline,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "state": {"m_eff": obs["m_eff"], "S_E": obs["S_E"], "delta": obs["delta"]},
+        "state": {"m_eff": obs["m_eff"], "S_E": obs["S_E"], "xi_e": obs["xi_e"], "delta": obs["delta"]},
     }
-    if "fp64" in runs and head_prec != "fp64":
-        r64 = runs["fp64"]
-        o64 = r64["obs"]
-        out["fp64"] = {
-            "steps_per_s": r64["steps_per_s"],
-            "ms_per_step": r64["ms_per_step"],
-            "stages_ms": {k: round(v, 4) for k, v in r64["stage_ms"].items()},
-        }
-        out["mixed_over_fp64"] = head["steps_per_s"] / r64["steps_per_s"]
-        # both paths ran the same steps from the same initial state
-        out["mixed_vs_fp64_after_run"] = {
-            "f_rel": abs(obs["f"] - o64["f"]) / abs(o64["f"]),
-            "E_abs": abs(obs["E"] - o64["E"]),
-            "M_abs": abs(obs["M"] - o64["M"]),
-            "S_E_abs": abs(obs["S_E"] - o64["S_E"]),
-            "m_eff": [obs["m_eff"], o64["m_eff"]],
-        }
-    if wruns and runs is not wruns:
-        f1 = {}
-        for prec, r in wruns.items():
-            w = r["warm"]
+
+    def after_run(a, b):
+        return {"f_rel": abs(a["f"] - b["f"]) / abs(b["f"]), "E_abs": abs(a["E"] - b["E"]),
+                "M_abs": abs(a["M"] - b["M"]), "S_E_abs": abs(a["S_E"] - b["S_E"]), "m_eff": [a["m_eff"], b["m_eff"]]}
+
+    paths = {}
+    for solver, rr in (("two_stage", ts), ("warm", wm)):
+        for prec, r in rr.items():
             ent = {"steps_per_s": r["steps_per_s"], "ms_per_step": r["ms_per_step"],
-                   "speedup_vs_two_stage": r["steps_per_s"] / runs[prec]["steps_per_s"] if prec in runs else None}
-            ent.update({k: w[k] for k in ("fallback_steps", "warm_steps", "fallback_rate", "passes_per_step",
-                                          "products_per_step", "tail_bound_last", "last_residual")})
-            ent["stages_ms"] = {k: round(v, 4) for k, v in r["stage_ms"].items() if v > 0}
-            if prec in runs:
-                ow, ot = r["obs"], runs[prec]["obs"]
-                ent["vs_two_stage_after_run"] = {
-                    "f_rel": abs(ow["f"] - ot["f"]) / abs(ot["f"]), "E_abs": abs(ow["E"] - ot["E"]),
-                    "M_abs": abs(ow["M"] - ot["M"]), "S_E_abs": abs(ow["S_E"] - ot["S_E"]),
-                    "m_eff": [ow["m_eff"], ot["m_eff"]]}
-            f1[prec] = ent
-        if "fp32" in wruns and "fp64" in wruns:
-            f1["mixed_over_fp64"] = wruns["fp32"]["steps_per_s"] / wruns["fp64"]["steps_per_s"]
-            if "fp64" in runs:
-                f1["mixed_warm_over_fp64_two_stage"] = wruns["fp32"]["steps_per_s"] / runs["fp64"]["steps_per_s"]
-        # the products C' V of the warm solver (split-K MFMA GEMM and its partial-sum kernel),
-        # each bracketed by HIP events on the stream that runs it
-        w = wruns[head_prec]["warm"]
-        if w["product_launches"] > 0:
-            avg_s = w["product_ms"] * 1e-3 / w["product_launches"]
-            fl = w["product_flops"] / w["product_launches"]
-            ach = fl / avg_s / 1e12
-            f1["product_roofline"] = {
-                "kernel": "C' V products (gemm_mfma split-K + partial sum)", "bound": "mfma",
-                "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
-                "algorithmic_flops_per_launch": fl, "avg_launch_ms": avg_s * 1e3,
-                "launches": w["product_launches"]}
-        out["f1_warm_eigensolver"] = f1
+                   "stages_ms": {k: round(v, 4) for k, v in r["stage_ms"].items() if v > 0}}
+            if "warm" in r:
+                ent.update({k: r["warm"][k] for k in ("fallback_steps", "warm_steps", "fallback_rate",
+                                                      "passes_per_step", "products_per_step", "exact_tail_steps",
+                                                      "tail_bound_last", "last_residual")})
+                if prec in ts:
+                    ent["speedup_vs_two_stage"] = r["steps_per_s"] / ts[prec]["steps_per_s"]
+                    ent["vs_two_stage_after_run"] = after_run(r["obs"], ts[prec]["obs"])
+            paths[f"{prec}_{solver}"] = ent
+    out["paths"] = paths
+    if "fp64" in ts and head_prec != "fp64":
+        # the plain FP64 path: FP64 contractions and the two-stage eigensolver; all paths ran the same
+        # steps from the same initial state
+        out["mixed_over_fp64"] = head["steps_per_s"] / ts["fp64"]["steps_per_s"]
+        out["mixed_over_fp64_basis"] = (f"the headline path ({desc[head_prec]}, {head_eig}) over the plain FP64 "
+                                        f"path (two-stage eigensolver)")
+        out["mixed_vs_fp64_after_run"] = after_run(obs, ts["fp64"]["obs"])
+        ratios = {}
+        for solver, rr in (("two_stage", ts), ("warm", wm)):
+            if "fp32" in rr and "fp64" in rr:
+                ratios[f"mixed_over_fp64_both_{solver}"] = rr["fp32"]["steps_per_s"] / rr["fp64"]["steps_per_s"]
+        out["ratios"] = ratios
+    if ts:
+        out["two_stage_roofline"] = bulge_roofline(ts[order[0]]["stage_ms"])
     if not args.no_fixed_point:
         out["time_to_fixed_point"] = time_to_fixed_point(V, 0.40, 64, 1e-12, 3000, args.band)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V, K, args.cpu_sample_m, m)
     if args.compare_eigh:
-        r64 = runs.get("fp64", head)
+        r64 = ts.get("fp64", head)
         cmp = eigh_comparison(V, K, m, args.band, args.warmup)
         cmp["own_eigensolver_ms"] = sum(r64["stage_ms"][k] for k in EIGEN_STAGES)
         cmp["own_eigensolver_computes"] = "all eigenvalues and the m leading eigenvectors"

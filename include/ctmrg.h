@@ -91,8 +91,11 @@ typedef enum { CTMRG_EIG_TWO_STAGE = 0, CTMRG_EIG_WARM = 1 } ctmrg_eig_solver;
  *     tail's share of S_E lies within a bound (ctmrg_get_eig_stats).
  *   CTMRG_WARM_TAIL_BOUND: no product; sum lambda^2 beyond the block is
  *     ||C'||_F^2 - sum theta^2, each |lambda| is at most |theta_k|, and the
- *     midpoint of the resulting interval for sum lambda^4 is taken. */
-typedef enum { CTMRG_WARM_TAIL_EXACT = 0, CTMRG_WARM_TAIL_BOUND = 1 } ctmrg_warm_tail;
+ *     midpoint of the resulting interval for sum lambda^4 is taken.
+ *   CTMRG_WARM_TAIL_AUTO (default): the product only in steps where the bound
+ *     on the tail's share of sum w^4 exceeds the contractions' own precision
+ *     (1e-14 with FP64 contractions, 1e-9 with FP32), the midpoint otherwise. */
+typedef enum { CTMRG_WARM_TAIL_EXACT = 0, CTMRG_WARM_TAIL_BOUND = 1, CTMRG_WARM_TAIL_AUTO = 2 } ctmrg_warm_tail;
 
 typedef struct {
     int precision;        /* ctmrg_precision of the contractions; the eigensolver is always FP64 */
@@ -107,7 +110,7 @@ typedef struct {
     int warm_degree;      /* CTMRG_EIG_WARM: largest Chebyshev degree per pass, 1..8 (0 = 8)   */
     double warm_tol;      /* CTMRG_EIG_WARM: kept residuals below warm_tol |lambda_1|
                              (0 = 1e-12 for FP64 contractions, 1e-9 for FP32)                  */
-    int warm_tail;        /* CTMRG_EIG_WARM: ctmrg_warm_tail (default CTMRG_WARM_TAIL_EXACT)   */
+    int warm_tail;        /* CTMRG_EIG_WARM: ctmrg_warm_tail (default CTMRG_WARM_TAIL_AUTO)    */
 } ctmrg_options;
 
 typedef struct {
@@ -310,8 +313,9 @@ ctmrg_status ctmrg_get_stage_times(ctmrg_ctx *ctx, double *ms, int *nsteps);
  * milliseconds of the solver's products C' V (HIP events around each launch),
  * out[9] their algorithmic flops (2 (q m)^2 columns each) and out[10] counts them.
  * out[11] is S_E as the last warm-solved step gave it (Ritz values plus the
- * bounded tail; ctmrg_observables computes it over all eigenvalues). */
-ctmrg_status ctmrg_get_eig_stats(ctmrg_ctx *ctx, double out[12]);
+ * bounded tail; ctmrg_observables computes it over all eigenvalues), out[12]
+ * the warm steps that took sum lambda^4 from the product C' C'. */
+ctmrg_status ctmrg_get_eig_stats(ctmrg_ctx *ctx, double out[13]);
 
 const char *ctmrg_last_error(const ctmrg_ctx *ctx);
 void ctmrg_destroy(ctmrg_ctx *ctx);

@@ -430,7 +430,7 @@ int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s,
         ADJ_CK(align_to(w, w.Ucur, d, w.sel, in.gap_tol, s));
         ADJ_CK(halfrow_products(w.A, w.Ucur, w.Y, q, d, s));
         ADJ_CK(weight_mix(in.W, w.Y, w.Z, q, d, s));
-        ADJ_CK(projection(w.Ucur, w.Z, w.Pt, q, d, s));
+        ADJ_CK(projection(w.Ucur, w.Z, w.Pt, q, d, nullptr, 0, s));
         ADJ_CK(reduce_dot(w.Pt, w.Pt, (long)d * n, w.part, w.scal + S_NORM, OP_SQRT, 1.0, s));
         hipLaunchKernelGGL(div_by_kernel, dim3(grid_for((long)d * n)), dim3(256), 0, s, w.Pt, w.dAn, (long)d * n,
                            w.scal + S_NORM);
@@ -484,7 +484,7 @@ int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s,
     // P~*, its norm s*, and the K-derivative parts of C' and Z (dW/dK = -WH)
     ADJ_CK(halfrow_products(w.A, w.Ucur, w.Y, q, d, s));
     ADJ_CK(weight_mix(in.W, w.Y, w.Z, q, d, s));
-    ADJ_CK(projection(w.Ucur, w.Z, w.Pt, q, d, s));
+    ADJ_CK(projection(w.Ucur, w.Z, w.Pt, q, d, nullptr, 0, s));
     ADJ_CK(reduce_dot(w.Pt, w.Pt, (long)d * n, w.part, w.scal + S_NORM, OP_SQRT, 1.0, s));
     ADJ_CK(gemm_mfma(GEMM_MIX, A_T{in.WH, q2}, B_Mix{w.X, q, d, n}, EpiMix_<double, true>{w.Cb, q, d, n, -1.0}, q2,
                      d * d, q2, s));

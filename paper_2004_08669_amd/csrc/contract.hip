@@ -259,10 +259,22 @@ hipError_t halfrow_products(const double *A, const double *U, double *Y, int q, 
     return gemm_mfma(GEMM_LARGE, A_T{A, N}, B_Ublk{U, m}, EpiStore{Y, N, 1.0}, (int)N, (int)N, m, s);
 }
 
-hipError_t projection(const double *U, const double *Z, double *Pt, int q, int m, hipStream_t s)
+// Splits of the projection's inner dimension (K = q m, output m x q m): enough workgroups for
+// the device, partials within the work buffer (none without one).
+static int projection_splits(int m, long N, size_t work_elems)
+{
+    const long tiles = (long)ceil_div(m, 128) * ceil_div(N, 128);
+    int sp = 1;
+    while (tiles * sp < 768 && sp < 8 && (size_t)(sp + 1) * m * N <= work_elems && N / (sp + 1) >= 1024) ++sp;
+    return sp;
+}
+
+hipError_t projection(const double *U, const double *Z, double *Pt, int q, int m, double *work, size_t work_elems,
+                      hipStream_t s)
 {
     const long N = (long)q * m;
-    return gemm_mfma(GEMM_LARGE, A_T{U, m}, B_RM{Z, N}, EpiStore{Pt, N, 1.0}, m, (int)N, (int)N, s);
+    const int sp = projection_splits(m, N, work ? work_elems : 0);
+    return gemm_mfma_splitk(A_T{U, m}, B_RM{Z, N}, EpiStore{Pt, N, 1.0}, m, (int)N, (int)N, sp, work, s, GEMM_LARGE);
 }
 
 // ---- mixed precision: FP32 operands on the FP32 matrix cores, FP32 accumulation.
@@ -319,10 +331,13 @@ hipError_t weight_mix_f32(const float *W32, const float *Y32, float *Z32, int q,
                      q2, s);
 }
 
-hipError_t projection_f32(const float *U32, const float *Z32, double *Pt, int q, int m, double wscale, hipStream_t s)
+hipError_t projection_f32(const float *U32, const float *Z32, double *Pt, int q, int m, double wscale, double *work,
+                          size_t work_elems, hipStream_t s)
 {
     const long N = (long)q * m;
-    return gemm_mfma(GEMM_LARGE, A_Tf{U32, m}, B_RMf{Z32, N}, EpiStore{Pt, N, wscale}, m, (int)N, (int)N, s);
+    const int sp = projection_splits(m, N, work ? work_elems : 0);
+    return gemm_mfma_splitk(A_Tf{U32, m}, B_RMf{Z32, N}, EpiStore{Pt, N, wscale}, m, (int)N, (int)N, sp, work, s,
+                            GEMM_LARGE);
 }
 
 hipError_t normalize_and_book(const double *Pt, double *A, int q, int m, double *partials, Book *book,

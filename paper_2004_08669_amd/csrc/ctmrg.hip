@@ -106,7 +106,9 @@ bool valid_eig_options(const ctmrg_options &o)
 {
     if (o.eig_solver != CTMRG_EIG_TWO_STAGE && o.eig_solver != CTMRG_EIG_WARM) return false;
     if (o.warm_guard < 0 || o.warm_degree < 0 || o.warm_degree > WARM_DMAX || !(o.warm_tol >= 0.0)) return false;
-    if (o.warm_tail != CTMRG_WARM_TAIL_EXACT && o.warm_tail != CTMRG_WARM_TAIL_BOUND) return false;
+    if (o.warm_tail != CTMRG_WARM_TAIL_EXACT && o.warm_tail != CTMRG_WARM_TAIL_BOUND &&
+        o.warm_tail != CTMRG_WARM_TAIL_AUTO)
+        return false;
     return true;
 }
 
@@ -252,11 +254,14 @@ ctmrg_status one_step(ctmrg_ctx *c)
         prm.degree = c->opt.warm_degree > 0 ? c->opt.warm_degree : 8;
         prm.tol = c->opt.warm_tol > 0.0 ? c->opt.warm_tol : (c->opt.precision == CTMRG_FP32 ? 1e-9 : 1e-12);
         prm.profile = c->profile;
+        // the exact tail only where the bound could matter at the contractions' own precision
+        prm.tail_exact = c->opt.warm_tail == CTMRG_WARM_TAIL_EXACT;
+        prm.tail_tol = c->opt.precision == CTMRG_FP32 ? 1e-9 : 1e-14;
         std::string why;
         const long attempts = c->warm.steps;
         // dX (N x N) is free between the extension and the half-row products
         HIPCHK(c, warm_symmetrize(c->dC, N, s));
-        double *sq = (c->opt.warm_tail == CTMRG_WARM_TAIL_EXACT) ? c->dX : nullptr;
+        double *sq = (c->opt.warm_tail != CTMRG_WARM_TAIL_BOUND) ? c->dX : nullptr;
         HIPCHK(c, warm_solve(c->warm, c->dC, N, m, prm, c->dOmega, c->dOmNew, c->dSel, c->dPost, c->dU, m_eff_prev,
                              c->eig.evals, sq, s, &warm_done, &why));
         if (!warm_done && c->warm.steps > attempts) c->warm.fallbacks += 1;
@@ -312,13 +317,14 @@ ctmrg_status one_step(ctmrg_ctx *c)
         mark(c->eig, MK_HALF, s);
         HIPCHK(c, weight_mix_f32(c->dW32, Y32, Z32, q, m, s));
         mark(c->eig, MK_WMIX2, s);
-        HIPCHK(c, projection_f32(c->dU32, Z32, c->dPt, q, m, c->wscale, s));
+        // dX (Y32) is free once Z is formed: it takes the projection's split-K partials
+        HIPCHK(c, projection_f32(c->dU32, Z32, c->dPt, q, m, c->wscale, c->dX, (size_t)N * N, s));
     } else {
         HIPCHK(c, halfrow_products(c->dA, c->dU, c->dX, q, m, s));
         mark(c->eig, MK_HALF, s);
         HIPCHK(c, weight_mix(c->dW, c->dX, Zb, q, m, s));
         mark(c->eig, MK_WMIX2, s);
-        HIPCHK(c, projection(c->dU, Zb, c->dPt, q, m, s));
+        HIPCHK(c, projection(c->dU, Zb, c->dPt, q, m, c->dX, (size_t)N * N, s));
     }
     mark(c->eig, MK_PROJ, s);
     HIPCHK(c, normalize_and_book(c->dPt, c->dA, q, m, c->dPart, c->dBook, &c->dPost->n_C, &c->dPost->S_E, s));
@@ -376,7 +382,7 @@ ctmrg_status ctmrg_default_options(ctmrg_options *opt)
     opt->warm_guard = 0;
     opt->warm_degree = 0;
     opt->warm_tol = 0.0;
-    opt->warm_tail = CTMRG_WARM_TAIL_EXACT;
+    opt->warm_tail = CTMRG_WARM_TAIL_AUTO;
     return CTMRG_OK;
 }
 
@@ -830,6 +836,7 @@ ctmrg_status ctmrg_get_eig_stats(ctmrg_ctx *c, double *out)
     out[6] = (double)c->warm.last_reason;
     out[7] = c->warm.last_rmax;
     out[11] = c->warm_last_SE;
+    out[12] = (double)c->warm.exact_tails;
     out[8] = c->warm.product_ms;
     out[9] = c->warm.product_flops;
     out[10] = (double)c->warm.product_launches;

@@ -182,7 +182,12 @@ template <> struct Mfma<float> {
 };
 
 // ---------------------------------------------------------------- kernel
-template <int BM, int BN, int BK, int WM, int WN, class LA, class LB, class EPI>
+// PAD: doubles (or floats) of padding per LDS row.  DB: two LDS buffers, so that the next
+// K slice is staged while the matrix cores read the current one (one barrier per slice).
+// VA, VB: consecutive elements of A and B per thread and load (along k when the operand is
+// contiguous in k, else along m / n), so that contiguous operands are read with 16-byte loads.
+template <int BM, int BN, int BK, int WM, int WN, class LA, class LB, class EPI, int PAD = 1, bool DB = false,
+          int VA = 1, int VB = 1>
 __global__ void __launch_bounds__(WM * WN * 64)
 gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
 {
@@ -193,9 +198,10 @@ gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
     constexpr int TM = BM / WM / 16;
     constexpr int TN = BN / WN / 16;
     static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
-    static_assert(BK % 4 == 0, "BK");
-    __shared__ T As[BK][BM + 1];
-    __shared__ T Bs[BK][BN + 1];
+    static_assert(BK % 4 == 0 && BK % VA == 0 && BK % VB == 0 && BM % VA == 0 && BN % VB == 0, "BK / VA / VB");
+    constexpr int NB = DB ? 2 : 1;
+    __shared__ T As[NB][BK][BM + PAD];
+    __shared__ T Bs[NB][BK][BN + PAD];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -252,71 +258,125 @@ gemm_mfma_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
                 }
     }
 
-    // Each thread holds its share of the next K slice in registers while the
-    // matrix cores work on the current one from LDS (one slice of prefetch).
-    constexpr int PA = (BM * BK + NT - 1) / NT;
-    constexpr int PB = (BN * BK + NT - 1) / NT;
-    T ra[PA], rb[PB];
+    // Each thread holds its share of the next K slice in registers while the matrix cores
+    // work on the current one from LDS.  A thread's share is groups of VA (VB) elements.
+    constexpr int GA = BM * BK / VA, GB = BN * BK / VB;
+    constexpr int PA = (GA + NT - 1) / NT;
+    constexpr int PB = (GB + NT - 1) / NT;
+    T ra[PA][VA], rb[PB][VB];
+    // group g of A: VA consecutive k of row mm (contiguous in k) or VA consecutive rows at kk
+    auto a_pos = [](int g, int &mm, int &kk) {
+        if (LA::kContigK) { mm = g / (BK / VA); kk = (g - mm * (BK / VA)) * VA; }
+        else { kk = g / (BM / VA); mm = (g - kk * (BM / VA)) * VA; }
+    };
+    auto b_pos = [](int g, int &nn, int &kk) {
+        if (LB::kContigK) { nn = g / (BK / VB); kk = (g - nn * (BK / VB)) * VB; }
+        else { kk = g / (BN / VB); nn = (g - kk * (BN / VB)) * VB; }
+    };
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < PA; ++u) {
-            const int idx = tid + u * NT;
+            const int g = tid + u * NT;
             int mm, kk;
-            if (LA::kContigK) { mm = idx / BK; kk = idx - mm * BK; }
-            else { kk = idx / BM; mm = idx - kk * BM; }
+            a_pos(g, mm, kk);
             const int gm = m0 + mm, gk = k0 + kk;
-            ra[u] = (idx < BM * BK && gm < M && gk < kend) ? la(gm, gk) : T(0);
+            const bool full = g < GA && (LA::kContigK ? (gm < M && gk + VA <= kend) : (gm + VA <= M && gk < kend));
+            if (full) {
+#pragma unroll
+                for (int v = 0; v < VA; ++v) ra[u][v] = LA::kContigK ? la(gm, gk + v) : la(gm + v, gk);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VA; ++v) {
+                    const int em = LA::kContigK ? gm : gm + v, ek = LA::kContigK ? gk + v : gk;
+                    ra[u][v] = (g < GA && em < M && ek < kend) ? la(em, ek) : T(0);
+                }
+            }
         }
 #pragma unroll
         for (int u = 0; u < PB; ++u) {
-            const int idx = tid + u * NT;
+            const int g = tid + u * NT;
             int nn, kk;
-            if (LB::kContigK) { nn = idx / BK; kk = idx - nn * BK; }
-            else { kk = idx / BN; nn = idx - kk * BN; }
+            b_pos(g, nn, kk);
             const int gn = n0 + nn, gk = k0 + kk;
-            rb[u] = (idx < BN * BK && gn < N && gk < kend) ? lb(gk, gn) : T(0);
+            const bool full = g < GB && (LB::kContigK ? (gn < N && gk + VB <= kend) : (gn + VB <= N && gk < kend));
+            if (full) {
+#pragma unroll
+                for (int v = 0; v < VB; ++v) rb[u][v] = LB::kContigK ? lb(gk + v, gn) : lb(gk, gn + v);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VB; ++v) {
+                    const int en = LB::kContigK ? gn : gn + v, ek = LB::kContigK ? gk + v : gk;
+                    rb[u][v] = (g < GB && en < N && ek < kend) ? lb(ek, en) : T(0);
+                }
+            }
         }
     };
-    auto stage = [&]() {
+    auto stage = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < PA; ++u) {
-            const int idx = tid + u * NT;
-            if (idx < BM * BK) {
+            const int g = tid + u * NT;
+            if (g < GA) {
                 int mm, kk;
-                if (LA::kContigK) { mm = idx / BK; kk = idx - mm * BK; }
-                else { kk = idx / BM; mm = idx - kk * BM; }
-                As[kk][mm] = ra[u];
+                a_pos(g, mm, kk);
+#pragma unroll
+                for (int v = 0; v < VA; ++v) {
+                    if (LA::kContigK) As[buf][kk + v][mm] = ra[u][v];
+                    else As[buf][kk][mm + v] = ra[u][v];
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < PB; ++u) {
-            const int idx = tid + u * NT;
-            if (idx < BN * BK) {
+            const int g = tid + u * NT;
+            if (g < GB) {
                 int nn, kk;
-                if (LB::kContigK) { nn = idx / BK; kk = idx - nn * BK; }
-                else { kk = idx / BN; nn = idx - kk * BN; }
-                Bs[kk][nn] = rb[u];
+                b_pos(g, nn, kk);
+#pragma unroll
+                for (int v = 0; v < VB; ++v) {
+                    if (LB::kContigK) Bs[buf][kk + v][nn] = rb[u][v];
+                    else Bs[buf][kk][nn + v] = rb[u][v];
+                }
             }
         }
     };
-    if (kbeg < kend) fetch(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        stage();
-        __syncthreads();
-        if (k0 + BK < kend) fetch(k0 + BK);
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             T a[TM], b[TN];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) a[i] = As[kk + (lane >> 4)][(wm * TM + i) * 16 + (lane & 15)];
+            for (int i = 0; i < TM; ++i) a[i] = As[buf][kk + (lane >> 4)][(wm * TM + i) * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < TN; ++j) b[j] = Bs[kk + (lane >> 4)][(wn * TN + j) * 16 + (lane & 15)];
+            for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kk + (lane >> 4)][(wn * TN + j) * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(a[i], b[j], acc[i][j]);
         }
+    };
+    if constexpr (DB) {
+        if (kbeg < kend) {
+            fetch(kbeg);
+            stage(0);
+        }
         __syncthreads();
+        int buf = 0;
+        for (int k0 = kbeg; k0 < kend; k0 += BK) {
+            const bool more = k0 + BK < kend;
+            if (more) fetch(k0 + BK);
+            compute(buf);
+            if (more) stage(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    } else {
+        if (kbeg < kend) fetch(kbeg);
+        for (int k0 = kbeg; k0 < kend; k0 += BK) {
+            stage(0);
+            __syncthreads();
+            if (k0 + BK < kend) fetch(k0 + BK);
+            compute(0);
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -388,6 +448,19 @@ reduce_items_kernel(const double *p1, const double *p2, int M, int N, int K, int
     Y[(long)i * ldy + j] = s;
 }
 
+// Staging of the tiles per element type (measured on the contraction shapes at q = 20,
+// m = 512): FP32 operands are read four at a time (16-byte loads) into LDS rows padded by
+// four; FP64 operands one at a time into rows padded by one.  Two LDS buffers pay for the
+// long K loops of the FP64 products with C' (split-K), not for the short ones.
+template <class T> struct TileCfg {
+    static constexpr int PAD = 1, VA = 1, VB = 1;
+    static constexpr bool DB_LONGK = true;
+};
+template <> struct TileCfg<float> {
+    static constexpr int PAD = 4, VA = 4, VB = 4;
+    static constexpr bool DB_LONGK = false;
+};
+
 // Tile configurations.
 enum GemmShape {
     GEMM_LARGE,   // 128 x 128 tile, 2 x 2 waves
@@ -401,25 +474,26 @@ template <class LA, class LB, class EPI>
 hipError_t gemm_mfma(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K, hipStream_t s)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
+    using C = TileCfg<typename LA::value_type>;
     switch (shape) {
     case GEMM_LARGE:
-        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EPI>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
                            dim3(ceil_div(M, 128), ceil_div(N, 128), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_TALL:
-        hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EPI>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
                            dim3(ceil_div(M, 128), ceil_div(N, 32), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_TALL16:
-        hipLaunchKernelGGL((gemm_mfma_kernel<128, 16, 16, 4, 1, LA, LB, EPI>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 16, 16, 4, 1, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
                            dim3(ceil_div(M, 128), ceil_div(N, 16), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_MIX:
-        hipLaunchKernelGGL((gemm_mfma_kernel<80, 128, 16, 1, 4, LA, LB, EPI>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<80, 128, 16, 1, 4, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
                            dim3(ceil_div(M, 80), ceil_div(N, 128), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_SMALL:
-        hipLaunchKernelGGL((gemm_mfma_kernel<64, 64, 16, 2, 2, LA, LB, EPI>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<64, 64, 16, 2, 2, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
                            dim3(ceil_div(M, 64), ceil_div(N, 64), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     }
@@ -446,8 +520,9 @@ hipError_t gemm_mfma_lower_large(LA la, LB lb, EPI epi, int N, int K, hipStream_
     static_assert(lower_tiles<EPI>::value, "lower-tile epilogue");
     if (N <= 0) return hipSuccess;
     const long T = ceil_div(N, 128);
-    hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EPI>), dim3((unsigned)(T * (T + 1) / 2), 1, 1),
-                       dim3(256), 0, s, la, lb, epi, N, N, K, K);
+    using C = TileCfg<typename LA::value_type>;
+    hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EPI, C::PAD, C::DB_LONGK, C::VA, C::VB>),
+                       dim3((unsigned)(T * (T + 1) / 2), 1, 1), dim3(256), 0, s, la, lb, epi, N, N, K, K);
     return hipGetLastError();
 }
 
@@ -462,16 +537,17 @@ hipError_t gemm_mfma_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int spli
     int kchunk = ceil_div(ceil_div(K, splits), 16) * 16;
     splits = ceil_div(K, kchunk);
     EpiPartial part{work, M, N};
+    using C = TileCfg<typename LA::value_type>;
     if (shape == GEMM_LARGE)
-        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EpiPartial>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EpiPartial, C::PAD, C::DB_LONGK, C::VA, C::VB>),
                            dim3(ceil_div(M, 128), ceil_div(N, 128), splits), dim3(256), 0, s, la, lb, part, M, N, K,
                            kchunk);
     else if (shape == GEMM_TALL)
-        hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EpiPartial>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EpiPartial, C::PAD, false, C::VA, C::VB>),
                            dim3(ceil_div(M, 128), ceil_div(N, 32), splits), dim3(256), 0, s, la, lb, part, M, N, K,
                            kchunk);
     else
-        hipLaunchKernelGGL((gemm_mfma_kernel<64, 64, 16, 2, 2, LA, LB, EpiPartial>),
+        hipLaunchKernelGGL((gemm_mfma_kernel<64, 64, 16, 2, 2, LA, LB, EpiPartial, C::PAD, false, C::VA, C::VB>),
                            dim3(ceil_div(M, 64), ceil_div(N, 64), splits), dim3(256), 0, s, la, lb, part, M, N, K,
                            kchunk);
     long total = (long)M * N;

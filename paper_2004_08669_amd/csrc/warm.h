@@ -74,7 +74,7 @@ struct WarmWork {
     int kcur = 0;                     // valid columns of V (0: no warm start)
     double a_prev = 0.0;              // filter bound of the last pass
     // statistics since the last reset
-    long steps = 0, fallbacks = 0, passes = 0, products = 0;
+    long steps = 0, fallbacks = 0, passes = 0, products = 0, exact_tails = 0;
     double tail_bound_max = 0.0;
     double last_rmax = 0.0;           // largest kept residual / |theta_1| of the last pass
     // why the last attempt ended: 0 converged, 1 no warm start, 2 Gram matrix not positive
@@ -88,6 +88,10 @@ struct WarmParams {
     int degree = 4;                   // Chebyshev degree per pass
     int max_passes = 8;
     bool profile = false;             // time every product with C' (HIP events)
+    // sum lambda^4 from ||C'^2||_F^2 (given the scratch): always, or when the bound on the share
+    // of sum w^4 beyond the block exceeds tail_tol
+    bool tail_exact = true;
+    double tail_tol = 0.0;
 };
 
 constexpr int WARM_DMAX = 8;          // largest degree per pass
@@ -104,10 +108,15 @@ size_t warm_bytes(int N, int m, int p);
 // Ritz values ascending followed by NaN.  U must hold the previous step's kept vectors
 // (m_eff_prev columns) on entry.  V then holds the new Ritz vectors for the next step.  sq
 // (N x N scratch, or null): sum lambda^4 is then taken exactly as ||C'^2||_F^2 (one product
-// C' C' on the tiles on and below the diagonal) instead of bounded from ||C'||_F.
+// C' C' on the tiles on and below the diagonal; see WarmParams::tail_exact) instead of bounded
+// from ||C'||_F.
 hipError_t warm_solve(WarmWork &w, const double *C, int N, int m, const WarmParams &prm, const double *omega_prev,
                       double *omega_new, double *selval, PostOut *post_dev, double *U, int m_eff_prev,
                       double *spectrum, double *sq, hipStream_t s, int *converged, std::string *why);
+
+// Upper bound on the share of sum lambda^4 beyond the k values theta (descending |.|), from
+// fro2 = ||C'||_F^2.
+double tail_share_bound(const double *theta, int k, double fro2);
 
 // Copies the lower triangle of C (N x N, row-major) into the upper one.
 hipError_t warm_symmetrize(double *C, int N, hipStream_t s);

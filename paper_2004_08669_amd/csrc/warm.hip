@@ -698,6 +698,23 @@ hipError_t warm_frobenius(WarmWork &w, const double *C, long n2, hipStream_t s)
     return hipGetLastError();
 }
 
+// Upper bound on the share of sum lambda^4 beyond the k Ritz values theta (descending |.|):
+// the remaining sum lambda^2 is ||C'||_F^2 - sum theta^2 and each remaining |lambda| <= |theta_k|.
+double tail_share_bound(const double *theta, int k, double fro2)
+{
+    const double l1 = fabs(theta[0]);
+    if (!(l1 > 0.0)) return 1.0;
+    double s4 = 0.0, s2 = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double x = theta[i] / l1;
+        s4 += (x * x) * (x * x);
+        s2 += x * x;
+    }
+    const double thk = fabs(theta[k - 1]) / l1;
+    const double t4 = thk * thk * std::max(0.0, fro2 / (l1 * l1) - s2);
+    return t4 / (s4 + t4);
+}
+
 hipError_t warm_symmetrize(double *C, int N, hipStream_t s)
 {
     if (N <= 0) return hipSuccess;
@@ -749,11 +766,6 @@ hipError_t warm_solve(WarmWork &w, const double *C, int N, int m, const WarmPara
     }
     hipError_t e = warm_frobenius(w, C, (long)N * N, s);
     if (e != hipSuccess) return e;
-    const double *sum4 = nullptr;
-    if (sq && k < N) {
-        if ((e = warm_sum4(w, C, N, sq, s)) != hipSuccess) return e;
-        sum4 = w.sum4;
-    }
     w.steps += 1;
     // Ritz values of the block from the previous step or pass (host copy), descending |theta|
     double a = std::max(w.a_prev, 1e-12 * fabs(w.h_theta[0]));
@@ -870,6 +882,7 @@ hipError_t warm_solve(WarmWork &w, const double *C, int N, int m, const WarmPara
         e = hipMemcpyAsync(w.h_theta + nl, w.theta + nl, sizeof(double) * ka, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(w.h_res + nl, resn + nl, sizeof(double) * ka, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(w.h_scal + 4, w.fro2, sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
         collect_product_times(w);
@@ -895,6 +908,14 @@ hipError_t warm_solve(WarmWork &w, const double *C, int N, int m, const WarmPara
         }
         const double rtol = prm.tol * fabs(w.h_theta[0]);
         if (rmax <= rtol) {
+            // sum lambda^4 exactly (||C'^2||_F^2) when asked, or when the bound on the share of
+            // sum w^4 beyond the block is above prm.tail_tol
+            const double *sum4 = nullptr;
+            if (sq && k < N && (prm.tail_exact || tail_share_bound(w.h_theta, k, w.h_scal[4]) > prm.tail_tol)) {
+                if ((e = warm_sum4(w, C, N, sq, s)) != hipSuccess) return e;
+                sum4 = w.sum4;
+                w.exact_tails += 1;
+            }
             // 5. outputs: kept vectors in the previous step's gauge, post-eigen quantities
             e = align_block(w, w.V, ld, N, me, w.theta, U, m, m_eff_prev, prm.gap_tol, s);
             if (e != hipSuccess) return e;

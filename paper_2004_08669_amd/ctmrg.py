@@ -30,7 +30,7 @@ STAGES = ["extension", "wmix_C", "dense_to_band", "band_to_tridiag", "bisection"
           "inverse_iteration", "orthonormalize", "backtransform_band", "backtransform_dense", "halfrow",
           "wmix_Z", "projection", "normalize", "step", "warm_topk"]
 EIG_SOLVERS = {"two_stage": 0, "warm": 1}
-WARM_TAILS = {"exact": 0, "bound": 1}
+WARM_TAILS = {"exact": 0, "bound": 1, "auto": 2}
 
 
 class CTMRGError(RuntimeError):
@@ -210,7 +210,7 @@ class CTMRG:
     def __init__(self, V, K: float, m: int, bc: str = "fixed", boundary_spin: int = 0, band: int = 16,
                  gap_tol: float | None = None, rank_tol: float = 1e-13, precision: str = "fp64", stream=None,
                  eig: str = "two_stage", warm_guard: int = 0, warm_degree: int = 0, warm_tol: float = 0.0,
-                 warm_tail: str = "exact"):
+                 warm_tail: str = "auto"):
         lib = load()
         self._lib = lib
         self.V = _f64(V)
@@ -340,12 +340,13 @@ class CTMRG:
 
     def eig_stats(self) -> dict:
         """Counters of the warm eigensolver (see ctmrg_get_eig_stats)."""
-        out = np.zeros(12)
+        out = np.zeros(13)
         self._check(self._lib.ctmrg_get_eig_stats(self._h, _p(out)))
         return {"warm_steps": int(out[0]), "fallback_steps": int(out[1]), "passes": int(out[2]),
                 "products": int(out[3]), "tail_bound_max": float(out[4]), "tail_bound_last": float(out[5]),
                 "last_reason": int(out[6]), "last_residual": float(out[7]), "product_ms": float(out[8]),
-                "product_flops": float(out[9]), "product_launches": int(out[10]), "last_step_S_E": float(out[11])}
+                "product_flops": float(out[9]), "product_launches": int(out[10]), "last_step_S_E": float(out[11]),
+                "exact_tails": int(out[12])}
 
     def P_slices(self) -> np.ndarray:
         """The current P as q slices P_s (m x m)."""

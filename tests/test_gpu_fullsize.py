@@ -6,7 +6,12 @@ compute one by one and properties that hold at any size:
   * the spectrum of C' against its trace and Frobenius norm (sum lambda = Tr C',
     sum lambda^2 = ||C'||_F^2);
   * the kept eigenpairs: residuals ||C' u - lambda u|| and orthonormality;
-  * the normalization omega = lambda / (sum lambda^4)^(1/4) and the symmetry of the new P slices.
+  * the normalization omega = lambda / (sum lambda^4)^(1/4) and the symmetry of the new P slices;
+  * that the kept set is the true top m_eff by modulus, from Sylvester's law of inertia: with t
+    between |lambda_{m_eff}| and |lambda_{m_eff+1}|, the LDL^T factorizations (Bunch-Kaufman,
+    on the host) of C' - t I and C' + t I count the eigenvalues above t and below -t, and
+    together they must be m_eff;
+  * n_C: sum lambda^4 against ||C'^2||_F^2 from one host product.
 Tolerances: backward errors of order N u ||C'|| with N = 10240, u = 1.1e-16 (about 1e-12 ||C'||),
 with a factor ten of margin.
 """
@@ -30,6 +35,26 @@ def _lib():
 
 def say(*a):
     print(*a, flush=True)
+
+
+def _inertia(D):
+    """(positive, negative) eigenvalue counts of the block-diagonal D of an LDL^T factorization
+    (1 x 1 and 2 x 2 blocks)."""
+    n = D.shape[0]
+    sub = np.diag(D, -1)
+    pos = neg = 0
+    i = 0
+    while i < n:
+        if i + 1 < n and sub[i] != 0.0:
+            ev = np.linalg.eigvalsh(np.array([[D[i, i], D[i + 1, i]], [D[i + 1, i], D[i + 1, i + 1]]]))
+            pos += int(np.sum(ev > 0))
+            neg += int(np.sum(ev < 0))
+            i += 2
+        else:
+            pos += int(D[i, i] > 0)
+            neg += int(D[i, i] < 0)
+            i += 1
+    return pos, neg
 
 
 def test_fullsize_m512_step():
@@ -88,6 +113,27 @@ def test_fullsize_m512_step():
     say(f"  kept residual max ||C'u - lambda u|| = {res:.3e} (|lambda_1| = {l1:.3e}); ||U^T U - I|| = {orth:.3e}")
     assert res <= 1e-11 * l1
     assert orth <= 1e-11
+    # the kept set is the top m_eff by modulus (inertia), and n_C from ||C'^2||_F
+    from scipy import linalg
+    mags = np.sort(np.abs(lam))[::-1]
+    t = 0.5 * (mags[me - 1] + mags[me])
+    say(f"  inertia at t = {t:.6e} (|lambda_m_eff| = {mags[me - 1]:.6e}, next {mags[me]:.6e})")
+    Ct = C.copy()
+    Ct[np.diag_indices(N)] -= t
+    _, D, _ = linalg.ldl(Ct, lower=True, overwrite_a=True, check_finite=False)
+    above, _ = _inertia(D)
+    Ct = C.copy()
+    Ct[np.diag_indices(N)] += t
+    _, D, _ = linalg.ldl(Ct, lower=True, overwrite_a=True, check_finite=False)
+    _, below = _inertia(D)
+    del Ct, D
+    say(f"  eigenvalues above t: {above}, below -t: {below}; m_eff {me}")
+    assert above + below == me
+    C2 = C @ C
+    s4 = float(np.sum(C2 * C2))
+    del C2
+    say(f"  sum lambda^4 {np.sum(lam ** 4):.15e} vs ||C'^2||_F^2 {s4:.15e}")
+    assert abs(np.sum(lam ** 4) - s4) <= 1e-12 * s4
     sym = float(np.abs(Pn - Pn.transpose(0, 2, 1)).max())
     say(f"  new P: max |P_s - P_s^T| = {sym:.3e}, max |P| = {np.abs(Pn).max():.3e}")
     assert sym <= 1e-12 * np.abs(Pn).max()
