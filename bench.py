@@ -342,7 +342,7 @@ def main():
         avg_s = w["product_ms"] * 1e-3 / w["product_launches"]
         fl = w["product_flops"] / w["product_launches"]
         ach = fl / avg_s / 1e12
-        return {"kernel": "gemm_mfma_kernel<128, 128, 16, 2, 2, A_RM<double>, B_RM<double>, EpiPartial> + partial sum "
+        return {"kernel": "gemm_mfma_kernel<128, 128, 16, 4, 2, A_RM<double>, B_RM<double>, EpiPartial> + partial sum "
                           "(products C' V of the warm solver)",
                 "bound": "mfma", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / PEAK_FP64_TFLOPS, "traffic": None, "algorithmic_flops_per_launch": fl,

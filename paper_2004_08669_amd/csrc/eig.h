@@ -42,6 +42,7 @@ struct EigWork {
     int pqr_gprev = 0;         // workgroups of the previous panel QR launch
     int pqr_cap = 0;           // panel QR workgroups the device holds at once
     int ysym_cap = 0;          // single-pass Y workgroups the device holds at once
+    size_t lds_bulge_bytes = 0;  // dynamic LDS the in-LDS bulge chasing may use (0: launches only)
     double *splitk = nullptr;  // split-K partials
     size_t splitk_elems = 0;
     // stage 2

@@ -630,6 +630,40 @@ bulge_front_kernel(double *band, int N, int tau, int jlo, double *refl, double *
     bulge_step_pre<B>(band, N, j, t, refl, rtau, Tmax, vsh, wsh);
 }
 
+// The same wavefront order for a band small enough to live in LDS (one workgroup): the band
+// is loaded once, the steps of each tau run on the workgroup's waves, a workgroup barrier
+// separates consecutive tau (it orders the LDS accesses as kernel boundaries order the
+// launches above), and the band is written back at the end.  Each step is the same
+// arithmetic in the same order as in bulge_front_kernel, so the results are identical; what
+// goes away is one launch per tau.  Dynamic LDS: (N 2B + 2 * 16 B) doubles.
+template <int B>
+__global__ void __launch_bounds__(1024)
+bulge_lds_kernel(double *band, int N, double *refl, double *rtau, int Tmax)
+{
+    extern __shared__ double smem[];
+    const int ld = 2 * B;
+    const long total = (long)N * ld;
+    double *sb = smem;
+    double *vsh = smem + total, *wsh = vsh + 16 * B;
+    for (long i = threadIdx.x; i < total; i += blockDim.x) sb[i] = band[i];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int taumax = 3 * (N - 3) + bulge_nsteps(N, B, N - 3);
+    for (int tau = 0; tau < taumax; ++tau) {
+        const int jhi = min(tau / 3, N - 3);
+        const int jlo = max(0, (tau - (Tmax - 1)) / 3);
+        for (int j = jlo + wave; j <= jhi; j += nw) {
+            const int t = tau - 3 * j;
+            if (t >= 0 && t < bulge_nsteps(N, B, j))
+                bulge_step_pre<B>(sb, N, j, t, refl, rtau, Tmax, vsh + wave * B, wsh + wave * B);
+        }
+        __syncthreads();
+    }
+    for (long i = threadIdx.x; i < total; i += blockDim.x) band[i] = sb[i];
+}
+
+size_t bulge_lds_bytes(int N, int b) { return sizeof(double) * ((size_t)N * 2 * b + 2 * 16 * (size_t)b); }
+
 __global__ void band_to_tridiag_kernel(const double *band, int N, int b, double *d, double *e, double *e2)
 {
     const int ld = 2 * b;
@@ -1567,6 +1601,16 @@ static hipError_t eig_setup_limits(EigWork &w, int b)
     int ys_cu = 0;
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ys_cu, (const void *)ysym_items_kernel, 256, 0);
     w.ysym_cap = std::max(1, ys_cu * cus);
+    // the largest dynamic LDS a workgroup may opt into: the bulge chasing of small bands in LDS
+    int lds_max = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+    w.lds_bulge_bytes = 0;
+    if (e == hipSuccess && lds_max > 0) {
+        const size_t want = std::min<size_t>((size_t)lds_max, bulge_lds_bytes(w.Nmax, b));
+        e = hipFuncSetAttribute(b == 32 ? (const void *)bulge_lds_kernel<32> : (const void *)bulge_lds_kernel<16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)want);
+        if (e == hipSuccess) w.lds_bulge_bytes = want;
+    }
     return e;
 }
 
@@ -1969,9 +2013,17 @@ hipError_t eig_values(EigWork &w, double *A, long lda, int N, hipStream_t s)
                        lda, N, b, w.band);
     if (N > 2) {
         const int Tmax = w.Tmax;
-        // one launch per wavefront tau = 3 j + t of independent steps
+        // one launch per wavefront tau = 3 j + t of independent steps, or one workgroup over
+        // them all when the band fits in its LDS
         const int taumax = 3 * (N - 3) + bulge_nsteps(N, b, N - 3);
-        for (int tau = 0; tau < taumax; ++tau) {
+        const size_t lb = bulge_lds_bytes(N, b);
+        if (lb <= w.lds_bulge_bytes) {
+            if (b == 32)
+                hipLaunchKernelGGL(bulge_lds_kernel<32>, dim3(1), dim3(1024), lb, s, w.band, N, w.refl, w.rtau, Tmax);
+            else
+                hipLaunchKernelGGL(bulge_lds_kernel<16>, dim3(1), dim3(1024), lb, s, w.band, N, w.refl, w.rtau, Tmax);
+        }
+        for (int tau = 0; tau < taumax && lb > w.lds_bulge_bytes; ++tau) {
             const int jhi = std::min(tau / 3, N - 3);
             const int jlo = std::max(0, (tau - (Tmax - 1)) / 3);
             if (jhi < jlo) continue;

@@ -450,23 +450,21 @@ reduce_items_kernel(const double *p1, const double *p2, int M, int N, int K, int
 
 // Staging of the tiles per element type (measured on the contraction shapes at q = 20,
 // m = 512): FP32 operands are read four at a time (16-byte loads) into LDS rows padded by
-// four; FP64 operands one at a time into rows padded by one.  Two LDS buffers pay for the
-// long K loops of the FP64 products with C' (split-K), not for the short ones.
+// four; FP64 operands one at a time into rows padded by one.  With eight waves per
+// 128 x 128 tile, two LDS buffers no longer pay.
 template <class T> struct TileCfg {
     static constexpr int PAD = 1, VA = 1, VB = 1;
-    static constexpr bool DB_LONGK = true;
 };
 template <> struct TileCfg<float> {
     static constexpr int PAD = 4, VA = 4, VB = 4;
-    static constexpr bool DB_LONGK = false;
 };
 
 // Tile configurations.
 enum GemmShape {
-    GEMM_LARGE,   // 128 x 128 tile, 2 x 2 waves
+    GEMM_LARGE,   // 128 x 128 tile, 4 x 2 waves (each 32 x 64)
     GEMM_TALL,    // 128 x 32 tile, 4 x 1 waves (outputs with few columns)
     GEMM_TALL16,  // 128 x 16 tile, 4 x 1 waves (outputs of 16 columns)
-    GEMM_MIX,     // 80 x 128 tile, 1 x 4 waves (the q^2 = 400 rows of the W-mix)
+    GEMM_MIX,     // 80 x 128 tile, 1 x 8 waves (the q^2 = 400 rows of the W-mix)
     GEMM_SMALL,   // 64 x 64 tile, 2 x 2 waves
 };
 
@@ -477,8 +475,8 @@ hipError_t gemm_mfma(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K
     using C = TileCfg<typename LA::value_type>;
     switch (shape) {
     case GEMM_LARGE:
-        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
-                           dim3(ceil_div(M, 128), ceil_div(N, 128), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 4, 2, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
+                           dim3(ceil_div(M, 128), ceil_div(N, 128), 1), dim3(512), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_TALL:
         hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
@@ -489,8 +487,8 @@ hipError_t gemm_mfma(GemmShape shape, LA la, LB lb, EPI epi, int M, int N, int K
                            dim3(ceil_div(M, 128), ceil_div(N, 16), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_MIX:
-        hipLaunchKernelGGL((gemm_mfma_kernel<80, 128, 16, 1, 4, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
-                           dim3(ceil_div(M, 80), ceil_div(N, 128), 1), dim3(256), 0, s, la, lb, epi, M, N, K, K);
+        hipLaunchKernelGGL((gemm_mfma_kernel<80, 128, 16, 1, 8, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
+                           dim3(ceil_div(M, 80), ceil_div(N, 128), 1), dim3(512), 0, s, la, lb, epi, M, N, K, K);
         break;
     case GEMM_SMALL:
         hipLaunchKernelGGL((gemm_mfma_kernel<64, 64, 16, 2, 2, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
@@ -521,8 +519,8 @@ hipError_t gemm_mfma_lower_large(LA la, LB lb, EPI epi, int N, int K, hipStream_
     if (N <= 0) return hipSuccess;
     const long T = ceil_div(N, 128);
     using C = TileCfg<typename LA::value_type>;
-    hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EPI, C::PAD, C::DB_LONGK, C::VA, C::VB>),
-                       dim3((unsigned)(T * (T + 1) / 2), 1, 1), dim3(256), 0, s, la, lb, epi, N, N, K, K);
+    hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 4, 2, LA, LB, EPI, C::PAD, false, C::VA, C::VB>),
+                       dim3((unsigned)(T * (T + 1) / 2), 1, 1), dim3(512), 0, s, la, lb, epi, N, N, K, K);
     return hipGetLastError();
 }
 
@@ -539,8 +537,8 @@ hipError_t gemm_mfma_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int spli
     EpiPartial part{work, M, N};
     using C = TileCfg<typename LA::value_type>;
     if (shape == GEMM_LARGE)
-        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 2, 2, LA, LB, EpiPartial, C::PAD, C::DB_LONGK, C::VA, C::VB>),
-                           dim3(ceil_div(M, 128), ceil_div(N, 128), splits), dim3(256), 0, s, la, lb, part, M, N, K,
+        hipLaunchKernelGGL((gemm_mfma_kernel<128, 128, 16, 4, 2, LA, LB, EpiPartial, C::PAD, false, C::VA, C::VB>),
+                           dim3(ceil_div(M, 128), ceil_div(N, 128), splits), dim3(512), 0, s, la, lb, part, M, N, K,
                            kchunk);
     else if (shape == GEMM_TALL)
         hipLaunchKernelGGL((gemm_mfma_kernel<128, 32, 16, 4, 1, LA, LB, EpiPartial, C::PAD, false, C::VA, C::VB>),

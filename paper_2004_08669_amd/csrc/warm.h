@@ -60,7 +60,7 @@ struct WarmWork {
     double *h_theta = nullptr, *h_res = nullptr, *h_coef = nullptr;  // pinned host copies
     PostOut *h_post = nullptr;
     double *h_scal = nullptr;         // pinned host scalars
-    double *pbig = nullptr;           // split-K partials of the products with C' (part_elems)
+    double *pbig = nullptr;           // split-K partials of the products with C' (part_elems = 4 N kmax)
     size_t part_elems = 0;
     // live timing of the products with C' (when profiling): event pairs of one pass, the sums
     static constexpr int NEV = 24;

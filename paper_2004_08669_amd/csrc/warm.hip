@@ -540,7 +540,7 @@ hipError_t product(WarmWork &w, const double *C, int N, const double *B, int ka,
 {
     const long tiles = (long)ceil_div(N, 128) * ceil_div(ka, 128);
     int sp = 1;
-    while (tiles * sp < 768 && (size_t)(2 * sp) * N * ka <= w.part_elems) sp *= 2;
+    while (tiles * sp < 1024 && (size_t)(2 * sp) * N * ka <= w.part_elems) sp *= 2;
     const bool rec = timed && w.nev < WarmWork::NEV;
     if (rec) (void)hipEventRecord(w.ev[2 * w.nev], s);
     hipError_t e = (sp == 1) ? gemm_mfma(GEMM_LARGE, A_RM{C, N}, B_RM{B, w.kmax}, epi, N, ka, N, s)
@@ -626,7 +626,7 @@ size_t warm_bytes(int N, int m, int p)
 {
     const size_t k = (size_t)std::min(N, m + p);
     const size_t nb = (k + CB - 1) / CB;
-    size_t s = sizeof(double) * (6 * (size_t)N * k + 5 * k * k + nb * CB * CB + 3 * (k + 8) + k + 2 * WARM_DMAX * k +
+    size_t s = sizeof(double) * (8 * (size_t)N * k + 5 * k * k + nb * CB * CB + 3 * (k + 8) + k + 2 * WARM_DMAX * k +
                                  RES_CHUNKS * k + k + 1024 + 24);
     s += sizeof(PostOut) + 64;
     s += eig_bytes((int)k, (int)k, 16);
@@ -647,9 +647,9 @@ hipError_t warm_alloc(WarmWork &w, int N, int m, int p)
         {&w.G, k * k}, {&w.H, k * k}, {&w.Hs, k * k}, {&w.X, k * k}, {&w.Mov, k * k},
         {&w.Linv, (size_t)w.nb * CB * CB}, {&w.theta, k + 8}, {&w.zero, k + 8}, {&w.scr, k + 8},
         {&w.coef, 2 * (size_t)WARM_DMAX * k}, {&w.res, (size_t)RES_CHUNKS * k + k}, {&w.part, 1024}, {&w.fro2, 8}, {&w.sum4, 8},
-        {&w.pbig, 2 * (size_t)N * k},
+        {&w.pbig, 4 * (size_t)N * k},
     };
-    w.part_elems = 2 * (size_t)N * k;
+    w.part_elems = 4 * (size_t)N * k;
     for (auto &r : reqs) {
         hipError_t e = hipMalloc((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
         if (e != hipSuccess) return e;

@@ -6,7 +6,9 @@ References that do not come from the GPU path:
   * q = 20: the oracle's central difference [F(K+h) - F(K-h)] / 2h of its own fixed points
     (h = 1e-4, each converged to Delta < 1e-13: accurate to about 1e-8), the oracle's impurity
     energy at the same m (equal to dF/dK at an exact fixed point), and the central difference
-    of that energy for d2F/dK2 (accurate to about 1e-7).
+    of that energy for d2F/dK2 (accurate to about 1e-7);
+  * q = 20, m = 128 at T = 0.40, 0.44, 0.48 (three temperatures of the sweep): the oracle's f
+    and impurity energy at its own fixed point (tests/golden).
 """
 import os
 
@@ -115,19 +117,41 @@ def test_backward_combines_the_derivatives():
     g.close()
 
 
-def test_derivative_m128_equals_impurity_energy():
-    """At m = 128 (C' 2560 x 2560, the size of the temperature sweep with derivatives): the
-    derivative of F equals the energy of the impurity plaquette on the same fixed point."""
+@pytest.mark.parametrize("T", [0.40, 0.44, 0.48])
+def test_derivative_m128_equals_impurity_energy(T):
+    """At m = 128 (C' 2560 x 2560, the size of the temperature sweep with derivatives), at three of
+    its temperatures: the derivative of F equals the energy of the impurity plaquette on the same
+    fixed point and on the oracle's own fixed point (tests/golden, converged independently to
+    1e-12); at T = 0.44 it also equals the central difference of F = K f over fixed points at
+    K +- 1e-4."""
     ct = _lib()
     V = I.dodecahedron()
-    K = 1.0 / 0.40
-    say("[derivative m=128] T=0.40")
+    K = 1.0 / T
+    ref = _golden(f"fixedpoint_q20_m128_T{T:.2f}.npz")
+    say(f"[derivative m=128] T={T}; oracle fixed point in {int(ref['steps'])} steps")
     g = _converged(ct, V, K, 128, tol=1e-12, max_steps=2000)
     obs = g.observables()
     r = g.fixed_point_derivative()
     g.close()
-    say(f"  {r}; E_imp {obs['E']:.13f}")
+    Eo, fo = float(ref["E"]), float(ref["f"])
+    say(f"  {r}; E_imp gpu {obs['E']:.13f} oracle {Eo:.13f}; f gpu {obs['f']:.13f} oracle {fo:.13f}")
     assert abs(r["dF_dK"] - obs["E"]) <= 1e-8
+    assert abs(r["dF_dK"] - Eo) <= 1e-8
+    assert abs(obs["f"] - fo) <= 1e-10 * abs(fo)
+    assert abs(r["F"] - K * fo) <= 1e-10 * abs(K * fo)
+    if T == 0.44:
+        h = 1e-4
+        F = {}
+        for sgn in (1, -1):
+            # the fixed points at K +- h with the warm-started eigensolver (f is exact on it)
+            w = ct.CTMRG(V, K + sgn * h, 128, eig="warm")
+            ks, d, conv = w.run_to_fixed_point(1e-12, 3000)
+            assert conv, (ks, d)
+            F[sgn] = (K + sgn * h) * w.observables()["f"]
+            w.close()
+        fd = (F[1] - F[-1]) / (2 * h)
+        say(f"  dF/dK {r['dF_dK']:.13f}, central difference of F {fd:.13f}")
+        assert abs(r["dF_dK"] - fd) <= 1e-7
 
 
 def test_autograd_function():
