@@ -111,6 +111,13 @@ typedef struct {
     double warm_tol;      /* CTMRG_EIG_WARM: kept residuals below warm_tol |lambda_1|
                              (0 = 1e-12 for FP64 contractions, 1e-9 for FP32)                  */
     int warm_tail;        /* CTMRG_EIG_WARM: ctmrg_warm_tail (default CTMRG_WARM_TAIL_AUTO)    */
+    void *workspace;      /* NULL, or device memory of workspace_bytes >= ctmrg_workspace_size()
+                             bytes, owned by the caller and kept alive until ctmrg_destroy: every
+                             device buffer ctmrg_init would allocate is carved from it instead
+                             (256-byte aligned).  Pinned host buffers, and the buffers that
+                             ctmrg_observables and the derivative allocate on first use
+                             (ctmrg_extra_workspace_size), are still allocated by the library. */
+    size_t workspace_bytes;
 } ctmrg_options;
 
 typedef struct {
@@ -159,6 +166,18 @@ ctmrg_status ctmrg_step(ctmrg_ctx *ctx, int nsteps, double *delta_out);
 /* Step until Delta < tol (after at least two steps) or max_steps steps were taken.
  * Returns CTMRG_E_NOT_CONVERGED if max_steps is reached (the state is kept). */
 ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *ctx, double tol, int max_steps, int *steps_out, double *delta_out);
+
+/* A sweep over temperatures, the scans of Sec. IV (for one cutoff m: a (T, m) grid is one
+ * context per m).  For each T[i] in order: K = 1/T[i]; the state restarts from the boundary
+ * (warm_start = 0; as ctmrg_set_K) or is kept from the previous temperature's fixed point
+ * (warm_start = 1, from the second temperature on; W is rebuilt); at least two and at most
+ * max_steps steps until Delta < tol; then out[i] = ctmrg_observables (M, S_E, xi_e, f, E, ...).
+ * steps_out[i] and converged[i] (both nullable) receive the steps taken and whether Delta < tol
+ * was reached; a temperature that does not converge is reported and the sweep continues.
+ * Errors: CTMRG_E_INVALID_ARG (n < 0, a temperature not positive, max_steps < 2, tol < 0),
+ * and those of ctmrg_step and ctmrg_observables, which stop the sweep. */
+ctmrg_status ctmrg_sweep(ctmrg_ctx *ctx, int n, const double *T, double tol, int max_steps, int warm_start,
+                         ctmrg_observables_t *out, int *steps_out, int *converged);
 
 /* Observables of the current state (Sec. II: Eqs. 3-6 on the fixed-point
  * matrices; the free energy from the normalization history).  Needs >= 1 step
@@ -227,7 +246,8 @@ ctmrg_status ctmrg_import_state(ctmrg_ctx *ctx, const void *host_buf, size_t byt
  * omega (d values), d <= m.  The normalization history is reset. */
 ctmrg_status ctmrg_set_state(ctmrg_ctx *ctx, int d, const double *P, const double *omega);
 
-/* Device bytes a context with these sizes allocates. */
+/* Device bytes a context with these sizes allocates at init (each buffer rounded up to 256
+ * bytes; with dim = 3, an upper bound for smaller dim): the size a caller-owned workspace needs. */
 ctmrg_status ctmrg_workspace_size(int q, int m, const ctmrg_options *opt, size_t *bytes);
 
 /* Device bytes a context allocates later, on first use (each once, kept until

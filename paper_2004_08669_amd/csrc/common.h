@@ -77,3 +77,28 @@ CTMRG_DEVINL double hash_uniform(uint64_t key)
     z = z ^ (z >> 31);
     return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
+
+// Device buffers of a context either from hipMalloc (no base) or carved, 256-byte aligned, from
+// one block of device memory the caller owns (base, cap).  count_only: only add up the bytes the
+// carving would use (no HIP call).
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    bool count_only = false;
+    static size_t round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+    bool carving() const { return base != nullptr || count_only; }
+    hipError_t take(void **p, size_t bytes)
+    {
+        const size_t sz = round(bytes > 0 ? bytes : 1);
+        if (count_only) {
+            *p = nullptr;
+            used += sz;
+            return hipSuccess;
+        }
+        if (!base) return hipMalloc(p, sz);
+        if (used + sz > cap) return hipErrorOutOfMemory;
+        *p = base + used;
+        used += sz;
+        return hipSuccess;
+    }
+};

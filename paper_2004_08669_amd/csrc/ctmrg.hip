@@ -47,9 +47,10 @@ struct ctmrg_ctx {
     int m_eff_prev2 = 0;  // kept dimension of the step before the last
     // N x N: the half-row Z of a warm-mode step, which leaves that step's C' in dC
     double *dZ = nullptr;
-    bool last_warm = false;
+    bool last_warm = false;  // the last step was solved warm (its C' is intact in dC)
+    bool carved = false;     // the device buffers of init are carved from the caller's workspace
     // effective correlation length (Lanczos on the row-to-row transfer matrix), allocated on first use
-    XiWork xi;  // the last step was solved warm (its C' is intact in dC)
+    XiWork xi;
     // fixed-point derivative: its workspace and the weight at K +- dK
     AdjWork adj;
     double *dWd = nullptr, *dWHd = nullptr;
@@ -128,18 +129,18 @@ void free_all(ctmrg_ctx *c)
 {
     xi_free(c->xi);
     double *bufs[] = {c->dV, c->dW, c->dWH, c->dA, c->dOA, c->dPt, c->dOmega, c->dOmNew, c->dSel,
-                      c->dX, c->dC, c->dU, c->dPart, c->dObs, c->dH, c->dWork, c->dZ};
-    for (double *p : bufs)
-        if (p) (void)hipFree(p);
+                      c->dX, c->dC, c->dU, c->dPart, c->dObs, c->dH, c->dWork, c->dZ, c->dSelK, c->dOmK};
     float *fbufs[] = {c->dW32, c->dA32, c->dOA32, c->dU32};
-    for (float *p : fbufs)
-        if (p) (void)hipFree(p);
-    if (c->dBook) (void)hipFree(c->dBook);
-    if (c->dPost) (void)hipFree(c->dPost);
+    if (!c->carved) {
+        for (double *p : bufs)
+            if (p) (void)hipFree(p);
+        for (float *p : fbufs)
+            if (p) (void)hipFree(p);
+        if (c->dBook) (void)hipFree(c->dBook);
+        if (c->dPost) (void)hipFree(c->dPost);
+        if (c->dPostK) (void)hipFree(c->dPostK);
+    }
     if (c->hPost) (void)hipHostFree(c->hPost);
-    if (c->dSelK) (void)hipFree(c->dSelK);
-    if (c->dOmK) (void)hipFree(c->dOmK);
-    if (c->dPostK) (void)hipFree(c->dPostK);
     if (c->hPostK) (void)hipHostFree(c->hPostK);
     warm_free(c->warm);
     eig_free(c->eig);
@@ -153,28 +154,75 @@ void free_all(ctmrg_ctx *c)
 
 int warm_guard(const ctmrg_options &o, int m) { return o.warm_guard > 0 ? o.warm_guard : std::max(8, m / 4); }
 
-size_t context_bytes(int q, int m, int band, int precision, const ctmrg_options &o)
+// Every device buffer a context allocates at init, through the arena, in one fixed order (a
+// count-only pass gives the bytes of the carving).
+hipError_t alloc_device(ctmrg_ctx *c, Arena &a)
 {
-    const size_t N = (size_t)q * m;
+    const int q = c->q, m = c->m, dim = c->dim;
+    const long N = c->N;
+    const ctmrg_options &o = c->opt;
     const size_t q4 = (size_t)q * q * q * q;
-    size_t s = 0;
-    s += sizeof(double) * (q * 3 + 2 * q4);
-    s += sizeof(double) * 3 * (size_t)m * N;
-    s += sizeof(double) * (3 * (size_t)m + 8);
-    s += sizeof(double) * 2 * N * N;
-    s += sizeof(double) * N * m;
-    s += sizeof(double) * (4096 + 64 + q + q4 + 64 * q4);
-    s += sizeof(Book) + sizeof(PostOut);
-    if (o.eig_solver == CTMRG_EIG_WARM) {
-        const int p = warm_guard(o, m), k = (int)std::min<size_t>(N, (size_t)m + p);
-        s += eig_bytes((int)N, k, band) + warm_bytes((int)N, m, p);
-        s += sizeof(double) * (2 * (size_t)k + 16) + sizeof(PostOut);
-        s += sizeof(double) * N * N;  // dZ
-    } else {
-        s += eig_bytes((int)N, m, band);
+    c->work_elems = 64 * q4;
+    struct Req { double **p; size_t n; };
+    Req reqs[] = {
+        {&c->dV, (size_t)q * dim}, {&c->dW, q4}, {&c->dWH, q4},
+        {&c->dA, (size_t)m * N}, {&c->dOA, (size_t)m * N}, {&c->dPt, (size_t)m * N},
+        {&c->dOmega, (size_t)m}, {&c->dOmNew, (size_t)m}, {&c->dSel, (size_t)m + 8},
+        {&c->dX, (size_t)N * N}, {&c->dC, (size_t)N * N}, {&c->dU, (size_t)N * m},
+        {&c->dPart, 4096}, {&c->dObs, (size_t)64 + q}, {&c->dH, q4}, {&c->dWork, c->work_elems},
+    };
+    hipError_t e = hipSuccess;
+    for (auto &r : reqs)
+        if (e == hipSuccess) e = a.take((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
+    if (o.precision == CTMRG_FP32) {
+        struct ReqF { float **p; size_t n; };
+        ReqF fr[] = {{&c->dW32, q4}, {&c->dA32, (size_t)m * N}, {&c->dOA32, (size_t)m * N}, {&c->dU32, (size_t)N * m}};
+        for (auto &r : fr)
+            if (e == hipSuccess) e = a.take((void **)r.p, sizeof(float) * std::max<size_t>(r.n, 1));
     }
-    if (precision == CTMRG_FP32) s += sizeof(float) * (q4 + 3 * (size_t)m * N);
-    return s;
+    if (e == hipSuccess) e = a.take((void **)&c->dBook, sizeof(Book));
+    if (e == hipSuccess) e = a.take((void **)&c->dPost, sizeof(PostOut));
+    const bool warm = o.eig_solver == CTMRG_EIG_WARM;
+    if (warm) {
+        c->warm_p = warm_guard(o, m);
+        c->warm_k = (int)std::min<long>(N, (long)m + c->warm_p);
+    }
+    // the eigensolver's workspace: one block when carving
+    const int kk = warm ? c->warm_k : m;
+    if (e == hipSuccess) {
+        if (a.carving()) {
+            void *base = nullptr;
+            const size_t eb = eig_bytes((int)N, kk, o.band);
+            e = a.take(&base, eb);
+            if (e == hipSuccess && !a.count_only) e = eig_carve(c->eig, base, eb, (int)N, kk, o.band, c->stream);
+            if (e == hipSuccess && !a.count_only) e = eig_attach_streams(c->eig);
+        } else {
+            e = eig_alloc(c->eig, (int)N, kk, o.band);
+        }
+    }
+    if (warm) {
+        if (e == hipSuccess) e = warm_alloc(c->warm, (int)N, m, c->warm_p, &a, c->stream);
+        if (e == hipSuccess) e = a.take((void **)&c->dSelK, sizeof(double) * ((size_t)c->warm_k + 8));
+        if (e == hipSuccess) e = a.take((void **)&c->dOmK, sizeof(double) * ((size_t)c->warm_k + 8));
+        if (e == hipSuccess) e = a.take((void **)&c->dPostK, sizeof(PostOut));
+        if (e == hipSuccess) e = a.take((void **)&c->dZ, sizeof(double) * (size_t)N * N);
+    }
+    return e;
+}
+
+// The bytes alloc_device carves (each buffer rounded up to 256 bytes).
+size_t context_bytes(int q, int m, int dim, const ctmrg_options &o)
+{
+    ctmrg_ctx t;
+    t.q = q;
+    t.m = m;
+    t.dim = dim;
+    t.N = q * m;
+    t.opt = o;
+    Arena a;
+    a.count_only = true;
+    (void)alloc_device(&t, a);
+    return a.used;
 }
 
 ctmrg_status reset_state(ctmrg_ctx *c)
@@ -408,7 +456,7 @@ ctmrg_status ctmrg_workspace_size(int q, int m, const ctmrg_options *opt, size_t
     if (!valid_band(o.band)) return CTMRG_E_INVALID_ARG;
     if (o.precision != CTMRG_FP64 && o.precision != CTMRG_FP32) return CTMRG_E_INVALID_ARG;
     if (!valid_eig_options(o)) return CTMRG_E_INVALID_ARG;
-    *bytes = context_bytes(q, m, o.band, o.precision, o);
+    *bytes = context_bytes(q, m, 3, o);
     return CTMRG_OK;
 }
 
@@ -449,44 +497,21 @@ ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, 
         }
         c->own_stream = true;
     }
-    const size_t q4 = (size_t)q * q * q * q;
-    c->work_elems = 64 * q4;
-    struct Req { double **p; size_t n; };
-    Req reqs[] = {
-        {&c->dV, (size_t)q * dim}, {&c->dW, q4}, {&c->dWH, q4},
-        {&c->dA, (size_t)m * N}, {&c->dOA, (size_t)m * N}, {&c->dPt, (size_t)m * N},
-        {&c->dOmega, (size_t)m}, {&c->dOmNew, (size_t)m}, {&c->dSel, (size_t)m + 8},
-        {&c->dX, (size_t)N * N}, {&c->dC, (size_t)N * N}, {&c->dU, (size_t)N * m},
-        {&c->dPart, 4096}, {&c->dObs, (size_t)64 + q}, {&c->dH, q4}, {&c->dWork, c->work_elems},
-    };
-    for (auto &r : reqs) {
-        hipError_t e = hipMalloc((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
-        if (e != hipSuccess) { *out = c; return hip_fail(c, e, "hipMalloc"); }
-    }
-    if (o.precision == CTMRG_FP32) {
-        struct ReqF { float **p; size_t n; };
-        ReqF fr[] = {{&c->dW32, q4}, {&c->dA32, (size_t)m * N}, {&c->dOA32, (size_t)m * N}, {&c->dU32, (size_t)N * m}};
-        for (auto &r : fr) {
-            hipError_t e = hipMalloc((void **)r.p, sizeof(float) * std::max<size_t>(r.n, 1));
-            if (e != hipSuccess) { *out = c; return hip_fail(c, e, "hipMalloc"); }
+    Arena arena;
+    if (o.workspace) {
+        const size_t need = context_bytes(q, m, dim, o);
+        if (o.workspace_bytes < need) {
+            *out = c;
+            return fail(c, CTMRG_E_INVALID_ARG, "workspace smaller than ctmrg_workspace_size");
         }
+        arena.base = static_cast<char *>(o.workspace);
+        arena.cap = o.workspace_bytes;
+        c->carved = true;
     }
-    hipError_t e = hipMalloc((void **)&c->dBook, sizeof(Book));
-    if (e == hipSuccess) e = hipMalloc((void **)&c->dPost, sizeof(PostOut));
+    hipError_t e = alloc_device(c, arena);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->hPost, sizeof(PostOut), hipHostMallocDefault);
-    if (o.eig_solver == CTMRG_EIG_WARM) {
-        c->warm_p = warm_guard(o, m);
-        c->warm_k = (int)std::min<long>(N, (long)m + c->warm_p);
-        if (e == hipSuccess) e = eig_alloc(c->eig, (int)N, c->warm_k, o.band);
-        if (e == hipSuccess) e = warm_alloc(c->warm, (int)N, m, c->warm_p);
-        if (e == hipSuccess) e = hipMalloc((void **)&c->dSelK, sizeof(double) * ((size_t)c->warm_k + 8));
-        if (e == hipSuccess) e = hipMalloc((void **)&c->dOmK, sizeof(double) * ((size_t)c->warm_k + 8));
-        if (e == hipSuccess) e = hipMalloc((void **)&c->dPostK, sizeof(PostOut));
-        if (e == hipSuccess) e = hipHostMalloc((void **)&c->hPostK, sizeof(PostOut), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMalloc((void **)&c->dZ, sizeof(double) * (size_t)N * N);
-    } else if (e == hipSuccess) {
-        e = eig_alloc(c->eig, (int)N, m, o.band);
-    }
+    if (e == hipSuccess && o.eig_solver == CTMRG_EIG_WARM)
+        e = hipHostMalloc((void **)&c->hPostK, sizeof(PostOut), hipHostMallocDefault);
     if (e != hipSuccess) { *out = c; return hip_fail(c, e, "allocation"); }
     e = hipMemcpy(c->dV, c->V.data(), sizeof(double) * q * dim, hipMemcpyHostToDevice);
     if (e != hipSuccess) { *out = c; return hip_fail(c, e, "hipMemcpy"); }
@@ -532,6 +557,43 @@ ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *c, double tol, int max_steps, i
     if (delta_out) *delta_out = c->delta;
     if (st == CTMRG_E_NOT_CONVERGED) c->err = "max_steps reached before Delta < tol";
     return st;
+}
+
+ctmrg_status ctmrg_sweep(ctmrg_ctx *c, int n, const double *T, double tol, int max_steps, int warm_start,
+                         ctmrg_observables_t *out, int *steps_out, int *converged)
+{
+    if (!c || n < 0 || (n > 0 && (!T || !out)) || max_steps < 2 || !(tol >= 0.0)) return CTMRG_E_INVALID_ARG;
+    for (int i = 0; i < n; ++i)
+        if (!(T[i] > 0.0) || !std::isfinite(T[i])) return fail(c, CTMRG_E_INVALID_ARG, "temperatures must be positive");
+    for (int i = 0; i < n; ++i) {
+        const double K = 1.0 / T[i];
+        if (warm_start && i > 0) {
+            // the previous temperature's fixed point is the start: new weights, same state
+            c->K = K;
+            HIPCHK(c, make_weight(c));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        } else {
+            const ctmrg_status st = ctmrg_set_K(c, K);
+            if (st != CTMRG_OK) return st;
+        }
+        // at least two steps at each temperature: Delta then compares two steps at the same K
+        int taken = 0;
+        bool conv = false;
+        while (taken < max_steps) {
+            const ctmrg_status st = one_step(c);
+            if (st != CTMRG_OK) return st;
+            ++taken;
+            if (taken >= 2 && c->delta < tol) {
+                conv = true;
+                break;
+            }
+        }
+        if (steps_out) steps_out[i] = taken;
+        if (converged) converged[i] = conv ? 1 : 0;
+        const ctmrg_status st = ctmrg_observables(c, out + i, nullptr);
+        if (st != CTMRG_OK) return st;
+    }
+    return CTMRG_OK;
 }
 
 ctmrg_status ctmrg_observables(ctmrg_ctx *c, ctmrg_observables_t *out, double *kept_spectrum)

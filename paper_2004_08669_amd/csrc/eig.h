@@ -104,6 +104,8 @@ hipError_t eig_alloc(EigWork &w, int Nmax, int kmax, int b);
 // 256-byte aligned); no allocation, no second stream (the look-ahead of stage 1 then runs in order on
 // the caller's stream).  The exchange slots and error flags are reset by fill kernels on s.
 hipError_t eig_carve(EigWork &w, void *base, size_t bytes, int Nmax, int kmax, int b, hipStream_t s);
+// The second stream and its events (the look-ahead of stage 1) for a carved workspace.
+hipError_t eig_attach_streams(EigWork &w);
 void eig_free(EigWork &w);
 size_t eig_bytes(int Nmax, int kmax, int b);
 

@@ -1671,6 +1671,14 @@ hipError_t eig_carve(EigWork &w, void *base, size_t bytes, int Nmax, int kmax, i
     return e;
 }
 
+hipError_t eig_attach_streams(EigWork &w)
+{
+    hipError_t e = hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_cols, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&w.ev_update, hipEventDisableTiming);
+    return e;
+}
+
 void eig_free(EigWork &w)
 {
     void *ptrs[] = {w.Vx, w.Tp, w.tau1, w.VW, w.WV, w.Y, w.X, w.sm, w.part, w.splitk, w.band, w.refl, w.rtau,

@@ -70,6 +70,7 @@ struct WarmWork {
     long product_launches = 0;
     double pending_flops[NEV] = {};
     EigWork rr;                       // two-stage solver for the k x k Rayleigh-Ritz problem
+    bool carved = false;              // device buffers carved from a caller's workspace (not freed here)
     // state carried between steps
     int kcur = 0;                     // valid columns of V (0: no warm start)
     double a_prev = 0.0;              // filter bound of the last pass
@@ -96,8 +97,9 @@ struct WarmParams {
 
 constexpr int WARM_DMAX = 8;          // largest degree per pass
 
-// k = m + p columns of at most N.
-hipError_t warm_alloc(WarmWork &w, int N, int m, int p);
+// k = m + p columns of at most N.  Device buffers through ar (hipMalloc when it does not carve);
+// with ar->count_only only ar->used grows.
+hipError_t warm_alloc(WarmWork &w, int N, int m, int p, Arena *ar = nullptr, hipStream_t s = nullptr);
 void warm_free(WarmWork &w);
 size_t warm_bytes(int N, int m, int p);
 

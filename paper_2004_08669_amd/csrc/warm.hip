@@ -633,8 +633,10 @@ size_t warm_bytes(int N, int m, int p)
     return s;
 }
 
-hipError_t warm_alloc(WarmWork &w, int N, int m, int p)
+hipError_t warm_alloc(WarmWork &w, int N, int m, int p, Arena *ar, hipStream_t s)
 {
+    Arena own;
+    Arena &a = ar ? *ar : own;
     w.N = N;
     w.m = m;
     w.p = p;
@@ -650,13 +652,19 @@ hipError_t warm_alloc(WarmWork &w, int N, int m, int p)
         {&w.pbig, 4 * (size_t)N * k},
     };
     w.part_elems = 4 * (size_t)N * k;
+    w.carved = a.carving();
     for (auto &r : reqs) {
-        hipError_t e = hipMalloc((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
+        hipError_t e = a.take((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
         if (e != hipSuccess) return e;
     }
-    hipError_t e = hipMalloc((void **)&w.rr_post, sizeof(PostOut));
-    if (e == hipSuccess) e = hipMalloc((void **)&w.err, 64);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&w.h_theta, sizeof(double) * (k + 8), hipHostMallocDefault);
+    hipError_t e = a.take((void **)&w.rr_post, sizeof(PostOut));
+    if (e == hipSuccess) e = a.take((void **)&w.err, 64);
+    // the small solver's workspace
+    void *rr_base = nullptr;
+    const size_t rr_bytes = eig_bytes(w.kmax, w.kmax, 16);
+    if (e == hipSuccess && a.carving()) e = a.take(&rr_base, rr_bytes);
+    if (e != hipSuccess || a.count_only) return e;
+    e = hipHostMalloc((void **)&w.h_theta, sizeof(double) * (k + 8), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w.h_res, sizeof(double) * (k + 8), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&w.h_coef, sizeof(double) * 2 * WARM_DMAX * k, hipHostMallocDefault);
@@ -665,7 +673,8 @@ hipError_t warm_alloc(WarmWork &w, int N, int m, int p)
 
     if (e == hipSuccess) e = hipMemset(w.zero, 0, sizeof(double) * (k + 8));
     if (e == hipSuccess) e = hipMemset(w.err, 0, 64);
-    if (e == hipSuccess) e = eig_alloc(w.rr, w.kmax, w.kmax, 16);
+    if (e == hipSuccess) e = rr_base ? eig_carve(w.rr, rr_base, rr_bytes, w.kmax, w.kmax, 16, s)
+                                     : eig_alloc(w.rr, w.kmax, w.kmax, 16);
     for (int i = 0; i < 2 * WarmWork::NEV && e == hipSuccess; ++i) e = hipEventCreate(&w.ev[i]);
     return e;
 }
@@ -673,11 +682,13 @@ hipError_t warm_alloc(WarmWork &w, int N, int m, int p)
 void warm_free(WarmWork &w)
 {
     double *bufs[] = {w.V, w.Y, w.CQ, w.CV, w.G, w.H, w.Hs, w.X, w.Mov, w.Linv, w.theta, w.zero, w.scr,
-                      w.coef, w.res, w.part, w.fro2, w.pbig};
-    for (double *p : bufs)
-        if (p) (void)hipFree(p);
-    if (w.rr_post) (void)hipFree(w.rr_post);
-    if (w.err) (void)hipFree(w.err);
+                      w.coef, w.res, w.part, w.fro2, w.sum4, w.pbig};
+    if (!w.carved) {
+        for (double *p : bufs)
+            if (p) (void)hipFree(p);
+        if (w.rr_post) (void)hipFree(w.rr_post);
+        if (w.err) (void)hipFree(w.err);
+    }
     if (w.h_theta) (void)hipHostFree(w.h_theta);
     if (w.h_res) (void)hipHostFree(w.h_res);
     if (w.h_coef) (void)hipHostFree(w.h_coef);

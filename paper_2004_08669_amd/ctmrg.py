@@ -53,6 +53,8 @@ class Options(ctypes.Structure):
         ("warm_degree", ctypes.c_int),
         ("warm_tol", ctypes.c_double),
         ("warm_tail", ctypes.c_int),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
     ]
 
 
@@ -116,6 +118,9 @@ def load():
         "ctmrg_run_to_fixed_point": ([_vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp],
                                      ctypes.c_int),
         "ctmrg_observables": ([_vp, ctypes.POINTER(Observables), _dp], ctypes.c_int),
+        "ctmrg_sweep": ([_vp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                         ctypes.POINTER(Observables), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                        ctypes.c_int),
         "ctmrg_backward": ([_vp, _dp, _dp, _dp], ctypes.c_int),
         "ctmrg_fixed_point_derivative": ([_vp, ctypes.c_int, ctypes.POINTER(Derivative)], ctypes.c_int),
         "ctmrg_export_state": ([_vp, _vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -157,9 +162,12 @@ def default_options() -> Options:
     return o
 
 
-def workspace_size(q: int, m: int, band: int = 16) -> int:
+def workspace_size(q: int, m: int, band: int = 16, precision: str = "fp64", eig: str = "two_stage") -> int:
+    """Device bytes a context allocates at init (what a caller-owned workspace needs)."""
     o = default_options()
     o.band = band
+    o.precision = {"fp64": 0, "fp32": 1}[precision]
+    o.eig_solver = EIG_SOLVERS[eig]
     n = ctypes.c_size_t(0)
     st = load().ctmrg_workspace_size(q, m, ctypes.byref(o), ctypes.byref(n))
     if st != CTMRG_OK:
@@ -210,7 +218,7 @@ class CTMRG:
     def __init__(self, V, K: float, m: int, bc: str = "fixed", boundary_spin: int = 0, band: int = 16,
                  gap_tol: float | None = None, rank_tol: float = 1e-13, precision: str = "fp64", stream=None,
                  eig: str = "two_stage", warm_guard: int = 0, warm_degree: int = 0, warm_tol: float = 0.0,
-                 warm_tail: str = "auto"):
+                 warm_tail: str = "auto", workspace=None):
         lib = load()
         self._lib = lib
         self.V = _f64(V)
@@ -231,6 +239,11 @@ class CTMRG:
         o.warm_degree = warm_degree
         o.warm_tol = warm_tol
         o.warm_tail = WARM_TAILS[warm_tail]
+        # workspace: a device tensor (or any object with data_ptr() and nbytes) the caller keeps alive
+        self._workspace = workspace
+        if workspace is not None:
+            o.workspace = ctypes.c_void_p(int(workspace.data_ptr()))
+            o.workspace_bytes = int(workspace.nbytes)
         h = _vp()
         st = lib.ctmrg_init(self.q, self.dim, _p(self.V), float(K), self.m, ctypes.byref(o), ctypes.byref(h))
         self._h = h
@@ -278,6 +291,23 @@ class CTMRG:
         self._check(self._lib.ctmrg_observables(self._h, ctypes.byref(o), _p(spec)))
         out = {name: getattr(o, name) for name, _ in Observables._fields_}
         out["kept_spectrum"] = spec
+        return out
+
+    def sweep(self, T, tol: float, max_steps: int, warm_start: bool = True) -> list:
+        """ctmrg_sweep over the temperatures T (one dict of observables per temperature, with
+        "T", "steps" and "converged" added)."""
+        Ts = _f64(np.atleast_1d(T))
+        n = int(Ts.size)
+        obs = (Observables * max(n, 1))()
+        steps = (ctypes.c_int * max(n, 1))()
+        conv = (ctypes.c_int * max(n, 1))()
+        self._check(self._lib.ctmrg_sweep(self._h, n, _p(Ts), float(tol), int(max_steps), 1 if warm_start else 0,
+                                          obs, steps, conv))
+        out = []
+        for i in range(n):
+            d = {name: getattr(obs[i], name) for name, _ in Observables._fields_}
+            d.update({"T": float(Ts[i]), "steps": int(steps[i]), "converged": bool(conv[i])})
+            out.append(d)
         return out
 
     def fixed_point_derivative(self, second_order: bool = False) -> dict:
