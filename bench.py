@@ -21,6 +21,8 @@ same steps.  `paths` holds all four, `roofline` the dominant kernel of the
 headline path (the products C' V, timed by HIP events around each launch),
 `two_stage_roofline` the dominant kernel of the two-stage path (the wavefront
 bulge chasing), `contraction_roofline` the largest contraction kernel,
+`kept_subspace_mixed_vs_fp64` the largest principal angle between the kept eigenvectors of
+one mixed and one FP64 step from the same state against the eigen-gap at the cut,
 `time_to_fixed_point` whole runs at m = 64 against the oracle's fixed point, and
 `cpu_baseline` the oracle's step time on the host.  Prints one JSON line.
 """
@@ -249,6 +251,44 @@ def time_to_fixed_point(V, T, m, tol, max_steps, band):
     return out
 
 
+def subspace_angle(V, K, m, band, gap_tol, warmup):
+    """The kept subspace of the mixed path against the FP64 path's, from the same FP64 state
+    (after `warmup` FP64 steps): one step of each, the largest principal angle between the
+    kept eigenvectors U (sin theta from the singular values of U_mixed^T U_fp64), the eigen-gap
+    at the cut |lambda_m_eff| - |lambda_m_eff+1| of C', and the Davis-Kahan bound
+    ||C'_mixed - C'_fp64||_2 / gap (the spectral norm bounded by the Frobenius norm)."""
+    import numpy as np
+    from paper_2004_08669_amd import ctmrg
+    a = ctmrg.CTMRG(V, K, m, band=band, gap_tol=gap_tol)
+    a.step(warmup)
+    st = a.export_state()
+    a.extend()
+    Ca = a.get("cext")
+    a.import_state(st)
+    a.step(1)
+    Ua, lam = a.get("U"), a.get("spectrum")
+    me_a = int(np.count_nonzero(a.get("omega")))
+    a.close()
+    b = ctmrg.CTMRG(V, K, m, band=band, precision="fp32", gap_tol=gap_tol)
+    b.import_state(st)
+    b.extend()
+    Cb = b.get("cext")
+    b.import_state(st)
+    b.step(1)
+    Ub = b.get("U")
+    me_b = int(np.count_nonzero(b.get("omega")))
+    b.close()
+    me = min(me_a, me_b)
+    s = np.linalg.svd(Ua[:, :me].T @ Ub[:, :me], compute_uv=False)
+    sin_max = float(np.sqrt(max(0.0, 1.0 - float(s.min()) ** 2)))
+    mags = np.sort(np.abs(lam))[::-1]
+    l1 = float(mags[0])
+    gap = float(mags[me - 1] - mags[me])
+    dC = float(np.linalg.norm(Ca - Cb))
+    return {"after_fp64_steps": warmup, "m_eff": [me_a, me_b], "sin_theta_max": sin_max,
+            "eigen_gap_rel": gap / l1, "dC_fro_rel": dC / l1, "davis_kahan_bound": dC / gap if gap > 0 else None}
+
+
 EIGEN_STAGES = ["dense_to_band", "band_to_tridiag", "bisection", "select_cut_entropy", "inverse_iteration",
                 "orthonormalize", "backtransform_band", "backtransform_dense"]
 
@@ -299,6 +339,7 @@ def main():
     ap.add_argument("--eig", choices=["both", "two_stage", "warm"], default="both",
                     help="both: the two-stage and the warm-started eigensolver (the headline is the warm one)")
     ap.add_argument("--no-fixed-point", action="store_true", help="skip the time-to-fixed-point runs (m=64)")
+    ap.add_argument("--no-subspace", action="store_true", help="skip the kept-subspace angle of mixed vs FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=128)
     ap.add_argument("--compare-eigh", action="store_true",
@@ -440,6 +481,8 @@ def main():
         out["ratios"] = ratios
     if ts:
         out["two_stage_roofline"] = bulge_roofline(ts[order[0]]["stage_ms"])
+    if "fp32" in order and "fp64" in order and not args.no_subspace:
+        out["kept_subspace_mixed_vs_fp64"] = subspace_angle(V, K, m, args.band, args.gap_tol, args.warmup)
     if not args.no_fixed_point:
         out["time_to_fixed_point"] = time_to_fixed_point(V, 0.40, 64, 1e-12, 3000, args.band)
     if not args.no_cpu_baseline:
