@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 matrix
 PEAK_HBM_GBS = 8000.0
 
 
@@ -139,13 +140,13 @@ def cpu_baseline(q_vectors, K, m_sample, m_target):
     }
 
 
-def run_path(V, K, m, band, precision, gap_tol, warmup, steps, eig="two_stage"):
+def run_path(V, K, m, band, precision, gap_tol, warmup, steps, eig="two_stage", warm_tol=0.0):
     """Warm up, then time `steps` CTMRG steps of one context; per-stage HIP-event times, and for
     the warm-started eigensolver its counters over the timed steps and the HIP-event times of
     its products C' V."""
     import torch
     from paper_2004_08669_amd import ctmrg
-    g = ctmrg.CTMRG(V, K, m, band=band, precision=precision, gap_tol=gap_tol, eig=eig)
+    g = ctmrg.CTMRG(V, K, m, band=band, precision=precision, gap_tol=gap_tol, eig=eig, warm_tol=warm_tol)
     tag = f"{precision}/{eig}"
     for i in range(warmup):
         g.step(1)
@@ -251,8 +252,8 @@ def time_to_fixed_point(V, T, m, tol, max_steps, band):
     return out
 
 
-def subspace_angle(V, K, m, band, gap_tol, warmup):
-    """The kept subspace of the mixed path against the FP64 path's, from the same FP64 state
+def subspace_angle(V, K, m, band, gap_tol, warmup, precision="fp32"):
+    """The kept subspace of a mixed path against the FP64 path's, from the same FP64 state
     (after `warmup` FP64 steps): one step of each, the largest principal angle between the
     kept eigenvectors U (sin theta from the singular values of U_mixed^T U_fp64), the eigen-gap
     at the cut |lambda_m_eff| - |lambda_m_eff+1| of C', and the Davis-Kahan bound
@@ -269,7 +270,7 @@ def subspace_angle(V, K, m, band, gap_tol, warmup):
     Ua, lam = a.get("U"), a.get("spectrum")
     me_a = int(np.count_nonzero(a.get("omega")))
     a.close()
-    b = ctmrg.CTMRG(V, K, m, band=band, precision="fp32", gap_tol=gap_tol)
+    b = ctmrg.CTMRG(V, K, m, band=band, precision=precision, gap_tol=gap_tol)
     b.import_state(st)
     b.extend()
     Cb = b.get("cext")
@@ -285,7 +286,8 @@ def subspace_angle(V, K, m, band, gap_tol, warmup):
     l1 = float(mags[0])
     gap = float(mags[me - 1] - mags[me])
     dC = float(np.linalg.norm(Ca - Cb))
-    return {"after_fp64_steps": warmup, "m_eff": [me_a, me_b], "sin_theta_max": sin_max,
+    return {"precision": precision, "gap_tol": gap_tol, "after_fp64_steps": warmup, "m_eff": [me_a, me_b],
+            "sin_theta_max": sin_max,
             "eigen_gap_rel": gap / l1, "dC_fro_rel": dC / l1, "davis_kahan_bound": dC / gap if gap > 0 else None}
 
 
@@ -340,6 +342,12 @@ def main():
                     help="both: the two-stage and the warm-started eigensolver (the headline is the warm one)")
     ap.add_argument("--no-fixed-point", action="store_true", help="skip the time-to-fixed-point runs (m=64)")
     ap.add_argument("--no-subspace", action="store_true", help="skip the kept-subspace angle of mixed vs FP64")
+    ap.add_argument("--warm-tol", type=float, default=0.0,
+                    help="residual tolerance of the warm-started solver on the mixed paths (0: the library default)")
+    ap.add_argument("--no-bf16x3", action="store_true",
+                    help="skip the split-bf16 path (contractions as three bf16 products, warm-started eigensolver)")
+    ap.add_argument("--gap-tol-bf16x3", type=float, default=1e-4,
+                    help="multiplet gap of the cut on the split-bf16 path (its rounding splits multiplets by ~1e-6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=128)
     ap.add_argument("--compare-eigh", action="store_true",
@@ -365,7 +373,12 @@ def main():
             ts[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps)
     if args.eig != "two_stage":
         for prec in order:
-            wm[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps, eig="warm")
+            wm[prec] = run_path(V, K, m, args.band, prec, args.gap_tol, args.warmup, args.steps, eig="warm",
+                                warm_tol=args.warm_tol if prec != "fp64" else 0.0)
+    x3 = None
+    if not args.no_bf16x3 and args.eig != "two_stage" and "fp32" in order:
+        x3 = run_path(V, K, m, args.band, "bf16x3", args.gap_tol_bf16x3, args.warmup, args.steps, eig="warm",
+                      warm_tol=args.warm_tol)
     # the headline: the mixed path (the first precision) with the warm-started eigensolver when it ran
     head_eig = "warm" if wm else "two_stage"
     head_prec = order[0]
@@ -441,6 +454,7 @@ def main():
             "workload": (f"CTMRG step, q=20 dodecahedron, m={m} (C' {q * m}x{q * m}), T={args.T}, fixed boundary, "
                          f"{desc[head_prec]}, {edesc[head_eig]}"),
             "q": q, "m": m, "T": args.T, "precision": head_prec, "band": args.band, "gap_tol": args.gap_tol,
+            "warm_tol": args.warm_tol if args.warm_tol > 0 else "default",
             "eigensolver": head_eig,
         },
         "roofline": roofline,
@@ -466,6 +480,28 @@ def main():
                     ent["speedup_vs_two_stage"] = r["steps_per_s"] / ts[prec]["steps_per_s"]
                     ent["vs_two_stage_after_run"] = after_run(r["obs"], ts[prec]["obs"])
             paths[f"{prec}_{solver}"] = ent
+    if x3 is not None:
+        ent = {"steps_per_s": x3["steps_per_s"], "ms_per_step": x3["ms_per_step"], "gap_tol": args.gap_tol_bf16x3,
+               "stages_ms": {k: round(v, 4) for k, v in x3["stage_ms"].items() if v > 0}}
+        ent.update({k: x3["warm"][k] for k in ("fallback_steps", "warm_steps", "fallback_rate", "passes_per_step",
+                                               "products_per_step", "exact_tail_steps", "last_residual")})
+        if "fp32" in wm:
+            ent["speedup_vs_fp32_warm"] = x3["steps_per_s"] / wm["fp32"]["steps_per_s"]
+        if "fp64" in ts:
+            ent["vs_fp64_two_stage_after_run"] = after_run(x3["obs"], ts["fp64"]["obs"])
+        # the split-bf16 contractions against the bf16 matrix-core peak (three bf16 products per
+        # algorithmic multiply-add) and as FP32-equivalent rates against the FP32 peak
+        xs = x3["stage_ms"]
+        ent["contraction_roofline"] = {
+            "peak_bf16_tflops": PEAK_BF16_TFLOPS,
+            "bf16_mfma_frac": {k: round(3.0 * flops[k] / (xs[k] * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4)
+                               for k in kernel_stages if xs.get(k, 0) > 0},
+            "fp32_equivalent_tflops": {k: round(flops[k] / (xs[k] * 1e-3) / 1e12, 2)
+                                       for k in kernel_stages if xs.get(k, 0) > 0},
+            "fp32_path_tflops": {k: round(flops[k] / (stage_ms[k] * 1e-3) / 1e12, 2)
+                                 for k in kernel_stages if stage_ms.get(k, 0) > 0} if head_prec == "fp32" else None,
+        }
+        paths["bf16x3_warm"] = ent
     out["paths"] = paths
     if "fp64" in ts and head_prec != "fp64":
         # the plain FP64 path: FP64 contractions and the two-stage eigensolver; all paths ran the same
@@ -483,6 +519,9 @@ def main():
         out["two_stage_roofline"] = bulge_roofline(ts[order[0]]["stage_ms"])
     if "fp32" in order and "fp64" in order and not args.no_subspace:
         out["kept_subspace_mixed_vs_fp64"] = subspace_angle(V, K, m, args.band, args.gap_tol, args.warmup)
+        if x3 is not None:
+            out["kept_subspace_bf16x3_vs_fp64"] = subspace_angle(V, K, m, args.band, args.gap_tol_bf16x3,
+                                                                 args.warmup, precision="bf16x3")
     if not args.no_fixed_point:
         out["time_to_fixed_point"] = time_to_fixed_point(V, 0.40, 64, 1e-12, 3000, args.band)
     if not args.no_cpu_baseline:

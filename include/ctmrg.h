@@ -65,8 +65,21 @@ typedef enum {
  *     FP64 with the factor restored.  The state, the eigensolver, the cut, all
  *     normalizations, the log bookkeeping and the observables stay FP64.  The
  *     contraction error is ~1e-7 relative to max|C'|, which also splits
- *     multiplets of C' by that much: use gap_tol >= 1e-6 on this path. */
-typedef enum { CTMRG_FP64 = 0, CTMRG_FP32 = 1 } ctmrg_precision;
+ *     multiplets of C' by that much: use gap_tol >= 1e-6 on this path.
+ *   CTMRG_BF16X3: the mixed path with the same FP32 operands, each split into
+ *     two bf16 parts (hi = bf16(x), lo = bf16(x - hi), round to nearest even),
+ *     and every product taken as hi*hi + hi*lo + lo*hi on the bf16 matrix cores
+ *     with FP32 accumulation (the three-term split of Henry, Tang and
+ *     Heinecke, ARITH 2019).  The dropped lo*lo term and the rounding of the lo
+ *     parts leave a relative error of order 2^-18 per product (2^-16 at
+ *     most), so the contraction error is about ten times CTMRG_FP32's (about
+ *     5e-6 of max|C'|) and f, E and M reach 1e-5 rather than 1e-6.  Its
+ *     rounding splits multiplets of C' by up to about 5e-6 |lambda_1|: a
+ *     gap_tol of 1e-5 or more recognizes them where the gaps at the cut are
+ *     wider (at q = 20, m = 512, T = 0.4398 they are about 2e-6 |lambda_1|,
+ *     below this path's resolution, and a wide gap_tol there merges the whole
+ *     tail into one cluster and cuts far below m). */
+typedef enum { CTMRG_FP64 = 0, CTMRG_FP32 = 1, CTMRG_BF16X3 = 2 } ctmrg_precision;
 typedef enum { CTMRG_BC_FIXED = 0, CTMRG_BC_FREE = 1 } ctmrg_bc;
 
 /* Eigensolver of step 3.
@@ -170,14 +183,22 @@ ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *ctx, double tol, int max_steps,
 /* A sweep over temperatures, the scans of Sec. IV (for one cutoff m: a (T, m) grid is one
  * context per m).  For each T[i] in order: K = 1/T[i]; the state restarts from the boundary
  * (warm_start = 0; as ctmrg_set_K) or is kept from the previous temperature's fixed point
- * (warm_start = 1, from the second temperature on; W is rebuilt); at least two and at most
+ * (warm_start = 1; W is rebuilt; for T[0], the state the context holds, so that a sweep can be
+ * continued by further calls, or the boundary if the context has taken no step since init or
+ * ctmrg_set_K); at least two and at most
  * max_steps steps until Delta < tol; then out[i] = ctmrg_observables (M, S_E, xi_e, f, E, ...).
  * steps_out[i] and converged[i] (both nullable) receive the steps taken and whether Delta < tol
  * was reached; a temperature that does not converge is reported and the sweep continues.
+ * deriv_out (nullable, n entries; declared below): at every temperature whose run converged
+ * (to Delta < min(tol, 1e-6)), deriv_out[i] = ctmrg_fixed_point_derivative with
+ * second_order = 1 (dF/dK, d2F/dK2 = dE/dK and dM/dK along the fixed point); zeros elsewhere.
  * Errors: CTMRG_E_INVALID_ARG (n < 0, a temperature not positive, max_steps < 2, tol < 0),
- * and those of ctmrg_step and ctmrg_observables, which stop the sweep. */
+ * and those of ctmrg_step, ctmrg_observables and ctmrg_fixed_point_derivative, which stop the
+ * sweep. */
+struct ctmrg_derivative_s;
 ctmrg_status ctmrg_sweep(ctmrg_ctx *ctx, int n, const double *T, double tol, int max_steps, int warm_start,
-                         ctmrg_observables_t *out, int *steps_out, int *converged);
+                         ctmrg_observables_t *out, int *steps_out, int *converged,
+                         struct ctmrg_derivative_s *deriv_out);
 
 /* Observables of the current state (Sec. II: Eqs. 3-6 on the fixed-point
  * matrices; the free energy from the normalization history).  Needs >= 1 step
@@ -204,10 +225,18 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *ctx, ctmrg_observables_t *out, double 
  * the fixed point.  The iteration stops when the tangent changes by less than
  * 1e-12, or when ds (hence dF/dK) changes by less than 1e-14 relative over two
  * consecutive windows of ten iterations (slowly converging directions that do
- * not move F; tangent_change reports the rest).  With second_order != 0 the
- * second derivative is the
- * central difference of dF/dK at K (1 +- 1e-4), each from its own converged
- * fixed point.  The context's state, K and weight are left unchanged; work
+ * not move F; tangent_change reports the rest).
+ * Along the converged tangent the routine also differentiates the impurity
+ * energy E of the plaquette (Sec. II; the product rule through the
+ * environment sums, with dW/dK = -W h4) and the magnetization M (Eq. 5; the
+ * spin weights of U Omega^4 U^T with the tangents of U and of the corner
+ * block): dE_dK and dM_dK are always filled.  dF/dK equals E at every fixed
+ * point (the CTMRG free energy is stationary in the environment; E and dF_dK
+ * agree to the convergence of the fixed point), so d2F/dK2 = dE/dK:
+ * second_order == 1 returns it as d2F_dK2 (no further fixed point);
+ * second_order == 2 returns instead the central difference of dF/dK at
+ * K (1 +- 1e-4), each from its own converged fixed point (a cross-check, three
+ * tangent solves).  The context's state, K and weight are left unchanged; work
  * memory (about 16 (q m_eff)^2 doubles plus a full eigensolver workspace) is
  * allocated on the first call and kept until ctmrg_destroy.  Runs in FP64
  * whatever the context's precision.
@@ -215,26 +244,29 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *ctx, ctmrg_observables_t *out, double 
  * if the aligned fixed point or the tangent iteration does not converge;
  * CTMRG_E_NUMERICAL if the kept dimension changes or a multiplet is larger
  * than 8. */
-typedef struct {
+typedef struct ctmrg_derivative_s {
     double F;              /* beta f = -1/2 ln ||P~||_F at the aligned fixed point           */
     double dF_dK;          /* dF/dK, the energy per site                                      */
-    double d2F_dK2;        /* d2F/dK2 (second_order only; else 0)                             */
+    double d2F_dK2;        /* d2F/dK2 (second_order 1: dE/dK; 2: central difference; 0: 0)     */
     double gauge_residual; /* max |P_next - P| of the aligned fixed point                     */
     double tangent_change; /* max change of the tangent in its last iteration                 */
     int aligned_steps;     /* FP64 steps taken to the aligned fixed point                     */
     int iterations;        /* tangent iterations                                              */
     int n_eigen;           /* eigenpairs of C' used (those above rank_tol |lambda_1|)          */
+    double E;              /* impurity energy of the plaquette at the aligned fixed point      */
+    double M;              /* magnetization (Eq. 5) at the aligned fixed point                 */
+    double dE_dK;          /* total derivative of E along the fixed point (= d2F/dK2)          */
+    double dM_dK;          /* total derivative of M along the fixed point                      */
 } ctmrg_derivative_t;
 
 ctmrg_status ctmrg_fixed_point_derivative(ctmrg_ctx *ctx, int second_order, ctmrg_derivative_t *out);
 
 /* Backward pass for the observables (f, E, M) of the fixed point as functions
- * of K: *K_bar = obs_bar[0] df/dK + obs_bar[1] dE/dK, with f = F/K and E = dF/dK
- * (the derivative form of the energy, which equals the impurity energy of
- * ctmrg_observables at the fixed point).  dE/dK = d2F/dK2 is computed only when
- * obs_bar[1] != 0 or d2F_dK2 is non-NULL.  The derivative of M is not available:
- * obs_bar[2] must be 0 (else CTMRG_E_UNSUPPORTED).  Same requirements and
- * errors as ctmrg_fixed_point_derivative. */
+ * of K: *K_bar = obs_bar[0] df/dK + obs_bar[1] dE/dK + obs_bar[2] dM/dK, with
+ * f = F/K, dE/dK = d2F/dK2 and dM/dK from one call of
+ * ctmrg_fixed_point_derivative (second_order 1); *d2F_dK2 (if non-NULL)
+ * receives d2F/dK2.  Same requirements and errors as
+ * ctmrg_fixed_point_derivative. */
 ctmrg_status ctmrg_backward(ctmrg_ctx *ctx, const double obs_bar[3], double *K_bar, double *d2F_dK2);
 
 /* Checkpoint of the state (P, Omega, the normalization history, step count).

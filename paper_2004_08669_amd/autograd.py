@@ -2,8 +2,8 @@
 
 The forward pass runs the library to its fixed point; the backward pass calls
 ctmrg_backward (implicit differentiation through the fixed point, see
-include/ctmrg.h).  Torch only carries the scalars; all work runs in the library.
-The derivative of M is not available, so M may not enter a differentiated loss.
+include/ctmrg.h), which gives df/dK, dE/dK = d2F/dK2 and dM/dK from one tangent
+solve.  Torch only carries the scalars; all work runs in the library.
 """
 from __future__ import annotations
 
@@ -24,9 +24,7 @@ class CTMRGFixedPoint(torch.autograd.Function):
             raise ctmrg.CTMRGError(4, f"no fixed point after {steps} steps (Delta {delta:.3e})")
         o = g.observables()
         ctx.g = g
-        out = [torch.tensor(o[k], dtype=torch.float64) for k in ("f", "E", "M")]
-        ctx.mark_non_differentiable(out[2])
-        return tuple(out)
+        return tuple(torch.tensor(o[k], dtype=torch.float64) for k in ("f", "E", "M"))
 
     @staticmethod
     def backward(ctx, grad_f, grad_E, grad_M):
@@ -34,7 +32,7 @@ class CTMRGFixedPoint(torch.autograd.Function):
         try:
             bar = [float(grad_f) if grad_f is not None else 0.0,
                    float(grad_E) if grad_E is not None else 0.0,
-                   0.0]
+                   float(grad_M) if grad_M is not None else 0.0]
             kb, _ = g.backward(bar)
         finally:
             g.close()

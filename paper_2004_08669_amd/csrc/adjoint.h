@@ -21,6 +21,22 @@
 // gauge: FP64 steps whose kept eigenvectors are rotated inside each multiplet
 // to best match the previous step's (orthogonal Procrustes), until P repeats
 // element by element.
+//
+// Observables along the tangent.  With X = A^T Omega A in the block layout
+// (X_{s sg} = P_s Omega P_sg), G = Om~ X Om~ (Om~ = diag(Omega, ..., Omega)),
+// C' = W-mix(X) and C'_h = (W h4)-mix(X), the impurity energy of the
+// plaquette (Sec. II) is E = 1/2 <G, C'_h> / <G, C'> (Frobenius products).
+// Its total derivative along the fixed point, dE/dK = d_K E + d_x E . t,
+// follows from the product rule with dW/dK = -W h4 and d(W h4)/dK = -W h4^2:
+//   d<G, C'> = 2 <Om~ X dOm~, C'> + <Om~ dX Om~, C'> + <G, dC'>
+// (X, C' and dOm~ symmetric), and the same with C'_h.  Since dF/dK equals E
+// at every fixed point (the stationarity of the CTMRG free energy; checked by
+// the tests to the convergence of the fixed point), d2F/dK2 = dE/dK exactly.
+// The magnetization (Eq. 5) weighs the spins by
+// prob_s = sum_b (U Omega^4 U^T)[(s,b),(s,b)]; with the corner's tangent a full
+// symmetric block dOm, d(Omega^4)[j][k] = dOm[j][k] (w_j^3 + w_j^2 w_k +
+// w_j w_k^2 + w_k^3), and
+//   d prob_s = sum_b [2 (dU Omega^4 U^T) + U d(Omega^4) U^T][(s,b),(s,b)].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,6 +54,8 @@ struct AdjInputs {
     const double *A = nullptr;        // m x (q m) state (padded), omega (m), last kept U ((q m) x m)
     const double *omega = nullptr;
     const double *U = nullptr;
+    const double *V = nullptr;        // spin vectors (q x dim), for M
+    int dim = 0, bc = 0, s0 = 0;      // boundary condition and the boundary spin, for M
     double gap_tol = 1e-10, rank_tol = 1e-13;
     int max_aligned_steps = 500, max_iterations = 3000;
     double gauge_tol = 1e-10;         // element-wise |P_next - P| of the aligned fixed point
@@ -53,6 +71,8 @@ struct AdjResult {
     int aligned_steps = 0;
     int iterations = 0;
     int n_eigen = 0;           // eigenpairs of C'* used (its rank)
+    double E = 0.0, dEdK = 0.0;  // impurity energy at the aligned fixed point and its total derivative
+    double M = 0.0, dMdK = 0.0;  // magnetization (Eq. 5) and its total derivative
 };
 
 struct AdjWork {
@@ -65,6 +85,7 @@ struct AdjWork {
     double *dX = nullptr, *dC = nullptr, *dY = nullptr, *dZ = nullptr, *dPt = nullptr;
     double *T1 = nullptr, *Bm = nullptr, *R = nullptr, *dU = nullptr;
     double *part = nullptr, *scal = nullptr, *hscal = nullptr;
+    double *W2 = nullptr, *obsv = nullptr, *hobsv = nullptr;  // W h4^2 (q^4); prob, d prob (device, host)
     PostOut *post = nullptr, *hpost = nullptr;
     unsigned *err = nullptr;
     EigWork eig;

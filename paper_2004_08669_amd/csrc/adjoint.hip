@@ -16,9 +16,10 @@ namespace ctm {
 namespace {
 
 constexpr int KB = 8;        // largest multiplet the alignment handles
-constexpr int NSCAL = 16;    // device scalars: 0 s*, 1 dn_C/n_C^3-scaled, 2 ds, 3 tangent change, 5 gauge residual
+constexpr int NSCAL = 16;    // device scalars: 0 s*, 1 dn_C/n_C^3-scaled, 2 ds, 3 tangent change, 5 gauge residual,
+                             // 6 .. 14 the Frobenius products of the energy's tangent
 
-enum { S_NORM = 0, S_DNC = 1, S_DS = 2, S_CHANGE = 3, S_GAUGE = 5 };
+enum { S_NORM = 0, S_DNC = 1, S_DS = 2, S_CHANGE = 3, S_GAUGE = 5, S_OBS = 6 };
 enum { OP_SUM = 0, OP_SQRT = 1, OP_MAX = 2, OP_MAX_ACC = 3 };
 
 int grid_for(long n) { return (int)std::max<long>(1, std::min<long>(1024, (n + 255) / 256)); }
@@ -264,6 +265,66 @@ __global__ void tangent_norm_kernel(const double *dPt, const double *Pt, long to
         dA[i] = dPt[i] / sv - Pt[i] * dsv / (sv * sv);
 }
 
+// W2 = W h4^2 = (W h4)^2 / W (W > 0)
+__global__ void weight_h2_kernel(const double *W, const double *WH, double *W2, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        W2[i] = WH[i] * WH[i] / W[i];
+}
+
+// Partial sums of sum_{r,c} w_{r mod d} [w_{c mod d}] M[r][c] C[r][c] over an n x n pair (both = the
+// product <Om~ M Om~, C>; else <Om~ M, C>), one per workgroup.
+__global__ void __launch_bounds__(256) wdot_partial_kernel(const double *M, const double *C, const double *om, int n,
+                                                           int d, int both, double *part)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int r = blockIdx.x; r < n; r += gridDim.x) {
+        const double wr = om[r % d];
+        const double *mr = M + (long)r * n, *cr = C + (long)r * n;
+        double a = 0.0;
+        for (int c = threadIdx.x; c < n; c += 256) a += (both ? om[c % d] : 1.0) * mr[c] * cr[c];
+        acc += wr * a;
+    }
+    acc = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// D4[j][k] = dOm[j][k] (w_j^3 + w_j^2 w_k + w_j w_k^2 + w_k^3): the derivative of Omega^4 along dOm
+__global__ void omega4_tangent_kernel(const double *dOm, const double *om, int d, double *D4)
+{
+    const long total = (long)d * d;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / d), k = (int)(idx - (long)j * d);
+        const double a = om[j], b = om[k];
+        D4[idx] = dOm[idx] * (a * a * a + a * a * b + a * b * b + b * b * b);
+    }
+}
+
+// One workgroup per spin s: out[s] = prob_s = sum_{b,j} U[(s,b),j]^2 w_j^4 and
+// out[q + s] = sum_{b,j} U[(s,b),j] (2 dU[(s,b),j] w_j^4 + V1[(s,b),j]), with V1 = U D4.
+__global__ void __launch_bounds__(256) spin_tangent_kernel(const double *U, const double *dU, const double *V1,
+                                                           const double *om, int q, int d, double *out)
+{
+    __shared__ double red[4];
+    const int s = blockIdx.x;
+    double p = 0.0, dp = 0.0;
+    const long total = (long)d * d;
+    for (long idx = threadIdx.x; idx < total; idx += 256) {
+        const int b = (int)(idx / d), j = (int)(idx - (long)b * d);
+        const long at = (long)(s * d + b) * d + j;
+        const double w = om[j], w4 = (w * w) * (w * w), u = U[at];
+        p += u * u * w4;
+        dp += u * (2.0 * dU[at] * w4 + V1[at]);
+    }
+    p = block_sum<256>(p, red);
+    dp = block_sum<256>(dp, red);
+    if (threadIdx.x == 0) {
+        out[s] = p;
+        out[q + s] = dp;
+    }
+}
+
 // ---------------------------------------------------------------- host helpers
 
 hipError_t reduce_dot(const double *x, const double *y, long n, double *part, double *out, int op, double scale,
@@ -280,6 +341,16 @@ hipError_t reduce_maxdiff(const double *x, const double *y, long n, double *part
     const int np = grid_for(n);
     hipLaunchKernelGGL(maxdiff_partial_kernel, dim3(np), dim3(256), 0, s, x, y, n, part);
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, part, np, out, acc ? OP_MAX_ACC : OP_MAX, 1.0);
+    return hipGetLastError();
+}
+
+// *out = <Om~ M Om~, C> (both) or <Om~ M, C> over n x n matrices
+hipError_t reduce_wdot(const double *M, const double *C, const double *om, int n, int d, bool both, double *part,
+                       double *out, hipStream_t s)
+{
+    const int np = std::min(n, 1024);
+    hipLaunchKernelGGL(wdot_partial_kernel, dim3(np), dim3(256), 0, s, M, C, om, n, d, both ? 1 : 0, part);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, part, np, out, OP_SUM, 1.0);
     return hipGetLastError();
 }
 
@@ -320,7 +391,7 @@ std::vector<AdjReq> adj_requests(AdjWork &w, int q, int d)
         {&w.dA, dd * n}, {&w.dAn, dd * n}, {&w.dOA, dd * n}, {&w.dom, dd * dd}, {&w.domn, dd * dd},
         {&w.dX, n * n}, {&w.dC, n * n}, {&w.dY, n * n}, {&w.dZ, n * n}, {&w.dPt, dd * n},
         {&w.T1, n * dd}, {&w.Bm, n * dd}, {&w.R, n * dd}, {&w.dU, n * dd},
-        {&w.part, 1024}, {&w.scal, NSCAL + n + 8},
+        {&w.part, 1024}, {&w.scal, NSCAL + n + 8}, {&w.W2, (size_t)q * q * q * q}, {&w.obsv, 4 * (size_t)q + 8},
     };
 }
 
@@ -349,6 +420,7 @@ hipError_t adj_alloc(AdjWork &w, int q, int d, int band)
     hipError_t e = hipMalloc((void **)&w.post, sizeof(PostOut));
     if (e == hipSuccess) e = hipHostMalloc((void **)&w.hpost, sizeof(PostOut), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w.hscal, sizeof(double) * NSCAL, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&w.hobsv, sizeof(double) * (4 * (size_t)q + 8), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void **)&w.err, sizeof(unsigned) * 4);
     if (e == hipSuccess) e = eig_alloc(w.eig, w.n, w.n, band);
     if (e == hipSuccess) e = hipMemset(w.zero, 0, sizeof(double) * (n + 8));
@@ -359,12 +431,13 @@ void adj_free(AdjWork &w)
 {
     double *bufs[] = {w.A, w.OA, w.Pt, w.om, w.omn, w.zero, w.Ucur, w.Uprev, w.Mov, w.X, w.C, w.Y, w.Z, w.Cb,
                       w.Zb, w.Uall, w.M3, w.lam, w.sel, w.dA, w.dAn, w.dOA, w.dom, w.domn, w.dX, w.dC, w.dY, w.dZ,
-                      w.dPt, w.T1, w.Bm, w.R, w.dU, w.part, w.scal};
+                      w.dPt, w.T1, w.Bm, w.R, w.dU, w.part, w.scal, w.W2, w.obsv};
     for (double *p : bufs)
         if (p) (void)hipFree(p);
     if (w.post) (void)hipFree(w.post);
     if (w.hpost) (void)hipHostFree(w.hpost);
     if (w.hscal) (void)hipHostFree(w.hscal);
+    if (w.hobsv) (void)hipHostFree(w.hobsv);
     if (w.err) (void)hipFree(w.err);
     eig_free(w.eig);
     const int band = w.band;
@@ -506,30 +579,41 @@ int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s,
     double change = INFINITY, ds = 0.0, ds_prev[2] = {NAN, NAN};
     bool functional_converged = false;
     int it = 0;
-    for (it = 0; it < in.max_iterations; ++it) {
+#define TF_CK(expr)                          \
+    do {                                     \
+        hipError_t e3 = (expr);              \
+        if (e3 != hipSuccess) return e3;     \
+    } while (0)
+    // The front of one tangent step from (dA, dOm): dX, dC', the eigen part (dOm of the
+    // next state in domn, dU)
+    auto tangent_front = [&]() -> hipError_t {
         // dOA = dOmega A + Omega dA (dOmega: the full symmetric corner tangent)
         hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(nd)), dim3(256), 0, s, w.om, w.dA, d, (long)n, w.dOA);
-        ADJ_CK(gemm_mfma(GEMM_SMALL, A_RM{w.dom, d}, B_RM{w.A, n}, EpiAxpby{w.dOA, n, 1.0, 1.0}, d, n, d, s));
+        TF_CK(gemm_mfma(GEMM_SMALL, A_RM{w.dom, d}, B_RM{w.A, n}, EpiAxpby{w.dOA, n, 1.0, 1.0}, d, n, d, s));
         // dX = dA^T (Omega A) + A^T (dOmega A + Omega dA)
-        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.dA, n}, B_RM{w.OA, n}, EpiStore{w.dX, n, 1.0}, n, n, d, s));
-        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.A, n}, B_RM{w.dOA, n}, EpiAxpby{w.dX, n, 1.0, 1.0}, n, n, d, s));
+        TF_CK(gemm_mfma(GEMM_LARGE, A_T{w.dA, n}, B_RM{w.OA, n}, EpiStore{w.dX, n, 1.0}, n, n, d, s));
+        TF_CK(gemm_mfma(GEMM_LARGE, A_T{w.A, n}, B_RM{w.dOA, n}, EpiAxpby{w.dX, n, 1.0, 1.0}, n, n, d, s));
         // dC' = W-mix(dX) + W'-mix(X*)
-        ADJ_CK(weight_mix(in.W, w.dX, w.dC, q, d, s));
+        TF_CK(weight_mix(in.W, w.dX, w.dC, q, d, s));
         hipLaunchKernelGGL(axpy_kernel, dim3(grid_for((long)n * n)), dim3(256), 0, s, w.dC, w.Cb, (long)n * n);
         // eigenvector and eigenvalue derivatives
-        ADJ_CK(gemm_mfma(GEMM_TALL, A_RM{w.dC, n}, B_RM{w.Ucur, d}, EpiStore{w.T1, d, 1.0}, n, d, n, s));
-        ADJ_CK(gemm_mfma(GEMM_TALL, A_T{w.Uall, n}, B_RM{w.T1, d}, EpiStore{w.Bm, d, 1.0}, np, d, n, s));
+        TF_CK(gemm_mfma(GEMM_TALL, A_RM{w.dC, n}, B_RM{w.Ucur, d}, EpiStore{w.T1, d, 1.0}, n, d, n, s));
+        TF_CK(gemm_mfma(GEMM_TALL, A_T{w.Uall, n}, B_RM{w.T1, d}, EpiStore{w.Bm, d, 1.0}, np, d, n, s));
         if (np < n) {
-            ADJ_CK(copy2d(w.T1, d, w.R, d, n, d, s));
-            ADJ_CK(gemm_mfma(GEMM_TALL, A_RM{w.Uall, n}, B_RM{w.Bm, d}, EpiAxpby{w.R, d, -1.0, 1.0}, n, d, np, s));
+            TF_CK(copy2d(w.T1, d, w.R, d, n, d, s));
+            TF_CK(gemm_mfma(GEMM_TALL, A_RM{w.Uall, n}, B_RM{w.Bm, d}, EpiAxpby{w.R, d, -1.0, 1.0}, n, d, np, s));
         }
-        ADJ_CK(reduce_dot(w.M3, w.dC, (long)n * n, w.part, w.scal + S_DNC, OP_SUM, 1.0 / (nC * nC * nC), s));
+        TF_CK(reduce_dot(w.M3, w.dC, (long)n * n, w.part, w.scal + S_DNC, OP_SUM, 1.0 / (nC * nC * nC), s));
         hipLaunchKernelGGL(eigen_tangent_kernel, dim3(grid_for((long)np * d)), dim3(256), 0, s, w.Bm, np, d, w.lam,
                            nC, w.scal + S_DNC, w.domn);
-        ADJ_CK(gemm_mfma(GEMM_TALL, A_RM{w.Uall, n}, B_RM{w.Bm, d}, EpiStore{w.dU, d, 1.0}, n, d, np, s));
+        TF_CK(gemm_mfma(GEMM_TALL, A_RM{w.Uall, n}, B_RM{w.Bm, d}, EpiStore{w.dU, d, 1.0}, n, d, np, s));
         if (np < n)
             hipLaunchKernelGGL(nullspace_tangent_kernel, dim3(grid_for((long)n * d)), dim3(256), 0, s, w.dU, w.R,
                                (long)n, d, w.lam);
+        return hipSuccess;
+    };
+    for (it = 0; it < in.max_iterations; ++it) {
+        ADJ_CK(tangent_front());
         // dY = dA^T U + A^T dU,  dZ = W-mix(dY) + W'-mix(Y*),  dP~ = dU^T Z* + U^T dZ
         ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.dA, n}, B_Ublk{w.Ucur, d}, EpiStore{w.dY, n, 1.0}, n, n, d, s));
         ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.A, n}, B_Ublk{w.dU, d}, EpiAxpby{w.dY, n, 1.0, 1.0}, n, n, d, s));
@@ -572,7 +656,78 @@ int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s,
         *msg = "the tangent iteration did not converge (change " + std::to_string(change) + ")";
         return CTMRG_E_NOT_CONVERGED;
     }
+
+    // ---- 4. E and M at x* and their derivatives along the converged tangent (dK = 1)
+    ADJ_CK(tangent_front());  // dX, dC', domn and dU of the final (dA, dOm)
+    // C' (into Z, free now), Om~ X dOm~ (as X reshaped to (q n) x d times dOm, into dY),
+    // (W h4^2)-mix(X) (into dZ) and (W h4)-mix(dX) (into Zb)
+    ADJ_CK(weight_mix(in.W, w.X, w.Z, q, d, s));
+    ADJ_CK(gemm_mfma(GEMM_TALL, A_RM{w.X, d}, B_RM{w.dom, d}, EpiStore{w.dY, d, 1.0}, n * q, d, d, s));
+    hipLaunchKernelGGL(weight_h2_kernel, dim3(grid_for((long)q2 * q2)), dim3(256), 0, s, in.W, in.WH, w.W2,
+                       (long)q2 * q2);
+    ADJ_CK(hipGetLastError());
+    ADJ_CK(weight_mix(w.W2, w.X, w.dZ, q, d, s));
+    ADJ_CK(weight_mix(in.WH, w.dX, w.Zb, q, d, s));
+    // slots: 6 <G,C'>  7 <G,Cb>  8 <Om~X dOm~,C'>  9 <Om~ dX Om~,C'>  10 <G,dC'>
+    //        11 <Om~X dOm~,Cb>  12 <Om~ dX Om~,Cb>  13 <G,(W h4)-mix(dX)>  14 <G,(W h4^2)-mix(X)>
+    // (Cb = -(W h4)-mix(X))
+    double *sc = w.scal + S_OBS;
+    ADJ_CK(reduce_wdot(w.X, w.Z, w.om, n, d, true, w.part, sc + 0, s));
+    ADJ_CK(reduce_wdot(w.X, w.Cb, w.om, n, d, true, w.part, sc + 1, s));
+    ADJ_CK(reduce_wdot(w.dY, w.Z, w.om, n, d, false, w.part, sc + 2, s));
+    ADJ_CK(reduce_wdot(w.dX, w.Z, w.om, n, d, true, w.part, sc + 3, s));
+    ADJ_CK(reduce_wdot(w.X, w.dC, w.om, n, d, true, w.part, sc + 4, s));
+    ADJ_CK(reduce_wdot(w.dY, w.Cb, w.om, n, d, false, w.part, sc + 5, s));
+    ADJ_CK(reduce_wdot(w.dX, w.Cb, w.om, n, d, true, w.part, sc + 6, s));
+    ADJ_CK(reduce_wdot(w.X, w.Zb, w.om, n, d, true, w.part, sc + 7, s));
+    ADJ_CK(reduce_wdot(w.X, w.dZ, w.om, n, d, true, w.part, sc + 8, s));
+    // M: prob_s and d prob_s from U*, dU and d(Omega^4) (the next state's corner tangent domn)
+    hipLaunchKernelGGL(omega4_tangent_kernel, dim3(grid_for((long)d * d)), dim3(256), 0, s, w.domn, w.om, d, w.Bm);
+    ADJ_CK(hipGetLastError());
+    ADJ_CK(gemm_mfma(GEMM_TALL, A_RM{w.Ucur, d}, B_RM{w.Bm, d}, EpiStore{w.T1, d, 1.0}, n, d, d, s));
+    hipLaunchKernelGGL(spin_tangent_kernel, dim3(q), dim3(256), 0, s, w.Ucur, w.dU, w.T1, w.om, q, d, w.obsv);
+    ADJ_CK(hipGetLastError());
+    ADJ_CK(hipMemcpyAsync(w.hobsv, w.obsv, sizeof(double) * 2 * q, hipMemcpyDeviceToHost, s));
+    ADJ_CK(fetch_scal());
+    {
+        const double *h = w.hscal + S_OBS;
+        const double Zd = h[0], ZH = -h[1];
+        const double dZd = 2.0 * h[2] + h[3] + h[4];
+        const double dZH = -2.0 * h[5] - h[6] + h[7] - h[8];
+        res->E = 0.5 * ZH / Zd;
+        res->dEdK = 0.5 * (dZH / Zd - ZH * dZd / (Zd * Zd));
+        const double *prob = w.hobsv, *dprob = w.hobsv + q;
+        double ps = 0.0, dps = 0.0, mn = 0.0, dmn = 0.0, v[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
+        std::vector<double> hv((size_t)q * std::max(in.dim, 1), 0.0);
+        if (in.V && in.dim > 0) ADJ_CK(hipMemcpy(hv.data(), in.V, sizeof(double) * q * in.dim, hipMemcpyDeviceToHost));
+        for (int sp = 0; sp < q; ++sp) {
+            ps += prob[sp];
+            dps += dprob[sp];
+            double dot = 0.0;
+            for (int x = 0; x < in.dim; ++x) dot += hv[(size_t)in.s0 * in.dim + x] * hv[(size_t)sp * in.dim + x];
+            mn += prob[sp] * dot;
+            dmn += dprob[sp] * dot;
+            for (int x = 0; x < std::min(in.dim, 3); ++x) {
+                v[x] += prob[sp] * hv[(size_t)sp * in.dim + x];
+                dv[x] += dprob[sp] * hv[(size_t)sp * in.dim + x];
+            }
+        }
+        if (in.bc == 0) {
+            res->M = mn / ps;
+            res->dMdK = (dmn * ps - mn * dps) / (ps * ps);
+        } else {
+            const double nv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const double dnv = nv > 0.0 ? (v[0] * dv[0] + v[1] * dv[1] + v[2] * dv[2]) / nv : 0.0;
+            res->M = nv / ps;
+            res->dMdK = (dnv * ps - nv * dps) / (ps * ps);
+        }
+        if (!std::isfinite(res->dEdK) || !std::isfinite(res->dMdK)) {
+            *msg = "non-finite derivative of E or M";
+            return CTMRG_E_NUMERICAL;
+        }
+    }
     return CTMRG_OK;
+#undef TF_CK
 #undef ADJ_CK
 }
 

@@ -31,18 +31,20 @@ hipError_t halfrow_products(const double *A, const double *U, double *Y, int q, 
 // P~ = U^T Z; work (nullable, work_elems doubles) holds split-K partials.
 hipError_t projection(const double *U, const double *Z, double *Pt, int q, int m, double *work, size_t work_elems,
                       hipStream_t s);
-// Mixed precision (FP32 operands and accumulation on the FP32 matrix cores).
+// Mixed precision (FP32 operands and accumulation on the FP32 matrix cores; with x3, the same
+// FP32 operands as three split-bf16 products on the bf16 matrix cores, FP32 accumulation).
 // W32 = W / wscale; C' and P~ are produced in FP64 with the factor wscale restored.
 hipError_t weight_to_f32(const double *W, float *W32, int q, double wscale, hipStream_t s);
 hipError_t state_to_f32(const double *A, const double *omega, float *A32, float *OA32, int q, int m, hipStream_t s);
 hipError_t vectors_to_f32(const double *U, float *U32, int q, int m, hipStream_t s);
-hipError_t extension_products_f32(const float *A32, const float *OA32, float *X32, int q, int m, hipStream_t s);
+hipError_t extension_products_f32(const float *A32, const float *OA32, float *X32, int q, int m, bool x3,
+                                  hipStream_t s);
 hipError_t weight_mix_f32_to_f64(const float *W32, const float *X32, double *Cout, int q, int m, double wscale,
-                                 hipStream_t s);
-hipError_t halfrow_products_f32(const float *A32, const float *U32, float *Y32, int q, int m, hipStream_t s);
-hipError_t weight_mix_f32(const float *W32, const float *Y32, float *Z32, int q, int m, hipStream_t s);
+                                 bool x3, hipStream_t s);
+hipError_t halfrow_products_f32(const float *A32, const float *U32, float *Y32, int q, int m, bool x3, hipStream_t s);
+hipError_t weight_mix_f32(const float *W32, const float *Y32, float *Z32, int q, int m, bool x3, hipStream_t s);
 hipError_t projection_f32(const float *U32, const float *Z32, double *Pt, int q, int m, double wscale, double *work,
-                          size_t work_elems, hipStream_t s);
+                          size_t work_elems, bool x3, hipStream_t s);
 
 // n_P = max|Pt|; A = Pt / n_P; book update with n_C (from post), n_P, S_E
 hipError_t normalize_and_book(const double *Pt, double *A, int q, int m, double *partials, Book *book,

@@ -145,13 +145,52 @@ __global__ void __launch_bounds__(256) spin_weight_kernel(const double *U, const
     if (threadIdx.x == 0) prob[s] = acc;
 }
 
-// out: [0] Z_b, [1] Z_h, [2] Z_d, [3] Z_d[W h4], [4] sum w^4, [5] M numerator, [6] sum prob
+// Partial sums of the environment scalars, one triple per workgroup:
+//   part[3 b + 0] = sum over rows i = b, b + G, ... of sum_{s,j} A[i, (s,j)]^2 w_i^2 w_j^2   (Z_h),
+//   part[3 b + 1] = its share of sum W H, part[3 b + 2] of sum W h4 H (the q^4 plaquette sums).
 __global__ void __launch_bounds__(256)
-env_scalars_kernel(const double *A, const double *omega, const double *W, const double *WH, const double *H,
-                   const double *prob, const double *V, int q, int dim, int m, int bc, int s0, double *out)
+env_partials_kernel(const double *A, const double *omega, const double *W, const double *WH, const double *H, int q,
+                    int m, double *part)
 {
     __shared__ double red[4];
     const long N = (long)q * m;
+    const int tid = threadIdx.x;
+    double zh = 0.0;
+    for (int i = blockIdx.x; i < m; i += gridDim.x) {
+        const double wi = omega[i];
+        const double *row = A + (long)i * N;
+        double r = 0.0;
+        for (int s = 0; s < q; ++s)
+            for (int j = tid; j < m; j += 256) {
+                const double p = row[(long)s * m + j], wj = omega[j];
+                r += p * p * wj * wj;
+            }
+        zh += r * wi * wi;
+    }
+    zh = block_sum<256>(zh, red);
+    const long q4 = (long)q * q * q * q;
+    double zd = 0.0, zdh = 0.0;
+    for (long idx = blockIdx.x * 256L + tid; idx < q4; idx += (long)gridDim.x * 256) {
+        zd += W[idx] * H[idx];
+        zdh += WH[idx] * H[idx];
+    }
+    zd = block_sum<256>(zd, red);
+    zdh = block_sum<256>(zdh, red);
+    if (tid == 0) {
+        part[3 * blockIdx.x + 0] = zh;
+        part[3 * blockIdx.x + 1] = zd;
+        part[3 * blockIdx.x + 2] = zdh;
+    }
+}
+
+// out: [0] Z_b, [1] Z_h, [2] Z_d, [3] Z_d[W h4], [4] sum w^4, [5] M numerator, [6] sum prob
+// (the partials of env_partials_kernel summed in workgroup order, so the result does not depend
+// on scheduling)
+__global__ void __launch_bounds__(256)
+env_scalars_kernel(const double *omega, const double *part, int np, const double *prob, const double *V, int q,
+                   int dim, int m, int bc, int s0, double *out)
+{
+    __shared__ double red[4];
     const int tid = threadIdx.x;
     double zb = 0.0;
     for (int i = tid; i < m; i += 256) {
@@ -159,44 +198,31 @@ env_scalars_kernel(const double *A, const double *omega, const double *W, const 
         zb += (w * w) * (w * w);
     }
     zb = block_sum<256>(zb, red);
-    double zh = 0.0;
-    const long total = (long)m * N;
-    for (long idx = tid; idx < total; idx += 256) {
-        const int i = (int)(idx / N);
-        const long col = idx - (long)i * N;
-        const int j = (int)(col % m);
-        const double p = A[idx];
-        zh += p * p * omega[i] * omega[i] * omega[j] * omega[j];
+    if (tid != 0) return;
+    double zh = 0.0, zd = 0.0, zdh = 0.0;
+    for (int b = 0; b < np; ++b) {
+        zh += part[3 * b];
+        zd += part[3 * b + 1];
+        zdh += part[3 * b + 2];
     }
-    zh = block_sum<256>(zh, red);
-    const long q4 = (long)q * q * q * q;
-    double zd = 0.0, zdh = 0.0;
-    for (long idx = tid; idx < q4; idx += 256) {
-        zd += W[idx] * H[idx];
-        zdh += WH[idx] * H[idx];
-    }
-    zd = block_sum<256>(zd, red);
-    zdh = block_sum<256>(zdh, red);
     double psum = 0.0, mnum = 0.0;
     double vx = 0.0, vy = 0.0, vz = 0.0;
-    if (tid == 0) {
-        for (int s = 0; s < q; ++s) {
-            psum += prob[s];
-            double dp = 0.0;
-            for (int x = 0; x < dim; ++x) dp += V[s0 * dim + x] * V[s * dim + x];
-            mnum += prob[s] * dp;
-            if (dim > 0) vx += prob[s] * V[s * dim + 0];
-            if (dim > 1) vy += prob[s] * V[s * dim + 1];
-            if (dim > 2) vz += prob[s] * V[s * dim + 2];
-        }
-        out[0] = zb;
-        out[1] = zh;
-        out[2] = zd;
-        out[3] = zdh;
-        out[4] = zb;
-        out[5] = (bc == 0) ? mnum : sqrt(vx * vx + vy * vy + vz * vz);
-        out[6] = psum;
+    for (int s = 0; s < q; ++s) {
+        psum += prob[s];
+        double dp = 0.0;
+        for (int x = 0; x < dim; ++x) dp += V[s0 * dim + x] * V[s * dim + x];
+        mnum += prob[s] * dp;
+        if (dim > 0) vx += prob[s] * V[s * dim + 0];
+        if (dim > 1) vy += prob[s] * V[s * dim + 1];
+        if (dim > 2) vz += prob[s] * V[s * dim + 2];
     }
+    out[0] = zb;
+    out[1] = zh;
+    out[2] = zd;
+    out[3] = zdh;
+    out[4] = zb;
+    out[5] = (bc == 0) ? mnum : sqrt(vx * vx + vy * vy + vz * vz);
+    out[6] = psum;
 }
 
 // FP32 operands of the mixed-precision contractions: A32 = A, OA32 = diag(omega) A (rounded once).
@@ -277,7 +303,8 @@ hipError_t projection(const double *U, const double *Z, double *Pt, int q, int m
     return gemm_mfma_splitk(A_T{U, m}, B_RM{Z, N}, EpiStore{Pt, N, 1.0}, m, (int)N, (int)N, sp, work, s, GEMM_LARGE);
 }
 
-// ---- mixed precision: FP32 operands on the FP32 matrix cores, FP32 accumulation.
+// ---- mixed precision: FP32 operands on the FP32 matrix cores (or as split-bf16 products on the
+// bf16 ones, gemm.h), FP32 accumulation.
 // W32 holds W / wscale (wscale = e^{4K} >= max W, so that no weight overflows FP32);
 // the factor is restored in FP64 in the epilogues that produce C' and P~.
 
@@ -302,40 +329,49 @@ hipError_t vectors_to_f32(const double *U, float *U32, int q, int m, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t extension_products_f32(const float *A32, const float *OA32, float *X32, int q, int m, hipStream_t s)
+// The FP32 contractions on the FP32 matrix cores, or as split-bf16 products (x3).
+template <GemmShape SH, class LA, class LB, class EPI>
+static hipError_t gemm32(bool x3, LA la, LB lb, EPI epi, int M, int N, int K, hipStream_t s)
+{
+    return x3 ? gemm_bf16x3<SH>(la, lb, epi, M, N, K, s) : gemm_mfma(SH, la, lb, epi, M, N, K, s);
+}
+
+hipError_t extension_products_f32(const float *A32, const float *OA32, float *X32, int q, int m, bool x3,
+                                  hipStream_t s)
 {
     const long N = (long)q * m;
-    return gemm_mfma(GEMM_LARGE, A_Tf{A32, N}, B_RMf{OA32, N}, EpiStoreF{X32, N, 1.0}, (int)N, (int)N, m, s);
+    return gemm32<GEMM_LARGE>(x3, A_Tf{A32, N}, B_RMf{OA32, N}, EpiStoreF{X32, N, 1.0}, (int)N, (int)N, m, s);
 }
 
 hipError_t weight_mix_f32_to_f64(const float *W32, const float *X32, double *Cout, int q, int m, double wscale,
-                                 hipStream_t s)
+                                 bool x3, hipStream_t s)
 {
     const long N = (long)q * m;
     const int q2 = q * q;
-    return gemm_mfma(GEMM_MIX, A_Tf{W32, q2}, B_Mixf{X32, q, m, N}, EpiMix_<double, true>{Cout, q, m, N, wscale}, q2,
-                     m * m, q2, s);
+    return gemm32<GEMM_MIX>(x3, A_Tf{W32, q2}, B_Mixf{X32, q, m, N}, EpiMix_<double, true>{Cout, q, m, N, wscale}, q2,
+                            m * m, q2, s);
 }
 
-hipError_t halfrow_products_f32(const float *A32, const float *U32, float *Y32, int q, int m, hipStream_t s)
+hipError_t halfrow_products_f32(const float *A32, const float *U32, float *Y32, int q, int m, bool x3, hipStream_t s)
 {
     const long N = (long)q * m;
-    return gemm_mfma(GEMM_LARGE, A_Tf{A32, N}, B_Ublkf{U32, m}, EpiStoreF{Y32, N, 1.0}, (int)N, (int)N, m, s);
+    return gemm32<GEMM_LARGE>(x3, A_Tf{A32, N}, B_Ublkf{U32, m}, EpiStoreF{Y32, N, 1.0}, (int)N, (int)N, m, s);
 }
 
-hipError_t weight_mix_f32(const float *W32, const float *Y32, float *Z32, int q, int m, hipStream_t s)
+hipError_t weight_mix_f32(const float *W32, const float *Y32, float *Z32, int q, int m, bool x3, hipStream_t s)
 {
     const long N = (long)q * m;
     const int q2 = q * q;
-    return gemm_mfma(GEMM_MIX, A_Tf{W32, q2}, B_Mixf{Y32, q, m, N}, EpiMix_<float, false>{Z32, q, m, N, 1.0}, q2, m * m,
-                     q2, s);
+    return gemm32<GEMM_MIX>(x3, A_Tf{W32, q2}, B_Mixf{Y32, q, m, N}, EpiMix_<float, false>{Z32, q, m, N, 1.0}, q2,
+                            m * m, q2, s);
 }
 
 hipError_t projection_f32(const float *U32, const float *Z32, double *Pt, int q, int m, double wscale, double *work,
-                          size_t work_elems, hipStream_t s)
+                          size_t work_elems, bool x3, hipStream_t s)
 {
     const long N = (long)q * m;
     const int sp = projection_splits(m, N, work ? work_elems : 0);
+    if (x3) return gemm_bf16x3<GEMM_LARGE>(A_Tf{U32, m}, B_RMf{Z32, N}, EpiStore{Pt, N, wscale}, m, (int)N, (int)N, s, sp, work);
     return gemm_mfma_splitk(A_Tf{U32, m}, B_RMf{Z32, N}, EpiStore{Pt, N, wscale}, m, (int)N, (int)N, sp, work, s,
                             GEMM_LARGE);
 }
@@ -369,7 +405,11 @@ hipError_t observables(const double *A, const double *omega, const double *U, co
     if (e != hipSuccess) return e;
     double *prob = out + 8;
     hipLaunchKernelGGL(spin_weight_kernel, dim3(q), dim3(256), 0, s, U, omega, m, prob);
-    hipLaunchKernelGGL(env_scalars_kernel, dim3(1), dim3(256), 0, s, A, omega, W, WH, H, prob, V, q, dim, m, bc, s0,
+    // the work buffer is free again once H is formed: it takes the partial sums
+    const int np = (int)std::min<size_t>({(size_t)512, (size_t)std::max(m, 1), work_elems / 3});
+    if (np < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(env_partials_kernel, dim3(np), dim3(256), 0, s, A, omega, W, WH, H, q, m, work);
+    hipLaunchKernelGGL(env_scalars_kernel, dim3(1), dim3(256), 0, s, omega, work, np, prob, V, q, dim, m, bc, s0,
                        out);
     return hipGetLastError();
 }

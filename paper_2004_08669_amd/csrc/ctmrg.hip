@@ -174,7 +174,7 @@ hipError_t alloc_device(ctmrg_ctx *c, Arena &a)
     hipError_t e = hipSuccess;
     for (auto &r : reqs)
         if (e == hipSuccess) e = a.take((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
-    if (o.precision == CTMRG_FP32) {
+    if (o.precision != CTMRG_FP64) {
         struct ReqF { float **p; size_t n; };
         ReqF fr[] = {{&c->dW32, q4}, {&c->dA32, (size_t)m * N}, {&c->dOA32, (size_t)m * N}, {&c->dU32, (size_t)N * m}};
         for (auto &r : fr)
@@ -257,12 +257,13 @@ hipError_t extend_corner(ctmrg_ctx *c)
     const int q = c->q, m = c->m;
     hipStream_t s = c->stream;
     hipError_t e;
-    if (c->opt.precision == CTMRG_FP32) {
+    if (c->opt.precision != CTMRG_FP64) {
+        const bool x3 = c->opt.precision == CTMRG_BF16X3;
         float *X32 = reinterpret_cast<float *>(c->dX);
         e = state_to_f32(c->dA, c->dOmega, c->dA32, c->dOA32, q, m, s);
-        if (e == hipSuccess) e = extension_products_f32(c->dA32, c->dOA32, X32, q, m, s);
+        if (e == hipSuccess) e = extension_products_f32(c->dA32, c->dOA32, X32, q, m, x3, s);
         mark(c->eig, MK_EXT, s);
-        if (e == hipSuccess) e = weight_mix_f32_to_f64(c->dW32, X32, c->dC, q, m, c->wscale, s);
+        if (e == hipSuccess) e = weight_mix_f32_to_f64(c->dW32, X32, c->dC, q, m, c->wscale, x3, s);
     } else {
         e = extension_products(c->dA, c->dOmega, c->dOA, c->dX, q, m, s);
         mark(c->eig, MK_EXT, s);
@@ -275,7 +276,7 @@ hipError_t extend_corner(ctmrg_ctx *c)
 hipError_t make_weight(ctmrg_ctx *c)
 {
     hipError_t e = build_weight(c->dV, c->q, c->dim, c->K, c->dW, c->dWH, c->stream);
-    if (e != hipSuccess || c->opt.precision != CTMRG_FP32) return e;
+    if (e != hipSuccess || c->opt.precision == CTMRG_FP64) return e;
     // every plaquette sum of four dot products of unit vectors is at most 4
     c->wscale = exp(4.0 * c->K);
     return weight_to_f32(c->dW, c->dW32, c->q, c->wscale, c->stream);
@@ -300,11 +301,11 @@ ctmrg_status one_step(ctmrg_ctx *c)
         prm.gap_tol = c->opt.gap_tol;
         prm.rank_tol = c->opt.rank_tol;
         prm.degree = c->opt.warm_degree > 0 ? c->opt.warm_degree : 8;
-        prm.tol = c->opt.warm_tol > 0.0 ? c->opt.warm_tol : (c->opt.precision == CTMRG_FP32 ? 1e-9 : 1e-12);
+        prm.tol = c->opt.warm_tol > 0.0 ? c->opt.warm_tol : (c->opt.precision != CTMRG_FP64 ? 1e-9 : 1e-12);
         prm.profile = c->profile;
         // the exact tail only where the bound could matter at the contractions' own precision
         prm.tail_exact = c->opt.warm_tail == CTMRG_WARM_TAIL_EXACT;
-        prm.tail_tol = c->opt.precision == CTMRG_FP32 ? 1e-9 : 1e-14;
+        prm.tail_tol = c->opt.precision != CTMRG_FP64 ? 1e-9 : 1e-14;
         std::string why;
         const long attempts = c->warm.steps;
         // dX (N x N) is free between the extension and the half-row products
@@ -358,15 +359,16 @@ ctmrg_status one_step(ctmrg_ctx *c)
     // warm mode keeps this step's C' (for the exact S_E of ctmrg_observables): Z goes to dZ
     double *Zb = warm_mode ? c->dZ : c->dC;
     c->last_warm = warm_done != 0;
-    if (c->opt.precision == CTMRG_FP32) {
+    if (c->opt.precision != CTMRG_FP64) {
+        const bool x3 = c->opt.precision == CTMRG_BF16X3;
         float *Y32 = reinterpret_cast<float *>(c->dX), *Z32 = reinterpret_cast<float *>(Zb);
         HIPCHK(c, vectors_to_f32(c->dU, c->dU32, q, m, s));
-        HIPCHK(c, halfrow_products_f32(c->dA32, c->dU32, Y32, q, m, s));
+        HIPCHK(c, halfrow_products_f32(c->dA32, c->dU32, Y32, q, m, x3, s));
         mark(c->eig, MK_HALF, s);
-        HIPCHK(c, weight_mix_f32(c->dW32, Y32, Z32, q, m, s));
+        HIPCHK(c, weight_mix_f32(c->dW32, Y32, Z32, q, m, x3, s));
         mark(c->eig, MK_WMIX2, s);
         // dX (Y32) is free once Z is formed: it takes the projection's split-K partials
-        HIPCHK(c, projection_f32(c->dU32, Z32, c->dPt, q, m, c->wscale, c->dX, (size_t)N * N, s));
+        HIPCHK(c, projection_f32(c->dU32, Z32, c->dPt, q, m, c->wscale, c->dX, (size_t)N * N, x3, s));
     } else {
         HIPCHK(c, halfrow_products(c->dA, c->dU, c->dX, q, m, s));
         mark(c->eig, MK_HALF, s);
@@ -454,7 +456,8 @@ ctmrg_status ctmrg_workspace_size(int q, int m, const ctmrg_options *opt, size_t
     ctmrg_default_options(&o);
     if (opt) o = *opt;
     if (!valid_band(o.band)) return CTMRG_E_INVALID_ARG;
-    if (o.precision != CTMRG_FP64 && o.precision != CTMRG_FP32) return CTMRG_E_INVALID_ARG;
+    if (o.precision != CTMRG_FP64 && o.precision != CTMRG_FP32 && o.precision != CTMRG_BF16X3)
+        return CTMRG_E_INVALID_ARG;
     if (!valid_eig_options(o)) return CTMRG_E_INVALID_ARG;
     *bytes = context_bytes(q, m, 3, o);
     return CTMRG_OK;
@@ -477,7 +480,8 @@ ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, 
     if (opt) o = *opt;
     if (!valid_band(o.band) || o.boundary_spin < 0 || o.boundary_spin >= q || (o.bc != 0 && o.bc != 1))
         return CTMRG_E_INVALID_ARG;
-    if (o.precision != CTMRG_FP64 && o.precision != CTMRG_FP32) return CTMRG_E_INVALID_ARG;
+    if (o.precision != CTMRG_FP64 && o.precision != CTMRG_FP32 && o.precision != CTMRG_BF16X3)
+        return CTMRG_E_INVALID_ARG;
     if (!valid_eig_options(o)) return CTMRG_E_INVALID_ARG;
     const long N = (long)q * m;
     if (N > 65536) return CTMRG_E_INVALID_ARG;
@@ -560,15 +564,16 @@ ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *c, double tol, int max_steps, i
 }
 
 ctmrg_status ctmrg_sweep(ctmrg_ctx *c, int n, const double *T, double tol, int max_steps, int warm_start,
-                         ctmrg_observables_t *out, int *steps_out, int *converged)
+                         ctmrg_observables_t *out, int *steps_out, int *converged, ctmrg_derivative_t *deriv_out)
 {
     if (!c || n < 0 || (n > 0 && (!T || !out)) || max_steps < 2 || !(tol >= 0.0)) return CTMRG_E_INVALID_ARG;
     for (int i = 0; i < n; ++i)
         if (!(T[i] > 0.0) || !std::isfinite(T[i])) return fail(c, CTMRG_E_INVALID_ARG, "temperatures must be positive");
     for (int i = 0; i < n; ++i) {
         const double K = 1.0 / T[i];
-        if (warm_start && i > 0) {
-            // the previous temperature's fixed point is the start: new weights, same state
+        if (warm_start && (i > 0 || c->steps > 0)) {
+            // the previous temperature's fixed point (or the state the context holds) is the
+            // start: new weights, same state
             c->K = K;
             HIPCHK(c, make_weight(c));
             HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -592,6 +597,13 @@ ctmrg_status ctmrg_sweep(ctmrg_ctx *c, int n, const double *T, double tol, int m
         if (converged) converged[i] = conv ? 1 : 0;
         const ctmrg_status st = ctmrg_observables(c, out + i, nullptr);
         if (st != CTMRG_OK) return st;
+        if (deriv_out) {
+            deriv_out[i] = ctmrg_derivative_t{};
+            if (conv && c->delta < 1e-6) {
+                const ctmrg_status sd = ctmrg_fixed_point_derivative(c, 1, deriv_out + i);
+                if (sd != CTMRG_OK) return sd;
+            }
+        }
     }
     return CTMRG_OK;
 }
@@ -659,6 +671,10 @@ ctmrg_status derivative_at(ctmrg_ctx *c, const double *W, const double *WH, AdjR
     in.A = c->dA;
     in.omega = c->dOmega;
     in.U = c->dU;
+    in.V = c->dV;
+    in.dim = c->dim;
+    in.bc = c->opt.bc;
+    in.s0 = c->opt.boundary_spin;
     in.gap_tol = c->opt.gap_tol;
     in.rank_tol = c->opt.rank_tol;
     c->adj.band = c->opt.band;
@@ -686,7 +702,12 @@ ctmrg_status ctmrg_fixed_point_derivative(ctmrg_ctx *c, int second_order, ctmrg_
     out->aligned_steps = r.aligned_steps;
     out->iterations = r.iterations;
     out->n_eigen = r.n_eigen;
-    if (second_order) {
+    out->E = r.E;
+    out->M = r.M;
+    out->dM_dK = r.dMdK;
+    out->dE_dK = r.dEdK;
+    if (second_order == 1) out->d2F_dK2 = r.dEdK;
+    if (second_order == 2) {
         const size_t q4 = (size_t)c->q * c->q * c->q * c->q;
         if (!c->dWd) HIPCHK(c, hipMalloc((void **)&c->dWd, sizeof(double) * q4));
         if (!c->dWHd) HIPCHK(c, hipMalloc((void **)&c->dWHd, sizeof(double) * q4));
@@ -708,14 +729,12 @@ ctmrg_status ctmrg_fixed_point_derivative(ctmrg_ctx *c, int second_order, ctmrg_
 ctmrg_status ctmrg_backward(ctmrg_ctx *c, const double *obs_bar, double *K_bar, double *d2F_dK2)
 {
     if (!c || !obs_bar || !K_bar) return CTMRG_E_INVALID_ARG;
-    if (obs_bar[2] != 0.0) return fail(c, CTMRG_E_UNSUPPORTED, "the derivative of M is not available");
-    const int second = (obs_bar[1] != 0.0 || d2F_dK2 != nullptr) ? 1 : 0;
     ctmrg_derivative_t d;
-    ctmrg_status st = ctmrg_fixed_point_derivative(c, second, &d);
+    ctmrg_status st = ctmrg_fixed_point_derivative(c, 1, &d);
     if (st != CTMRG_OK) return st;
     const double K = c->K;
     const double dfdK = d.dF_dK / K - d.F / (K * K);  // f = F / K
-    *K_bar = obs_bar[0] * dfdK + (second ? obs_bar[1] * d.d2F_dK2 : 0.0);
+    *K_bar = obs_bar[0] * dfdK + obs_bar[1] * d.d2F_dK2 + obs_bar[2] * d.dM_dK;
     if (d2F_dK2) *d2F_dK2 = d.d2F_dK2;
     return CTMRG_OK;
 }

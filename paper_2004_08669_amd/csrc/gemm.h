@@ -448,6 +448,175 @@ reduce_items_kernel(const double *p1, const double *p2, int M, int N, int K, int
     Y[(long)i * ldy + j] = s;
 }
 
+// ---------------------------------------------------------------- split-bf16 products
+// FP32 operands as three bf16 products on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16),
+// with FP32 accumulation: each operand value x is split into hi = bf16(x) and
+// lo = bf16(x - hi) (round to nearest even; x - hi is exact in FP32), and
+//   a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi,
+// dropping a_lo b_lo and the rounding of the lo parts, each about 2^-16 |a b|.
+// The bf16 products are exact in FP32, so the sum carries a relative error of order
+// 3 * 2^-16 per term on top of the FP32 accumulation.
+//
+// Tiles: BK = 32 (one bf16 MFMA per 16 x 16 block and product).  In LDS every row
+// (of A: an output row, of B: an output column) holds its 32 k of the slice contiguous,
+// hi and lo in separate arrays, padded to 40 entries (80 bytes: eight lanes storing or
+// loading 16 bytes in consecutive rows meet disjoint banks).  The fragment of an MFMA is
+// then one 16-byte LDS read per lane: lane l takes row l % 16 and the eight k
+// 8 (l / 16) .. 8 (l / 16) + 7, for A and B alike (the instruction pairs the same
+// lane group and element of both operands, so the products run over the same k).
+// D fragment: lane l, register r holds D[4 (l / 16) + r][l % 16].
+// A thread stages groups of eight k of one row: along m (n) across the lanes of a wave
+// when the operand is contiguous in m (n), along k when it is contiguous in k.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ inline unsigned bf16_rne_bits(float x)
+{
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+template <int BM, int BN, int WM, int WN, class LA, class LB, class EPI>
+__global__ void __launch_bounds__(WM * WN * 64)
+gemm_bf16x3_kernel(LA la, LB lb, EPI epi, int M, int N, int K, int kchunk)
+{
+    static_assert(std::is_same<typename LA::value_type, float>::value &&
+                      std::is_same<typename LB::value_type, float>::value, "FP32 operands");
+    static_assert(!has_krange<LA>::value && !has_items<LA>::value && !lower_tiles<EPI>::value &&
+                      !prefetch_c<EPI>::value, "plain tiles only");
+    constexpr int BK = 32, KP = 40;
+    constexpr int NT = WM * WN * 64;
+    constexpr int TM = BM / WM / 16;
+    constexpr int TN = BN / WN / 16;
+    static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
+    __shared__ __align__(16) unsigned short Ah[BM][KP], Al[BM][KP], Bh[BN][KP], Bl[BN][KP];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave % WM, wn = wave / WM;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int split = blockIdx.z;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+
+    float4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = (float4_t){0.f, 0.f, 0.f, 0.f};
+
+    constexpr int GA = BM * (BK / 8), GB = BN * (BK / 8);
+    constexpr int PA = (GA + NT - 1) / NT, PB = (GB + NT - 1) / NT;
+    float ra[PA][8], rb[PB][8];
+    // group g: the eight k kk .. kk + 7 of row r
+    auto pos = [](int g, int rows, bool contig_k, int &r, int &kk) {
+        if (contig_k) { r = g / (BK / 8); kk = (g - r * (BK / 8)) * 8; }
+        else { kk = (g / rows) * 8; r = g - (kk / 8) * rows; }
+    };
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < PA; ++u) {
+            const int g = tid + u * NT;
+            int r, kk;
+            pos(g, BM, LA::kContigK, r, kk);
+            const int gm = m0 + r, gk = k0 + kk;
+            if (g < GA && gm < M && gk + 8 <= kend) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) ra[u][v] = la(gm, gk + v);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) ra[u][v] = (g < GA && gm < M && gk + v < kend) ? la(gm, gk + v) : 0.f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            const int g = tid + u * NT;
+            int r, kk;
+            pos(g, BN, LB::kContigK, r, kk);
+            const int gn = n0 + r, gk = k0 + kk;
+            if (g < GB && gn < N && gk + 8 <= kend) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) rb[u][v] = lb(gk + v, gn);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) rb[u][v] = (g < GB && gn < N && gk + v < kend) ? lb(gk + v, gn) : 0.f;
+            }
+        }
+    };
+    // split eight values into hi and lo and store each as one 16-byte row segment
+    auto put = [](const float (&x)[8], unsigned short *hi, unsigned short *lo) {
+        unsigned h[8], l[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            h[v] = bf16_rne_bits(x[v]);
+            l[v] = bf16_rne_bits(x[v] - __uint_as_float(h[v] << 16));
+        }
+        *(uint4 *)hi = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+        *(uint4 *)lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int u = 0; u < PA; ++u) {
+            const int g = tid + u * NT;
+            if (g < GA) {
+                int r, kk;
+                pos(g, BM, LA::kContigK, r, kk);
+                put(ra[u], &Ah[r][kk], &Al[r][kk]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            const int g = tid + u * NT;
+            if (g < GB) {
+                int r, kk;
+                pos(g, BN, LB::kContigK, r, kk);
+                put(rb[u], &Bh[r][kk], &Bl[r][kk]);
+            }
+        }
+    };
+    auto compute = [&]() {
+        const int kq = (lane >> 4) * 8, rr = lane & 15;
+        bf16x8_t ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            ah[i] = __builtin_bit_cast(bf16x8_t, *(const uint4 *)&Ah[(wm * TM + i) * 16 + rr][kq]);
+            al[i] = __builtin_bit_cast(bf16x8_t, *(const uint4 *)&Al[(wm * TM + i) * 16 + rr][kq]);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            bh[j] = __builtin_bit_cast(bf16x8_t, *(const uint4 *)&Bh[(wn * TN + j) * 16 + rr][kq]);
+            bl[j] = __builtin_bit_cast(bf16x8_t, *(const uint4 *)&Bl[(wn * TN + j) * 16 + rr][kq]);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                // the two small cross terms first
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        stage();
+        __syncthreads();
+        if (k0 + BK < kend) fetch(k0 + BK);
+        compute();
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + (wm * TM + i) * 16 + 4 * (lane >> 4) + r;
+                const int col = n0 + (wn * TN + j) * 16 + (lane & 15);
+                if (row < M && col < N) epi(row, col, (double)acc[i][j][r], split);
+            }
+}
+
 // Staging of the tiles per element type (measured on the contraction shapes at q = 20,
 // m = 512): FP32 operands are read four at a time (16-byte loads) into LDS rows padded by
 // four; FP64 operands one at a time into rows padded by one.  With eight waves per
@@ -549,6 +718,33 @@ hipError_t gemm_mfma_splitk(LA la, LB lb, EPI epi, int M, int N, int K, int spli
                            dim3(ceil_div(M, 64), ceil_div(N, 64), splits), dim3(256), 0, s, la, lb, part, M, N, K,
                            kchunk);
     long total = (long)M * N;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(reduce_partials_kernel<EPI>, dim3(blocks), dim3(256), 0, s, work, splits, M, N, epi);
+    return hipGetLastError();
+}
+
+// The split-bf16 GEMM (FP32 operands, three bf16 products, FP32 accumulation) in the tile
+// shape SH (GEMM_LARGE or GEMM_MIX), with an optional split of K (partials in `work`, as in
+// gemm_mfma_splitk).
+template <GemmShape SH, class LA, class LB, class EPI>
+hipError_t gemm_bf16x3(LA la, LB lb, EPI epi, int M, int N, int K, hipStream_t s, int splits = 1,
+                       double *work = nullptr)
+{
+    static_assert(SH == GEMM_LARGE || SH == GEMM_MIX, "tile shape");
+    constexpr int BM = SH == GEMM_LARGE ? 128 : 80, WM = SH == GEMM_LARGE ? 4 : 1, WN = SH == GEMM_LARGE ? 2 : 8;
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (splits <= 1 || !work) {
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, 128, WM, WN, LA, LB, EPI>), dim3(ceil_div(M, BM), ceil_div(N, 128), 1),
+                           dim3(512), 0, s, la, lb, epi, M, N, K, K);
+        return hipGetLastError();
+    }
+    const int kchunk = ceil_div(ceil_div(K, splits), 32) * 32;
+    splits = ceil_div(K, kchunk);
+    EpiPartial part{work, M, N};
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, 128, WM, WN, LA, LB, EpiPartial>),
+                       dim3(ceil_div(M, BM), ceil_div(N, 128), splits), dim3(512), 0, s, la, lb, part, M, N, K, kchunk);
+    const long total = (long)M * N;
     int blocks = (int)((total + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(reduce_partials_kernel<EPI>, dim3(blocks), dim3(256), 0, s, work, splits, M, N, epi);

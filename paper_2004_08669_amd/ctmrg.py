@@ -89,6 +89,10 @@ class Derivative(ctypes.Structure):
         ("aligned_steps", ctypes.c_int),
         ("iterations", ctypes.c_int),
         ("n_eigen", ctypes.c_int),
+        ("E", ctypes.c_double),
+        ("M", ctypes.c_double),
+        ("dE_dK", ctypes.c_double),
+        ("dM_dK", ctypes.c_double),
     ]
 
 
@@ -119,7 +123,8 @@ def load():
                                      ctypes.c_int),
         "ctmrg_observables": ([_vp, ctypes.POINTER(Observables), _dp], ctypes.c_int),
         "ctmrg_sweep": ([_vp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                         ctypes.POINTER(Observables), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                         ctypes.POINTER(Observables), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                         ctypes.POINTER(Derivative)],
                         ctypes.c_int),
         "ctmrg_backward": ([_vp, _dp, _dp, _dp], ctypes.c_int),
         "ctmrg_fixed_point_derivative": ([_vp, ctypes.c_int, ctypes.POINTER(Derivative)], ctypes.c_int),
@@ -162,11 +167,16 @@ def default_options() -> Options:
     return o
 
 
+# ctmrg_precision: contractions in FP64, FP32, or FP32 operands as three split-bf16 products
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+GAP_TOL = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-4}
+
+
 def workspace_size(q: int, m: int, band: int = 16, precision: str = "fp64", eig: str = "two_stage") -> int:
     """Device bytes a context allocates at init (what a caller-owned workspace needs)."""
     o = default_options()
     o.band = band
-    o.precision = {"fp64": 0, "fp32": 1}[precision]
+    o.precision = PRECISIONS[precision]
     o.eig_solver = EIG_SOLVERS[eig]
     n = ctypes.c_size_t(0)
     st = load().ctmrg_workspace_size(q, m, ctypes.byref(o), ctypes.byref(n))
@@ -229,10 +239,11 @@ class CTMRG:
         o.bc = {"fixed": 0, "free": 1}[bc]
         o.boundary_spin = boundary_spin
         o.band = band
-        # multiplets of C' are split by the contraction rounding: ~1e-16 (FP64), ~1e-7 (FP32)
-        o.gap_tol = gap_tol if gap_tol is not None else (1e-10 if precision == "fp64" else 1e-6)
+        # multiplets of C' are split by the contraction rounding: ~1e-16 (FP64), ~1e-7 (FP32),
+        # ~1e-5 (split-bf16 products)
+        o.gap_tol = gap_tol if gap_tol is not None else GAP_TOL[precision]
         o.rank_tol = rank_tol
-        o.precision = {"fp64": 0, "fp32": 1}[precision]
+        o.precision = PRECISIONS[precision]
         o.hip_stream = stream
         o.eig_solver = EIG_SOLVERS[eig]
         o.warm_guard = warm_guard
@@ -293,31 +304,36 @@ class CTMRG:
         out["kept_spectrum"] = spec
         return out
 
-    def sweep(self, T, tol: float, max_steps: int, warm_start: bool = True) -> list:
+    def sweep(self, T, tol: float, max_steps: int, warm_start: bool = True, derivative: bool = False) -> list:
         """ctmrg_sweep over the temperatures T (one dict of observables per temperature, with
-        "T", "steps" and "converged" added)."""
+        "T", "steps" and "converged" added, and with derivative=True the fixed-point derivative
+        of each converged temperature under "derivative")."""
         Ts = _f64(np.atleast_1d(T))
         n = int(Ts.size)
         obs = (Observables * max(n, 1))()
         steps = (ctypes.c_int * max(n, 1))()
         conv = (ctypes.c_int * max(n, 1))()
+        der = (Derivative * max(n, 1))() if derivative else None
         self._check(self._lib.ctmrg_sweep(self._h, n, _p(Ts), float(tol), int(max_steps), 1 if warm_start else 0,
-                                          obs, steps, conv))
+                                          obs, steps, conv, der))
         out = []
         for i in range(n):
             d = {name: getattr(obs[i], name) for name, _ in Observables._fields_}
             d.update({"T": float(Ts[i]), "steps": int(steps[i]), "converged": bool(conv[i])})
+            if derivative:
+                d["derivative"] = {name: getattr(der[i], name) for name, _ in Derivative._fields_}
             out.append(d)
         return out
 
-    def fixed_point_derivative(self, second_order: bool = False) -> dict:
-        """dF/dK (and d2F/dK2) of F = beta f at the converged fixed point (see include/ctmrg.h)."""
+    def fixed_point_derivative(self, second_order=False) -> dict:
+        """dF/dK, dE/dK and dM/dK at the converged fixed point, and d2F/dK2 with second_order
+        (True or 1: dE/dK; 2: the central difference of dF/dK; see include/ctmrg.h)."""
         d = Derivative()
-        self._check(self._lib.ctmrg_fixed_point_derivative(self._h, 1 if second_order else 0, ctypes.byref(d)))
+        self._check(self._lib.ctmrg_fixed_point_derivative(self._h, int(second_order), ctypes.byref(d)))
         return {name: getattr(d, name) for name, _ in Derivative._fields_}
 
     def backward(self, obs_bar, want_d2: bool = False):
-        """K_bar = obs_bar . d(f, E, M)/dK (obs_bar[2] must be 0); also d2F/dK2 when requested."""
+        """K_bar = obs_bar . d(f, E, M)/dK; also d2F/dK2 when requested."""
         ob = _f64(obs_bar)
         kb = ctypes.c_double(0.0)
         d2 = ctypes.c_double(0.0)

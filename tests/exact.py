@@ -49,6 +49,15 @@ def ising_magnetization(K: float) -> float:
     return (1.0 - s ** -4) ** 0.125
 
 
+def ising_dM_dK(K: float) -> float:
+    """K-derivative of Yang's magnetization: with s = sinh 2K, M = (1 - s^-4)^(1/8) and
+    dM/dK = cosh(2K) s^-5 (1 - s^-4)^(-7/8) (zero above T_c)."""
+    s = math.sinh(2 * K)
+    if s <= 1.0:
+        return 0.0
+    return math.cosh(2 * K) * s ** -5 * (1.0 - s ** -4) ** -0.875
+
+
 def ising_d2F_dK2(K: float, h: float = 1e-4) -> float:
     """d^2(beta f)/dK^2 per site = -du/dK... computed by differentiating u (closed form) numerically."""
     return (ising_energy(K + h) - ising_energy(K - h)) / (2 * h)

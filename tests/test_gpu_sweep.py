@@ -10,6 +10,9 @@
   warm-started sweep takes fewer steps in all.
 * q = 12 (icosahedron, the workload shape of Fig. 3), m = 16: a short sweep converges at every
   temperature and M falls with T.
+* the sweep with derivatives (q = 20, m = 12, T = 0.38 then 0.40): at every point dF/dK equals
+  the impurity energy, and at T = 0.40 dF/dK, d2F/dK2 and dM/dK equal the oracle's central
+  differences of F, E and M over its own fixed points at K +- 1e-4 (tests/golden).
 """
 import os
 
@@ -86,6 +89,33 @@ def test_sweep_icosahedron_m16():
         assert p["converged"]
     Ms = [p["M"] for p in pts]
     assert all(a > b for a, b in zip(Ms, Ms[1:]))
+
+
+def test_sweep_with_derivatives_m12():
+    ct = _lib()
+    V = I.dodecahedron()
+    Ts = [0.38, 0.40]
+    say(f"[sweep with derivatives] q=20 m=12 T={Ts}")
+    g = ct.CTMRG(V, 1.0 / Ts[0], 12)
+    pts = g.sweep(Ts, 1e-13, 3000, derivative=True)
+    g.close()
+    for p in pts:
+        d = p["derivative"]
+        say(f"  T={p['T']}: {p['steps']} steps; E {p['E']!r} dF/dK {d['dF_dK']!r} d2F/dK2 {d['d2F_dK2']!r} "
+            f"dM/dK {d['dM_dK']!r} ({d['iterations']} tangent iterations)")
+        assert p["converged"]
+        assert abs(d["dF_dK"] - p["E"]) <= 1e-9
+        assert d["d2F_dK2"] == d["dE_dK"] and d["d2F_dK2"] < 0.0
+    ref = _golden("derivative_q20_m12_T0.40.npz")
+    h = float(ref["h"])
+    d = pts[1]["derivative"]
+    fd = (float(ref["F_p"]) - float(ref["F_m"])) / (2 * h)
+    d2 = (float(ref["E_p"]) - float(ref["E_m"])) / (2 * h)
+    dM = (float(ref["M_p"]) - float(ref["M_m"])) / (2 * h)
+    say(f"  oracle central differences at T=0.40: dF/dK {fd!r} d2F/dK2 {d2!r} dM/dK {dM!r}")
+    assert abs(d["dF_dK"] - fd) <= 1e-7
+    assert abs(d["d2F_dK2"] - d2) <= 1e-5 * abs(d2)
+    assert abs(d["dM_dK"] - dM) <= 1e-5 * abs(dM)
 
 
 def test_sweep_rejects_bad_input():

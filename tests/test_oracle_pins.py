@@ -177,6 +177,18 @@ def test_ising_second_difference_of_F_is_the_closed_form():
     assert abs(d2 - ref) <= 1e-4 * abs(ref)
 
 
+@pytest.mark.parametrize("T", [2.0, 1.5])
+def test_ising_dM_dK_closed_form(T):
+    """The derivative of Yang's magnetization in tests/exact.py (the reference of the GPU's dM/dK
+    at q = 2) against the central difference of the oracle's M over fixed points at K +- h
+    (h = 1e-5: M varies fast near T_c, so the difference's h^2 term is kept below 1e-7)."""
+    K, h = 1.0 / T, 1e-5
+    Mp = O.run_fixed_point(I.ising(), K + h, 16, tol=1e-14)[1]["M"]
+    Mm = O.run_fixed_point(I.ising(), K - h, 16, tol=1e-14)[1]["M"]
+    ref = E.ising_dM_dK(K)
+    assert abs((Mp - Mm) / (2 * h) - ref) <= 1e-6 * abs(ref)
+
+
 def test_cube_is_three_ising_copies():
     T = 0.6
     K = 1.0 / T
