@@ -346,8 +346,10 @@ def main():
                     help="residual tolerance of the warm-started solver on the mixed paths (0: the library default)")
     ap.add_argument("--no-bf16x3", action="store_true",
                     help="skip the split-bf16 path (contractions as three bf16 products, warm-started eigensolver)")
-    ap.add_argument("--gap-tol-bf16x3", type=float, default=1e-4,
-                    help="multiplet gap of the cut on the split-bf16 path (its rounding splits multiplets by ~1e-6)")
+    ap.add_argument("--gap-tol-bf16x3", type=float, default=1e-6,
+                    help="multiplet gap of the cut on the split-bf16 path (default: the same cut rule as the other "
+                         "paths; at m=512 the gaps at the cut, ~2e-6 |lambda_1|, are below its rounding, and a wider "
+                         "gap merges the tail and cuts far below m)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=128)
     ap.add_argument("--compare-eigh", action="store_true",

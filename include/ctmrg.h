@@ -122,7 +122,7 @@ typedef struct {
     int warm_guard;       /* CTMRG_EIG_WARM: guard vectors below the kept ones (0 = max(8, m/4)) */
     int warm_degree;      /* CTMRG_EIG_WARM: largest Chebyshev degree per pass, 1..8 (0 = 8)   */
     double warm_tol;      /* CTMRG_EIG_WARM: kept residuals below warm_tol |lambda_1|
-                             (0 = 1e-12 for FP64 contractions, 1e-9 for FP32)                  */
+                             (0 = 1e-12 for FP64 contractions, 1e-8 for FP32 / BF16X3)       */
     int warm_tail;        /* CTMRG_EIG_WARM: ctmrg_warm_tail (default CTMRG_WARM_TAIL_AUTO)    */
     void *workspace;      /* NULL, or device memory of workspace_bytes >= ctmrg_workspace_size()
                              bytes, owned by the caller and kept alive until ctmrg_destroy: every

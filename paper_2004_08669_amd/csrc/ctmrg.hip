@@ -294,14 +294,24 @@ ctmrg_status one_step(ctmrg_ctx *c)
     c->cext_valid = false;
     const bool warm_mode = c->opt.eig_solver == CTMRG_EIG_WARM;
     const int m_eff_prev = c->have_U ? c->m_eff : 0;
-    // warm-started solve when the last two steps kept the same dimension
+    // warm-started solve from the previous step's block when the last two steps kept the same
+    // dimension, or (m >= 64) both kept all but at most one multiplet (<= 8 states) of m: a flip
+    // of the cut by a multiplet near m is handled inside (the block holds m + p vectors, and the
+    // gauge is aligned over the states both steps kept), while the early steps, whose kept
+    // dimension still grows and whose C' has few nonzero eigenvalues, reseed from the two-stage
+    // solver
     int warm_done = 0;
-    if (warm_mode && c->warm.kcur > 0 && c->have_U && c->m_eff == c->m_eff_prev2) {
+    const bool same_dim = c->m_eff == c->m_eff_prev2 ||
+                          (c->m >= 64 && c->m_eff_prev2 > 0 && std::min(c->m_eff, c->m_eff_prev2) >= c->m - 8);
+    if (warm_mode && c->warm.kcur > 0 && c->have_U && same_dim) {
         WarmParams prm;
         prm.gap_tol = c->opt.gap_tol;
         prm.rank_tol = c->opt.rank_tol;
         prm.degree = c->opt.warm_degree > 0 ? c->opt.warm_degree : 8;
-        prm.tol = c->opt.warm_tol > 0.0 ? c->opt.warm_tol : (c->opt.precision != CTMRG_FP64 ? 1e-9 : 1e-12);
+        // residual tolerance: on the mixed paths C' itself carries a rounding error of about 1e-6 of
+        // |lambda_1| (Frobenius), so residuals below 1e-8 |lambda_1| leave the kept pairs as accurate as
+        // C' allows
+        prm.tol = c->opt.warm_tol > 0.0 ? c->opt.warm_tol : (c->opt.precision != CTMRG_FP64 ? 1e-8 : 1e-12);
         prm.profile = c->profile;
         // the exact tail only where the bound could matter at the contractions' own precision
         prm.tail_exact = c->opt.warm_tail == CTMRG_WARM_TAIL_EXACT;
