@@ -192,6 +192,8 @@ ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *ctx, double tol, int max_steps,
  * deriv_out (nullable, n entries; declared below): at every temperature whose run converged
  * (to Delta < min(tol, 1e-6)), deriv_out[i] = ctmrg_fixed_point_derivative with
  * second_order = 1 (dF/dK, d2F/dK2 = dE/dK and dM/dK along the fixed point); zeros elsewhere.
+ * With the environment variable CTMRG_PROGRESS set (to anything but 0), every hundredth step of
+ * a temperature is reported on stderr.
  * Errors: CTMRG_E_INVALID_ARG (n < 0, a temperature not positive, max_steps < 2, tol < 0),
  * and those of ctmrg_step, ctmrg_observables and ctmrg_fixed_point_derivative, which stop the
  * sweep. */
@@ -216,16 +218,17 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *ctx, ctmrg_observables_t *out, double 
  * (tangent mode).  The state must be converged (Delta < 1e-6; the routine
  * then converges it further in FP64, in the gauge in which the kept
  * eigenvectors of consecutive steps are aligned inside every multiplet, until
- * P repeats element by element).  The tangent t = dx/dK solves t = J t + d_K Phi
+ * P repeats element by element).  The tangent t = dx/dK solves (I - J) t = d_K Phi
  * (J: the derivative of one step, with the kept eigenvectors' derivative
  * sum_i u_i (u_i^T dC' u_j) / (lambda_j - lambda_i) over the discarded
  * eigenpairs i of C', and the corner's tangent carried as a full symmetric
  * block, so that rotations inside the kept space -- degenerate or not -- are
  * treated as gauge), and dF/dK follows from F = -1/2 ln ||P~||_F at
- * the fixed point.  The iteration stops when the tangent changes by less than
- * 1e-12, or when ds (hence dF/dK) changes by less than 1e-14 relative over two
- * consecutive windows of ten iterations (slowly converging directions that do
- * not move F; tangent_change reports the rest).
+ * the fixed point.  The linear system is solved by restarted GMRES (64 Krylov
+ * vectors, classical Gram-Schmidt twice) with J t applied matrix-free, to a
+ * relative residual of 1e-12 (or, where restarts no longer reduce it, 1e-10),
+ * at most 3000 products J t; tangent_change reports max |J t + d_K Phi - t| at
+ * the solution.
  * Along the converged tangent the routine also differentiates the impurity
  * energy E of the plaquette (Sec. II; the product rule through the
  * environment sums, with dW/dK = -W h4) and the magnetization M (Eq. 5; the
@@ -237,9 +240,12 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *ctx, ctmrg_observables_t *out, double 
  * second_order == 2 returns instead the central difference of dF/dK at
  * K (1 +- 1e-4), each from its own converged fixed point (a cross-check, three
  * tangent solves).  The context's state, K and weight are left unchanged; work
- * memory (about 16 (q m_eff)^2 doubles plus a full eigensolver workspace) is
- * allocated on the first call and kept until ctmrg_destroy.  Runs in FP64
- * whatever the context's precision.
+ * memory (about 16 (q m_eff)^2 doubles, 69 tangent vectors of q m_eff^2 +
+ * m_eff^2 doubles for GMRES, and a full eigensolver workspace;
+ * ctmrg_extra_workspace_size) is allocated on the first call and kept until
+ * ctmrg_destroy.  Runs in FP64 whatever the context's precision.  With the
+ * environment variable CTMRG_PROGRESS set (to anything but 0), every tenth
+ * aligned step and every twentieth product J t is reported on stderr.
  * Errors: CTMRG_E_STATE if the state is not converged; CTMRG_E_NOT_CONVERGED
  * if the aligned fixed point or the tangent iteration does not converge;
  * CTMRG_E_NUMERICAL if the kept dimension changes or a multiplet is larger
@@ -249,9 +255,9 @@ typedef struct ctmrg_derivative_s {
     double dF_dK;          /* dF/dK, the energy per site                                      */
     double d2F_dK2;        /* d2F/dK2 (second_order 1: dE/dK; 2: central difference; 0: 0)     */
     double gauge_residual; /* max |P_next - P| of the aligned fixed point                     */
-    double tangent_change; /* max change of the tangent in its last iteration                 */
+    double tangent_change; /* max |J t + d_K Phi - t| of the tangent solution                 */
     int aligned_steps;     /* FP64 steps taken to the aligned fixed point                     */
-    int iterations;        /* tangent iterations                                              */
+    int iterations;        /* products J t of the tangent solve                               */
     int n_eigen;           /* eigenpairs of C' used (those above rank_tol |lambda_1|)          */
     double E;              /* impurity energy of the plaquette at the aligned fixed point      */
     double M;              /* magnetization (Eq. 5) at the aligned fixed point                 */
@@ -286,8 +292,9 @@ ctmrg_status ctmrg_workspace_size(int q, int m, const ctmrg_options *opt, size_t
  * ctmrg_destroy): *observables_bytes by ctmrg_observables (the Lanczos vectors of
  * xi_e, min(400, m^2) + 1 vectors of m^2 doubles, and the products' buffers), and
  * *derivative_bytes by ctmrg_fixed_point_derivative / ctmrg_backward (the tangent
- * solve's 12 (q m)^2 + 13 q m^2 doubles and an eigensolver workspace for all q m
- * eigenvectors), both at their largest (m_eff = m).  Either pointer may be NULL. */
+ * solve's 12 (q m)^2 + 13 q m^2 doubles, its GMRES vectors, 69 of q m^2 + m^2
+ * doubles, and an eigensolver workspace for all q m eigenvectors), both at their
+ * largest (m_eff = m).  Either pointer may be NULL. */
 ctmrg_status ctmrg_extra_workspace_size(int q, int m, const ctmrg_options *opt, size_t *observables_bytes,
                                         size_t *derivative_bytes);
 

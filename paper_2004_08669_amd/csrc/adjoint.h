@@ -6,8 +6,8 @@
 // site at a fixed point x* is F = beta f = -1/2 ln s*, s* = ||P~(x*)||_F.  Its
 // total derivative is
 //     dF/dK = -1/2 (d s / dK) / s*,   ds/dK = d_K s + d_x s . t,
-// where the tangent t = dx*/dK solves t = J t + d_K Phi (J = d Phi / dx at x*),
-// found by iterating t <- J t + d_K Phi.  J t is the hand-written directional
+// where the tangent t = dx*/dK solves (I - J) t = d_K Phi (J = d Phi / dx at x*),
+// by restarted GMRES with J t applied matrix-free.  J t is the hand-written directional
 // derivative of one step: the product rule through the contractions, and the
 // derivative of the kept eigenvectors of C',
 //     dU_j = sum_i u_i (u_i^T dC' u_j) / (lambda_j - lambda_i)   (i discarded),
@@ -57,10 +57,10 @@ struct AdjInputs {
     const double *V = nullptr;        // spin vectors (q x dim), for M
     int dim = 0, bc = 0, s0 = 0;      // boundary condition and the boundary spin, for M
     double gap_tol = 1e-10, rank_tol = 1e-13;
-    int max_aligned_steps = 500, max_iterations = 3000;
+    int max_aligned_steps = 500, max_iterations = 3000;  // aligned steps; products J t of the tangent solve
     double gauge_tol = 1e-10;         // element-wise |P_next - P| of the aligned fixed point
-    double tangent_tol = 1e-12;       // max change of the tangent between iterations (or ds settled, see
-                                      // adjoint_dFdK)
+    double tangent_tol = 1e-12;       // GMRES: ||d_K Phi - (I - J) t|| / ||d_K Phi||
+    int restart = 64;                 // GMRES restart length
 };
 
 struct AdjResult {
@@ -86,13 +86,17 @@ struct AdjWork {
     double *T1 = nullptr, *Bm = nullptr, *R = nullptr, *dU = nullptr;
     double *part = nullptr, *scal = nullptr, *hscal = nullptr;
     double *W2 = nullptr, *obsv = nullptr, *hobsv = nullptr;  // W h4^2 (q^4); prob, d prob (device, host)
+    // GMRES of the tangent: Krylov basis (restart + 1 vectors of L = d n + d^2), right-hand side,
+    // solution, J times a vector, projections (device, host)
+    int restart = 0;
+    double *Vk = nullptr, *gb = nullptr, *gx = nullptr, *gy = nullptr, *gh = nullptr, *hgh = nullptr;
     PostOut *post = nullptr, *hpost = nullptr;
     unsigned *err = nullptr;
     EigWork eig;
 };
 
-hipError_t adj_alloc(AdjWork &w, int q, int d, int band);
-size_t adj_bytes(int q, int d, int band);  // what adj_alloc allocates
+hipError_t adj_alloc(AdjWork &w, int q, int d, int band, int restart = 64);
+size_t adj_bytes(int q, int d, int band, int restart = 64);  // what adj_alloc allocates
 void adj_free(AdjWork &w);
 
 // Returns 0 on success; otherwise a ctmrg_status value with a message in *msg.

@@ -1,5 +1,7 @@
 // Derivative of the CTMRG fixed point with respect to K; see adjoint.h.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <vector>
@@ -325,6 +327,53 @@ __global__ void __launch_bounds__(256) spin_tangent_kernel(const double *U, cons
     }
 }
 
+// part[i][b] = workgroup b's share of <V_i, x> for the nv vectors V_i (stride L) of a Krylov basis
+__global__ void __launch_bounds__(256) multi_dot_partial_kernel(const double *V, long L, int nv, const double *x,
+                                                                double *part)
+{
+    __shared__ double red[4];
+    for (int i = 0; i < nv; ++i) {
+        const double *v = V + (long)i * L;
+        double acc = 0.0;
+        for (long k = blockIdx.x * 256L + threadIdx.x; k < L; k += (long)gridDim.x * 256) acc += v[k] * x[k];
+        acc = block_sum<256>(acc, red);
+        if (threadIdx.x == 0) part[(long)i * gridDim.x + blockIdx.x] = acc;
+    }
+}
+
+// h[i] = sum of the np partials of vector i (fixed order)
+__global__ void multi_dot_finalize_kernel(const double *part, int np, int nv, double *h)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    double acc = 0.0;
+    for (int b = 0; b < np; ++b) acc += part[(long)i * np + b];
+    h[i] = acc;
+}
+
+// x += sign * sum_i c[i] V_i
+__global__ void lincomb_kernel(const double *V, long L, int nv, const double *c, double sign, double *x)
+{
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < L; k += (long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int i = 0; i < nv; ++i) acc += c[i] * V[(long)i * L + k];
+        x[k] += sign * acc;
+    }
+}
+
+// r = a - b + c
+__global__ void amb_kernel(const double *a, const double *b, const double *c, double *r, long n)
+{
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        r[k] = a[k] - b[k] + (c ? c[k] : 0.0);
+}
+
+// x *= a
+__global__ void scal_kernel(double *x, long n, double a)
+{
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) x[k] *= a;
+}
+
 // ---------------------------------------------------------------- host helpers
 
 hipError_t reduce_dot(const double *x, const double *y, long n, double *part, double *out, int op, double scale,
@@ -380,9 +429,10 @@ namespace {
 struct AdjReq { double **p; size_t n; };
 
 // The device buffers of the derivative (element counts), for n = q d.
-std::vector<AdjReq> adj_requests(AdjWork &w, int q, int d)
+std::vector<AdjReq> adj_requests(AdjWork &w, int q, int d, int restart)
 {
     const size_t n = (size_t)q * d, dd = (size_t)d;
+    const size_t L = dd * n + dd * dd;
     return {
         {&w.A, dd * n}, {&w.OA, dd * n}, {&w.Pt, dd * n}, {&w.om, n + 8}, {&w.omn, n + 8}, {&w.zero, n + 8},
         {&w.Ucur, n * dd}, {&w.Uprev, n * dd}, {&w.Mov, dd * dd},
@@ -391,29 +441,32 @@ std::vector<AdjReq> adj_requests(AdjWork &w, int q, int d)
         {&w.dA, dd * n}, {&w.dAn, dd * n}, {&w.dOA, dd * n}, {&w.dom, dd * dd}, {&w.domn, dd * dd},
         {&w.dX, n * n}, {&w.dC, n * n}, {&w.dY, n * n}, {&w.dZ, n * n}, {&w.dPt, dd * n},
         {&w.T1, n * dd}, {&w.Bm, n * dd}, {&w.R, n * dd}, {&w.dU, n * dd},
-        {&w.part, 1024}, {&w.scal, NSCAL + n + 8}, {&w.W2, (size_t)q * q * q * q}, {&w.obsv, 4 * (size_t)q + 8},
+        {&w.part, std::max<size_t>(1024, 256 * ((size_t)restart + 2))}, {&w.scal, NSCAL + n + 8},
+        {&w.W2, (size_t)q * q * q * q}, {&w.obsv, 4 * (size_t)q + 8},
+        {&w.Vk, L * ((size_t)restart + 1)}, {&w.gb, L}, {&w.gx, L}, {&w.gy, L}, {&w.gh, 2 * (size_t)restart + 8},
     };
 }
 
 }  // namespace
 
-size_t adj_bytes(int q, int d, int band)
+size_t adj_bytes(int q, int d, int band, int restart)
 {
     AdjWork w;
     size_t s = 0;
-    for (const AdjReq &r : adj_requests(w, q, d)) s += sizeof(double) * std::max<size_t>(r.n, 1);
+    for (const AdjReq &r : adj_requests(w, q, d, restart)) s += sizeof(double) * std::max<size_t>(r.n, 1);
     s += sizeof(PostOut) + sizeof(unsigned) * 4;
     return s + eig_bytes(q * d, q * d, band);
 }
 
-hipError_t adj_alloc(AdjWork &w, int q, int d, int band)
+hipError_t adj_alloc(AdjWork &w, int q, int d, int band, int restart)
 {
     w.q = q;
     w.d = d;
     w.n = q * d;
     w.band = band;
+    w.restart = restart;
     const size_t n = (size_t)w.n;
-    for (auto &r : adj_requests(w, q, d)) {
+    for (auto &r : adj_requests(w, q, d, restart)) {
         hipError_t e = hipMalloc((void **)r.p, sizeof(double) * std::max<size_t>(r.n, 1));
         if (e != hipSuccess) return e;
     }
@@ -421,6 +474,7 @@ hipError_t adj_alloc(AdjWork &w, int q, int d, int band)
     if (e == hipSuccess) e = hipHostMalloc((void **)&w.hpost, sizeof(PostOut), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w.hscal, sizeof(double) * NSCAL, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w.hobsv, sizeof(double) * (4 * (size_t)q + 8), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&w.hgh, sizeof(double) * (2 * (size_t)restart + 8), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void **)&w.err, sizeof(unsigned) * 4);
     if (e == hipSuccess) e = eig_alloc(w.eig, w.n, w.n, band);
     if (e == hipSuccess) e = hipMemset(w.zero, 0, sizeof(double) * (n + 8));
@@ -431,13 +485,14 @@ void adj_free(AdjWork &w)
 {
     double *bufs[] = {w.A, w.OA, w.Pt, w.om, w.omn, w.zero, w.Ucur, w.Uprev, w.Mov, w.X, w.C, w.Y, w.Z, w.Cb,
                       w.Zb, w.Uall, w.M3, w.lam, w.sel, w.dA, w.dAn, w.dOA, w.dom, w.domn, w.dX, w.dC, w.dY, w.dZ,
-                      w.dPt, w.T1, w.Bm, w.R, w.dU, w.part, w.scal, w.W2, w.obsv};
+                      w.dPt, w.T1, w.Bm, w.R, w.dU, w.part, w.scal, w.W2, w.obsv, w.Vk, w.gb, w.gx, w.gy, w.gh};
     for (double *p : bufs)
         if (p) (void)hipFree(p);
     if (w.post) (void)hipFree(w.post);
     if (w.hpost) (void)hipHostFree(w.hpost);
     if (w.hscal) (void)hipHostFree(w.hscal);
     if (w.hobsv) (void)hipHostFree(w.hobsv);
+    if (w.hgh) (void)hipHostFree(w.hgh);
     if (w.err) (void)hipFree(w.err);
     eig_free(w.eig);
     const int band = w.band;
@@ -450,6 +505,9 @@ void adj_free(AdjWork &w)
 int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s, std::string *msg)
 {
     const int q = in.q, d = in.d, n = q * d;
+    // with CTMRG_PROGRESS set in the environment, long solves report their progress on stderr
+    const char *pe = getenv("CTMRG_PROGRESS");
+    const bool progress = pe && *pe && *pe != '0';
     const int q2 = q * q;
     hipError_t e = hipSuccess;
 #define ADJ_CK(expr)                                                          \
@@ -475,9 +533,9 @@ int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s,
         (void)hipMemset(w.err, 0, sizeof(unsigned));
         return h | eig_take_errors(w.eig);
     };
-    if (w.q != q || w.d != d || !w.A) {
+    if (w.q != q || w.d != d || !w.A || w.restart != in.restart) {
         adj_free(w);
-        ADJ_CK(adj_alloc(w, q, d, w.band));
+        ADJ_CK(adj_alloc(w, q, d, w.band, in.restart));
     }
     ADJ_CK(hipMemsetAsync(w.err, 0, sizeof(unsigned), s));
     hipLaunchKernelGGL(compact_kernel, dim3(grid_for((long)d * n)), dim3(256), 0, s, in.A, in.omega, in.U, q, in.m, d,
@@ -522,6 +580,8 @@ int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s,
             *msg = "non-finite state in an aligned step";
             return CTMRG_E_NUMERICAL;
         }
+        if (progress && k % 10 == 9)
+            fprintf(stderr, "[ctmrg derivative] aligned step %d: |P_next - P| = %.3e\n", k + 1, resid);
         if (k >= 1 && resid < in.gauge_tol) break;
     }
     res->aligned_steps = k + 1;
@@ -572,30 +632,27 @@ int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s,
     res->F = -0.5 * log(sstar);
     res->n_eigen = np;
 
-    // ---- 3. tangent iteration t <- J t + d_K Phi (dK = 1)
+    // ---- 3. the tangent: (I - J) t = d_K Phi (dK = 1), by restarted GMRES
     const long nd = (long)d * n;
-    ADJ_CK(hipMemsetAsync(w.dA, 0, sizeof(double) * nd, s));
-    ADJ_CK(hipMemsetAsync(w.dom, 0, sizeof(double) * d * d, s));
-    double change = INFINITY, ds = 0.0, ds_prev[2] = {NAN, NAN};
-    bool functional_converged = false;
-    int it = 0;
+    const long L = nd + (long)d * d;  // a tangent vector: dA (d x n), then dOm (d x d)
 #define TF_CK(expr)                          \
     do {                                     \
         hipError_t e3 = (expr);              \
         if (e3 != hipSuccess) return e3;     \
     } while (0)
-    // The front of one tangent step from (dA, dOm): dX, dC', the eigen part (dOm of the
-    // next state in domn, dU)
-    auto tangent_front = [&]() -> hipError_t {
+    // The front of one tangent step from (tA, tOm): dX, dC', the eigen part (the next state's
+    // corner tangent into oOm, and dU).  with_b adds the K-derivative of the weights (d_K Phi).
+    auto tangent_front = [&](const double *tA, const double *tOm, double *oOm, bool with_b) -> hipError_t {
         // dOA = dOmega A + Omega dA (dOmega: the full symmetric corner tangent)
-        hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(nd)), dim3(256), 0, s, w.om, w.dA, d, (long)n, w.dOA);
-        TF_CK(gemm_mfma(GEMM_SMALL, A_RM{w.dom, d}, B_RM{w.A, n}, EpiAxpby{w.dOA, n, 1.0, 1.0}, d, n, d, s));
+        hipLaunchKernelGGL(scale_rows_kernel, dim3(grid_for(nd)), dim3(256), 0, s, w.om, tA, d, (long)n, w.dOA);
+        TF_CK(gemm_mfma(GEMM_SMALL, A_RM{tOm, d}, B_RM{w.A, n}, EpiAxpby{w.dOA, n, 1.0, 1.0}, d, n, d, s));
         // dX = dA^T (Omega A) + A^T (dOmega A + Omega dA)
-        TF_CK(gemm_mfma(GEMM_LARGE, A_T{w.dA, n}, B_RM{w.OA, n}, EpiStore{w.dX, n, 1.0}, n, n, d, s));
+        TF_CK(gemm_mfma(GEMM_LARGE, A_T{tA, n}, B_RM{w.OA, n}, EpiStore{w.dX, n, 1.0}, n, n, d, s));
         TF_CK(gemm_mfma(GEMM_LARGE, A_T{w.A, n}, B_RM{w.dOA, n}, EpiAxpby{w.dX, n, 1.0, 1.0}, n, n, d, s));
-        // dC' = W-mix(dX) + W'-mix(X*)
+        // dC' = W-mix(dX) (+ W'-mix(X*))
         TF_CK(weight_mix(in.W, w.dX, w.dC, q, d, s));
-        hipLaunchKernelGGL(axpy_kernel, dim3(grid_for((long)n * n)), dim3(256), 0, s, w.dC, w.Cb, (long)n * n);
+        if (with_b)
+            hipLaunchKernelGGL(axpy_kernel, dim3(grid_for((long)n * n)), dim3(256), 0, s, w.dC, w.Cb, (long)n * n);
         // eigenvector and eigenvalue derivatives
         TF_CK(gemm_mfma(GEMM_TALL, A_RM{w.dC, n}, B_RM{w.Ucur, d}, EpiStore{w.T1, d, 1.0}, n, d, n, s));
         TF_CK(gemm_mfma(GEMM_TALL, A_T{w.Uall, n}, B_RM{w.T1, d}, EpiStore{w.Bm, d, 1.0}, np, d, n, s));
@@ -605,60 +662,160 @@ int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s,
         }
         TF_CK(reduce_dot(w.M3, w.dC, (long)n * n, w.part, w.scal + S_DNC, OP_SUM, 1.0 / (nC * nC * nC), s));
         hipLaunchKernelGGL(eigen_tangent_kernel, dim3(grid_for((long)np * d)), dim3(256), 0, s, w.Bm, np, d, w.lam,
-                           nC, w.scal + S_DNC, w.domn);
+                           nC, w.scal + S_DNC, oOm);
         TF_CK(gemm_mfma(GEMM_TALL, A_RM{w.Uall, n}, B_RM{w.Bm, d}, EpiStore{w.dU, d, 1.0}, n, d, np, s));
         if (np < n)
             hipLaunchKernelGGL(nullspace_tangent_kernel, dim3(grid_for((long)n * d)), dim3(256), 0, s, w.dU, w.R,
                                (long)n, d, w.lam);
         return hipSuccess;
     };
-    for (it = 0; it < in.max_iterations; ++it) {
-        ADJ_CK(tangent_front());
-        // dY = dA^T U + A^T dU,  dZ = W-mix(dY) + W'-mix(Y*),  dP~ = dU^T Z* + U^T dZ
-        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.dA, n}, B_Ublk{w.Ucur, d}, EpiStore{w.dY, n, 1.0}, n, n, d, s));
-        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.A, n}, B_Ublk{w.dU, d}, EpiAxpby{w.dY, n, 1.0, 1.0}, n, n, d, s));
-        ADJ_CK(weight_mix(in.W, w.dY, w.dZ, q, d, s));
-        hipLaunchKernelGGL(axpy_kernel, dim3(grid_for((long)n * n)), dim3(256), 0, s, w.dZ, w.Zb, (long)n * n);
-        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.dU, d}, B_RM{w.Z, n}, EpiStore{w.dPt, n, 1.0}, d, n, n, s));
-        ADJ_CK(gemm_mfma(GEMM_LARGE, A_T{w.Ucur, d}, B_RM{w.dZ, n}, EpiAxpby{w.dPt, n, 1.0, 1.0}, d, n, n, s));
-        // normalization by the Frobenius norm
-        ADJ_CK(reduce_dot(w.Pt, w.dPt, nd, w.part, w.scal + S_DS, OP_SUM, 1.0 / sstar, s));
+    // One tangent step y = J x (+ d_K Phi with with_b); x and y are tangent vectors of length L.
+    auto step_t = [&](const double *x, double *y, bool with_b) -> hipError_t {
+        const double *tA = x, *tOm = x + nd;
+        TF_CK(tangent_front(tA, tOm, y + nd, with_b));
+        // dY = dA^T U + A^T dU,  dZ = W-mix(dY) (+ W'-mix(Y*)),  dP~ = dU^T Z* + U^T dZ
+        TF_CK(gemm_mfma(GEMM_LARGE, A_T{tA, n}, B_Ublk{w.Ucur, d}, EpiStore{w.dY, n, 1.0}, n, n, d, s));
+        TF_CK(gemm_mfma(GEMM_LARGE, A_T{w.A, n}, B_Ublk{w.dU, d}, EpiAxpby{w.dY, n, 1.0, 1.0}, n, n, d, s));
+        TF_CK(weight_mix(in.W, w.dY, w.dZ, q, d, s));
+        if (with_b)
+            hipLaunchKernelGGL(axpy_kernel, dim3(grid_for((long)n * n)), dim3(256), 0, s, w.dZ, w.Zb, (long)n * n);
+        TF_CK(gemm_mfma(GEMM_LARGE, A_T{w.dU, d}, B_RM{w.Z, n}, EpiStore{w.dPt, n, 1.0}, d, n, n, s));
+        TF_CK(gemm_mfma(GEMM_LARGE, A_T{w.Ucur, d}, B_RM{w.dZ, n}, EpiAxpby{w.dPt, n, 1.0, 1.0}, d, n, n, s));
+        // normalization by the Frobenius norm (ds into S_DS)
+        TF_CK(reduce_dot(w.Pt, w.dPt, nd, w.part, w.scal + S_DS, OP_SUM, 1.0 / sstar, s));
         hipLaunchKernelGGL(tangent_norm_kernel, dim3(grid_for(nd)), dim3(256), 0, s, w.dPt, w.Pt, nd,
-                           w.scal + S_NORM, w.scal + S_DS, w.dAn);
-        ADJ_CK(reduce_maxdiff(w.dAn, w.dA, nd, w.part, w.scal + S_CHANGE, false, s));
-        ADJ_CK(reduce_maxdiff(w.domn, w.dom, (long)d * d, w.part, w.scal + S_CHANGE, true, s));
-        std::swap(w.dA, w.dAn);
-        std::swap(w.dom, w.domn);
-        if (it % 10 == 9 || it + 1 == in.max_iterations) {
-            ADJ_CK(fetch_scal());
-            change = w.hscal[S_CHANGE];
-            ds = w.hscal[S_DS];
-            if (!std::isfinite(change) || !std::isfinite(ds)) {
-                *msg = "non-finite tangent";
+                           w.scal + S_NORM, w.scal + S_DS, y);
+        return hipGetLastError();
+    };
+    const int R = std::max(1, in.restart);
+    const int ndot = grid_for(L) < 256 ? grid_for(L) : 256;
+    // h[0 .. nv) = V[0 .. nv)^T x on the device, and on the host when `fetch`
+    auto project = [&](int nv, const double *x, double *h) -> hipError_t {
+        hipLaunchKernelGGL(multi_dot_partial_kernel, dim3(ndot), dim3(256), 0, s, w.Vk, L, nv, x, w.part);
+        hipLaunchKernelGGL(multi_dot_finalize_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, w.part, ndot, nv, h);
+        return hipGetLastError();
+    };
+    auto norm2 = [&](const double *x) -> double {
+        if (reduce_dot(x, x, L, w.part, w.gh + 2 * R + 6, OP_SQRT, 1.0, s) != hipSuccess) return NAN;
+        if (hipMemcpyAsync(w.hgh + 2 * R + 6, w.gh + 2 * R + 6, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return NAN;
+        return w.hgh[2 * R + 6];
+    };
+    // b = d_K Phi: the step with the K-derivative applied to t = 0
+    ADJ_CK(hipMemsetAsync(w.gx, 0, sizeof(double) * L, s));
+    ADJ_CK(step_t(w.gx, w.gb, true));
+    const double bnorm = norm2(w.gb);
+    if (!std::isfinite(bnorm) || !(bnorm > 0.0)) {
+        *msg = "non-finite or zero right-hand side of the tangent";
+        return CTMRG_E_NUMERICAL;
+    }
+    std::vector<double> H((size_t)(R + 1) * R, 0.0), cs(R), sn(R), g(R + 1), yv(R);
+    double gres = bnorm, true_prev = INFINITY;
+    int it = 0;
+    bool converged = false;
+    while (!converged && it <= in.max_iterations) {
+        // r = b - (x - J x), the first Krylov vector
+        if (it == 0) {
+            ADJ_CK(hipMemcpyAsync(w.Vk, w.gb, sizeof(double) * L, hipMemcpyDeviceToDevice, s));
+        } else {
+            ADJ_CK(step_t(w.gx, w.gy, false));
+            hipLaunchKernelGGL(amb_kernel, dim3(grid_for(L)), dim3(256), 0, s, w.gb, w.gx, w.gy, w.Vk, L);
+        }
+        const double beta = norm2(w.Vk);
+        if (!std::isfinite(beta)) {
+            *msg = "non-finite tangent residual";
+            return CTMRG_E_NUMERICAL;
+        }
+        gres = beta;
+        // converged, or a restart that no longer reduces the true residual once it is within 1e-10
+        // of the right-hand side (the attainable accuracy of the FP64 products)
+        if (beta <= in.tangent_tol * bnorm || (beta <= 1e-10 * bnorm && beta > 0.5 * true_prev)) {
+            converged = true;
+            break;
+        }
+        true_prev = beta;
+        if (it >= in.max_iterations) break;
+        hipLaunchKernelGGL(scal_kernel, dim3(grid_for(L)), dim3(256), 0, s, w.Vk, L, 1.0 / beta);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jn = 0;
+        for (int j = 0; j < R && it < in.max_iterations; ++j) {
+            double *vj = w.Vk + (long)j * L, *vn = w.Vk + (long)(j + 1) * L;
+            // vn = (I - J) vj, orthogonalized twice against v_0 .. v_j (classical Gram-Schmidt)
+            ADJ_CK(step_t(vj, w.gy, false));
+            hipLaunchKernelGGL(amb_kernel, dim3(grid_for(L)), dim3(256), 0, s, vj, w.gy, (const double *)nullptr, vn, L);
+            for (int pass = 0; pass < 2; ++pass) {
+                ADJ_CK(project(j + 1, vn, w.gh + pass * (R + 2)));
+                hipLaunchKernelGGL(lincomb_kernel, dim3(grid_for(L)), dim3(256), 0, s, w.Vk, L, j + 1,
+                                   w.gh + pass * (R + 2), -1.0, vn);
+            }
+            ADJ_CK(hipMemcpyAsync(w.hgh, w.gh, sizeof(double) * 2 * (R + 2), hipMemcpyDeviceToHost, s));
+            const double hn = norm2(vn);  // synchronizes the stream
+            if (!std::isfinite(hn)) {
+                *msg = "non-finite Krylov vector in the tangent solve";
                 return CTMRG_E_NUMERICAL;
             }
-            if (change < in.tangent_tol) break;
-            // Directions of the tangent that converge slowly without moving s: stop once ds itself
-            // has settled over two consecutive windows of ten iterations.
-            const double tol_ds = 1e-14 * fabs(ds);
-            if (it >= 99 && fabs(ds - ds_prev[0]) <= tol_ds && fabs(ds_prev[0] - ds_prev[1]) <= tol_ds) {
-                functional_converged = true;
-                break;
+            ++it;
+            double *hc = H.data() + (size_t)j * (R + 1);  // column j of the Hessenberg matrix
+            for (int i = 0; i <= j; ++i) hc[i] = w.hgh[i] + w.hgh[R + 2 + i];
+            hc[j + 1] = hn;
+            // the previous rotations, then a new one that annihilates hc[j + 1]
+            for (int i = 0; i < j; ++i) {
+                const double a = hc[i], b2 = hc[i + 1];
+                hc[i] = cs[i] * a + sn[i] * b2;
+                hc[i + 1] = -sn[i] * a + cs[i] * b2;
             }
-            ds_prev[1] = ds_prev[0];
-            ds_prev[0] = ds;
+            const double rr = std::hypot(hc[j], hc[j + 1]);
+            cs[j] = rr > 0.0 ? hc[j] / rr : 1.0;
+            sn[j] = rr > 0.0 ? hc[j + 1] / rr : 0.0;
+            hc[j] = rr;
+            hc[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            gres = fabs(g[j + 1]);
+            jn = j + 1;
+            if (progress && it % 20 == 0)
+                fprintf(stderr, "[ctmrg derivative] GMRES product %d: relative residual %.3e\n", it, gres / bnorm);
+            if (gres <= in.tangent_tol * bnorm || hn <= 1e-300) break;
+            hipLaunchKernelGGL(scal_kernel, dim3(grid_for(L)), dim3(256), 0, s, vn, L, 1.0 / hn);
         }
+        // x += V y with H y = g (upper triangular, jn x jn)
+        for (int i = jn - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int c = i + 1; c < jn; ++c) acc -= H[(size_t)c * (R + 1) + i] * yv[c];
+            yv[i] = acc / H[(size_t)i * (R + 1) + i];
+        }
+        ADJ_CK(hipMemcpyAsync(w.gh, yv.data(), sizeof(double) * jn, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(lincomb_kernel, dim3(grid_for(L)), dim3(256), 0, s, w.Vk, L, jn, w.gh, 1.0, w.gx);
+        ADJ_CK(hipStreamSynchronize(s));
+        // the next pass through the loop measures the true residual of the updated solution
     }
-    res->iterations = it + 1;
+    // the true residual and dF/dK from one more step t -> J t + d_K Phi of the solution
+    ADJ_CK(step_t(w.gx, w.gy, true));
+    ADJ_CK(reduce_maxdiff(w.gy, w.gx, L, w.part, w.scal + S_CHANGE, false, s));
+    ADJ_CK(fetch_scal());
+    const double change = w.hscal[S_CHANGE], ds = w.hscal[S_DS];
+    res->iterations = it;
     res->tangent_change = change;
     res->dFdK = -0.5 * ds / sstar;
-    if (!(change < in.tangent_tol) && !functional_converged) {
-        *msg = "the tangent iteration did not converge (change " + std::to_string(change) + ")";
+    if (!std::isfinite(change) || !std::isfinite(ds)) {
+        *msg = "non-finite tangent";
+        return CTMRG_E_NUMERICAL;
+    }
+    if (!converged) {
+        char buf[160];
+        snprintf(buf, sizeof(buf), "the tangent solve did not converge (relative residual %.3e after %d products)",
+                 gres / bnorm, it);
+        *msg = buf;
         return CTMRG_E_NOT_CONVERGED;
     }
+    // the state tangent for the observables below
+    ADJ_CK(hipMemcpyAsync(w.dA, w.gx, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
+    ADJ_CK(hipMemcpyAsync(w.dom, w.gx + nd, sizeof(double) * d * d, hipMemcpyDeviceToDevice, s));
 
     // ---- 4. E and M at x* and their derivatives along the converged tangent (dK = 1)
-    ADJ_CK(tangent_front());  // dX, dC', domn and dU of the final (dA, dOm)
+    ADJ_CK(tangent_front(w.dA, w.dom, w.domn, true));  // dX, dC', domn and dU of the final (dA, dOm)
     // C' (into Z, free now), Om~ X dOm~ (as X reshaped to (q n) x d times dOm, into dY),
     // (W h4^2)-mix(X) (into dZ) and (W h4)-mix(dX) (into Zb)
     ADJ_CK(weight_mix(in.W, w.X, w.Z, q, d, s));

@@ -1,5 +1,7 @@
 // Context, step orchestration and the C ABI declared in include/ctmrg.h.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -579,6 +581,9 @@ ctmrg_status ctmrg_sweep(ctmrg_ctx *c, int n, const double *T, double tol, int m
     if (!c || n < 0 || (n > 0 && (!T || !out)) || max_steps < 2 || !(tol >= 0.0)) return CTMRG_E_INVALID_ARG;
     for (int i = 0; i < n; ++i)
         if (!(T[i] > 0.0) || !std::isfinite(T[i])) return fail(c, CTMRG_E_INVALID_ARG, "temperatures must be positive");
+    // with CTMRG_PROGRESS set in the environment, every hundredth step is reported on stderr
+    const char *pe = getenv("CTMRG_PROGRESS");
+    const bool progress = pe && *pe && *pe != '0';
     for (int i = 0; i < n; ++i) {
         const double K = 1.0 / T[i];
         if (warm_start && (i > 0 || c->steps > 0)) {
@@ -598,6 +603,8 @@ ctmrg_status ctmrg_sweep(ctmrg_ctx *c, int n, const double *T, double tol, int m
             const ctmrg_status st = one_step(c);
             if (st != CTMRG_OK) return st;
             ++taken;
+            if (progress && taken % 100 == 0)
+                fprintf(stderr, "[ctmrg sweep] T = %.6f: step %d, Delta %.3e\n", T[i], taken, c->delta);
             if (taken >= 2 && c->delta < tol) {
                 conv = true;
                 break;

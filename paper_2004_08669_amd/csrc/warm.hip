@@ -52,11 +52,12 @@ __global__ void scale_rows_by_kernel(double *T, long ld, int rows, int cols, con
 // the inverse of that factor into Linv (CB x CB, row-major, zero above the diagonal).  A pivot
 // that is not positive raises flag 1 and is replaced by a tiny positive number.  The block
 // stays in LDS: right-looking by columns, the trailing update on a 16 x 16 thread grid; the
-// inverse row by row, all columns of a row at once.
+// inverse by forward substitution, one column per thread.
 __global__ void __launch_bounds__(256) chol_diag_kernel(double *G, int ld, int p0, int nb, double *Linv, unsigned *err)
 {
     __shared__ double A[CB][CB + 1];
     __shared__ double Li[CB][CB + 1];
+    __shared__ double dg[CB];
     const int tid = threadIdx.x;
     for (int idx = tid; idx < CB * CB; idx += 256) {
         const int i = idx / CB, j = idx - i * CB;
@@ -64,34 +65,40 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(double *G, int ld, int p
         Li[i][j] = 0.0;
     }
     __syncthreads();
+    // Right-looking factorization with one barrier per column: step j reads column j unscaled,
+    // updates the trailing lower triangle with A[i][j] A[l][j] / d, and writes the scaled column
+    // L[i][j] = A[i][j] / sqrt(d) to the unused upper triangle (A[j][i]) and sqrt(d) to dg[j];
+    // nothing a step writes is read in the same step.
     const int tx = tid & 15, ty = tid >> 4;
     for (int j = 0; j < nb; ++j) {
         const double d = A[j][j];
-        const double piv = sqrt(d > 0.0 ? d : 1e-300);
-        __syncthreads();
+        const bool bad = !(d > 0.0);
+        const double dd = bad ? 1e-300 : d;
+        const double piv = sqrt(dd), inv = 1.0 / piv, invd = 1.0 / dd;
         if (tid == 0) {
-            if (!(d > 0.0)) raise_error(err, 1u);
-            A[j][j] = piv;
+            if (bad) raise_error(err, 1u);
+            dg[j] = piv;
         }
-        for (int i = j + 1 + tid; i < nb; i += 256) A[i][j] /= piv;
-        __syncthreads();
         for (int i = j + 1 + ty; i < nb; i += 16) {
-            const double aij = A[i][j];
+            const double aij = A[i][j] * invd;
             for (int l = j + 1 + tx; l <= i; l += 16) A[i][l] -= aij * A[l][j];
         }
+        for (int i = j + 1 + tid; i < nb; i += 256) A[j][i] = A[i][j] * inv;
         __syncthreads();
     }
-    for (int i = 0; i < nb; ++i) {
-        for (int c = tid; c <= i; c += 256) {
+    // L^{-1} by forward substitution, one column per thread (a column depends on itself only)
+    if (tid < nb) {
+        const int c = tid;
+        for (int i = c; i < nb; ++i) {
             double acc = (i == c) ? 1.0 : 0.0;
-            for (int t = c; t < i; ++t) acc -= A[i][t] * Li[t][c];
-            Li[i][c] = acc / A[i][i];
+            for (int t = c; t < i; ++t) acc -= A[t][i] * Li[t][c];
+            Li[i][c] = acc / dg[i];
         }
-        __syncthreads();
     }
+    __syncthreads();
     for (int idx = tid; idx < nb * nb; idx += 256) {
         const int i = idx / nb, j = idx - i * nb;
-        G[(long)(p0 + i) * ld + p0 + j] = (j <= i) ? A[i][j] : 0.0;
+        G[(long)(p0 + i) * ld + p0 + j] = (j < i) ? A[j][i] : (j == i ? dg[i] : 0.0);
     }
     for (int idx = tid; idx < CB * CB; idx += 256) {
         const int i = idx / CB, j = idx - i * CB;

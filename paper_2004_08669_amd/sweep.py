@@ -34,9 +34,12 @@ def vertex_set(name: str) -> np.ndarray:
             "tetrahedron": I.tetrahedron, "ising": I.ising}[name]()
 
 
-def run(V, m: int, Ts, tol: float, max_steps: int, fd_every: int, dK: float, log=sys.stderr) -> dict:
+def run(V, m: int, Ts, tol: float, max_steps: int, fd_every: int, dK: float, log=sys.stderr,
+        precision: str = "fp64", eig: str = "two_stage", gap_tol=None) -> dict:
+    """The sweep on one context of the given contraction precision and eigensolver (the derivative
+    itself always runs in FP64)."""
     Ts = [float(t) for t in Ts]
-    g = ctmrg.CTMRG(V, 1.0 / Ts[0], m)
+    g = ctmrg.CTMRG(V, 1.0 / Ts[0], m, precision=precision, eig=eig, gap_tol=gap_tol)
     points = []
     t0 = time.perf_counter()
     for i, T in enumerate(Ts):
@@ -56,7 +59,7 @@ def run(V, m: int, Ts, tol: float, max_steps: int, fd_every: int, dK: float, log
         for i in range(0, len(Ts), fd_every):
             T = Ts[i]
             K = 1.0 / T
-            h = ctmrg.CTMRG(V, K, m)
+            h = ctmrg.CTMRG(V, K, m, precision=precision, eig=eig, gap_tol=gap_tol)
             trio = h.sweep([T, 1.0 / (K + dK), 1.0 / (K - dK)], tol, max_steps, warm_start=True)
             h.close()
             Fp = (K + dK) * trio[1]["f"]
@@ -75,7 +78,8 @@ def run(V, m: int, Ts, tol: float, max_steps: int, fd_every: int, dK: float, log
                      "specific_heat": -(p["T"] ** -2) * d["d2F_dK2"],
                      "dF_dK_minus_E": d["dF_dK"] - p["E"], "tangent_iterations": d["iterations"],
                      "aligned_steps": d["aligned_steps"]})
-    return {"m": m, "q": int(np.asarray(V).shape[0]), "tol": tol, "seconds": total, "points": rows,
+    return {"m": m, "q": int(np.asarray(V).shape[0]), "tol": tol, "precision": precision, "eigensolver": eig,
+            "seconds": total, "points": rows,
             "central_difference_checks": checks,
             "max_abs_dF_dK_minus_E": max(abs(r["dF_dK_minus_E"]) for r in rows)}
 
@@ -92,10 +96,15 @@ def main(argv=None):
     ap.add_argument("--max-steps", type=int, default=3000)
     ap.add_argument("--fd-every", type=int, default=10, help="central-difference check every k-th temperature (0: none)")
     ap.add_argument("--dK", type=float, default=1e-5)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="contractions of the sweep's steps (the derivative runs in FP64)")
+    ap.add_argument("--eig", default="two_stage", choices=["two_stage", "warm"])
+    ap.add_argument("--gap-tol", type=float, default=None)
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     Ts = np.linspace(args.T0, args.T1, args.n)
-    res = run(vertex_set(args.vertices), args.m, Ts, args.tol, args.max_steps, args.fd_every, args.dK)
+    res = run(vertex_set(args.vertices), args.m, Ts, args.tol, args.max_steps, args.fd_every, args.dK,
+              precision=args.precision, eig=args.eig, gap_tol=args.gap_tol)
     res["vertices"] = args.vertices
     text = json.dumps(res)
     if args.out:
