@@ -192,6 +192,8 @@ ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *ctx, double tol, int max_steps,
  * deriv_out (nullable, n entries; declared below): at every temperature whose run converged
  * (to Delta < min(tol, 1e-6)), deriv_out[i] = ctmrg_fixed_point_derivative with
  * second_order = 1 (dF/dK, d2F/dK2 = dE/dK and dM/dK along the fixed point); zeros elsewhere.
+ * A derivative that fails with CTMRG_E_NOT_CONVERGED or CTMRG_E_NUMERICAL leaves zeros with
+ * that status in deriv_out[i].status, and the sweep continues.
  * With the environment variable CTMRG_PROGRESS set (to anything but 0), every hundredth step of
  * a temperature is reported on stderr.
  * Errors: CTMRG_E_INVALID_ARG (n < 0, a temperature not positive, max_steps < 2, tol < 0),
@@ -263,6 +265,7 @@ typedef struct ctmrg_derivative_s {
     double M;              /* magnetization (Eq. 5) at the aligned fixed point                 */
     double dE_dK;          /* total derivative of E along the fixed point (= d2F/dK2)          */
     double dM_dK;          /* total derivative of M along the fixed point                      */
+    int status;            /* CTMRG_OK; in a sweep, the status of a derivative that failed     */
 } ctmrg_derivative_t;
 
 ctmrg_status ctmrg_fixed_point_derivative(ctmrg_ctx *ctx, int second_order, ctmrg_derivative_t *out);

@@ -587,7 +587,10 @@ int adjoint_dFdK(AdjWork &w, const AdjInputs &in, AdjResult *res, hipStream_t s,
     res->aligned_steps = k + 1;
     res->gauge_residual = resid;
     if (!(resid < in.gauge_tol)) {
-        *msg = "the aligned fixed point did not converge (|P_next - P| = " + std::to_string(resid) + ")";
+        char buf[128];
+        snprintf(buf, sizeof(buf), "the aligned fixed point did not converge (|P_next - P| = %.3e after %d steps)", resid,
+                 res->aligned_steps);
+        *msg = buf;
         return CTMRG_E_NOT_CONVERGED;
     }
 

@@ -618,7 +618,13 @@ ctmrg_status ctmrg_sweep(ctmrg_ctx *c, int n, const double *T, double tol, int m
             deriv_out[i] = ctmrg_derivative_t{};
             if (conv && c->delta < 1e-6) {
                 const ctmrg_status sd = ctmrg_fixed_point_derivative(c, 1, deriv_out + i);
-                if (sd != CTMRG_OK) return sd;
+                if (sd == CTMRG_E_NOT_CONVERGED || sd == CTMRG_E_NUMERICAL) {
+                    deriv_out[i] = ctmrg_derivative_t{};
+                    deriv_out[i].status = sd;
+                    if (progress) fprintf(stderr, "[ctmrg sweep] T = %.6f: derivative: %s\n", T[i], c->err.c_str());
+                } else if (sd != CTMRG_OK) {
+                    return sd;
+                }
             }
         }
     }
@@ -723,6 +729,7 @@ ctmrg_status ctmrg_fixed_point_derivative(ctmrg_ctx *c, int second_order, ctmrg_
     out->M = r.M;
     out->dM_dK = r.dMdK;
     out->dE_dK = r.dEdK;
+    out->status = CTMRG_OK;
     if (second_order == 1) out->d2F_dK2 = r.dEdK;
     if (second_order == 2) {
         const size_t q4 = (size_t)c->q * c->q * c->q * c->q;

@@ -93,6 +93,7 @@ class Derivative(ctypes.Structure):
         ("M", ctypes.c_double),
         ("dE_dK", ctypes.c_double),
         ("dM_dK", ctypes.c_double),
+        ("status", ctypes.c_int),
     ]
 
 

@@ -5,8 +5,8 @@ One context per cutoff m; each temperature starts from the previous one's fixed 
 dF/dK (the energy u per site), d2F/dK2 = dE/dK (the specific heat per site is
 c = du/dT = -K^2 d2F/dK2) and dM/dK
 along the fixed point.  Optional checks at every k-th temperature: dF/dK against the central
-difference [F(K + dK) - F(K - dK)] / 2 dK over fixed points at K +- dK (each started from the
-fixed point at K), and against the impurity energy E of the same fixed point.
+difference [F(K + dK) - F(K - dK)] / 2 dK over fixed points at K +- dK (started from the fixed
+point at K, in a second context), and at every point against the impurity energy E.
 
 Usage (from the repository root, on a gfx950 GPU):
 
@@ -35,53 +35,67 @@ def vertex_set(name: str) -> np.ndarray:
 
 
 def run(V, m: int, Ts, tol: float, max_steps: int, fd_every: int, dK: float, log=sys.stderr,
-        precision: str = "fp64", eig: str = "two_stage", gap_tol=None) -> dict:
+        precision: str = "fp64", eig: str = "two_stage", gap_tol=None, out_path=None) -> dict:
     """The sweep on one context of the given contraction precision and eigensolver (the derivative
-    itself always runs in FP64)."""
+    itself always runs in FP64).  With out_path the summary is rewritten after every temperature."""
     Ts = [float(t) for t in Ts]
     g = ctmrg.CTMRG(V, 1.0 / Ts[0], m, precision=precision, eig=eig, gap_tol=gap_tol)
-    points = []
+    points, checks = [], []
     t0 = time.perf_counter()
     for i, T in enumerate(Ts):
         # one temperature per call, so that progress is reported; with warm_start each call
         # continues from the fixed point the context holds (the boundary for the first)
         t1 = time.perf_counter()
         p = g.sweep([T], tol, max_steps, warm_start=True, derivative=True)[0]
+        p["seconds"] = time.perf_counter() - t1
         points.append(p)
         d = p["derivative"]
-        print(f"# T={T:.5f}: {p['steps']} steps, f {p['f']:.12f} E {p['E']:.10f} M {p['M']:.10f}; "
-              f"dF/dK {d['dF_dK']:.10f} d2F/dK2 {d['d2F_dK2']:.8f} dM/dK {d['dM_dK']:.8f} "
-              f"({d['iterations']} tangent iterations), {time.perf_counter() - t1:.1f} s", file=log, flush=True)
-    total = time.perf_counter() - t0
-    g.close()
-    checks = []
-    if fd_every > 0:
-        for i in range(0, len(Ts), fd_every):
-            T = Ts[i]
+        print(f"# T={T:.5f}: {p['steps']} steps (Delta {p['delta']:.2e}), f {p['f']:.12f} E {p['E']:.10f} "
+              f"M {p['M']:.10f}; dF/dK {d['dF_dK']:.10f} d2F/dK2 {d['d2F_dK2']:.8f} dM/dK {d['dM_dK']:.8f} "
+              f"({d['iterations']} products J t, status {d['status']}), {p['seconds']:.1f} s", file=log, flush=True)
+        if fd_every > 0 and i % fd_every == 0 and p["converged"] and d["status"] == 0 and d["iterations"] > 0:
+            # F at K +- dK over fixed points started from this one (a second context)
             K = 1.0 / T
             h = ctmrg.CTMRG(V, K, m, precision=precision, eig=eig, gap_tol=gap_tol)
-            trio = h.sweep([T, 1.0 / (K + dK), 1.0 / (K - dK)], tol, max_steps, warm_start=True)
+            h.import_state(g.export_state())
+            pair = h.sweep([1.0 / (K + dK), 1.0 / (K - dK)], tol, max_steps, warm_start=True)
             h.close()
-            Fp = (K + dK) * trio[1]["f"]
-            Fm = (K - dK) * trio[2]["f"]
-            fd = (Fp - Fm) / (2 * dK)
-            d = points[i]["derivative"]
+            fd = ((K + dK) * pair[0]["f"] - (K - dK) * pair[1]["f"]) / (2 * dK)
             checks.append({"T": T, "dK": dK, "central_difference_dF_dK": fd, "dF_dK": d["dF_dK"],
-                           "abs_diff": abs(d["dF_dK"] - fd), "converged": all(x["converged"] for x in trio)})
+                           "abs_diff": abs(d["dF_dK"] - fd), "converged": all(x["converged"] for x in pair)})
             print(f"# check T={T:.5f}: dF/dK {d['dF_dK']:.10f}, central difference {fd:.10f}", file=log, flush=True)
+        if out_path:
+            _write(out_path, _summary(V, m, tol, precision, eig, time.perf_counter() - t0, points, checks))
+    total = time.perf_counter() - t0
+    g.close()
+    res = _summary(V, m, tol, precision, eig, total, points, checks)
+    if out_path:
+        _write(out_path, res)
+    return res
+
+
+def _summary(V, m, tol, precision, eig, total, points, checks) -> dict:
     rows = []
     for p in points:
         d = p["derivative"]
+        ok = p["converged"] and d["status"] == 0 and d["iterations"] > 0
         rows.append({"T": p["T"], "K": 1.0 / p["T"], "steps": p["steps"], "converged": p["converged"],
-                     "m_eff": p["m_eff"], "f": p["f"], "E": p["E"], "M": p["M"], "S_E": p["S_E"], "xi_e": p["xi_e"],
-                     "dF_dK": d["dF_dK"], "d2F_dK2": d["d2F_dK2"], "dM_dK": d["dM_dK"],
-                     "specific_heat": -(p["T"] ** -2) * d["d2F_dK2"],
-                     "dF_dK_minus_E": d["dF_dK"] - p["E"], "tangent_iterations": d["iterations"],
-                     "aligned_steps": d["aligned_steps"]})
+                     "delta": p["delta"], "m_eff": p["m_eff"], "f": p["f"], "E": p["E"], "M": p["M"], "S_E": p["S_E"],
+                     "xi_e": p["xi_e"], "derivative": ok, "derivative_status": d["status"],
+                     "dF_dK": d["dF_dK"] if ok else None, "d2F_dK2": d["d2F_dK2"] if ok else None,
+                     "dM_dK": d["dM_dK"] if ok else None,
+                     "specific_heat": -(p["T"] ** -2) * d["d2F_dK2"] if ok else None,
+                     "dF_dK_minus_E": d["dF_dK"] - p["E"] if ok else None, "tangent_products": d["iterations"],
+                     "aligned_steps": d["aligned_steps"], "seconds": p.get("seconds")})
+    diffs = [abs(r["dF_dK_minus_E"]) for r in rows if r["derivative"]]
     return {"m": m, "q": int(np.asarray(V).shape[0]), "tol": tol, "precision": precision, "eigensolver": eig,
-            "seconds": total, "points": rows,
-            "central_difference_checks": checks,
-            "max_abs_dF_dK_minus_E": max(abs(r["dF_dK_minus_E"]) for r in rows)}
+            "seconds": total, "points": rows, "central_difference_checks": checks,
+            "max_abs_dF_dK_minus_E": max(diffs) if diffs else None}
+
+
+def _write(path: str, res: dict):
+    with open(path, "w") as fh:
+        fh.write(json.dumps(res) + "\n")
 
 
 def main(argv=None):
@@ -104,13 +118,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
     Ts = np.linspace(args.T0, args.T1, args.n)
     res = run(vertex_set(args.vertices), args.m, Ts, args.tol, args.max_steps, args.fd_every, args.dK,
-              precision=args.precision, eig=args.eig, gap_tol=args.gap_tol)
+              precision=args.precision, eig=args.eig, gap_tol=args.gap_tol, out_path=args.out)
     res["vertices"] = args.vertices
-    text = json.dumps(res)
-    if args.out:
-        with open(args.out, "w") as fh:
-            fh.write(text + "\n")
-    print(text, flush=True)
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

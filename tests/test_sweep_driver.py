@@ -1,0 +1,63 @@
+"""Host logic of the sweep driver (paper_2004_08669_amd/sweep.py) with the library replaced by a
+stand-in that returns fixed observables: one call per temperature, the central-difference checks
+on the requested temperatures, the per-temperature summary (derivatives only where they were
+computed) and the JSON written after every temperature.  No GPU."""
+import json
+
+import numpy as np
+
+from paper_2004_08669_amd import sweep
+
+
+class FakeContext:
+    calls = []
+
+    def __init__(self, V, K, m, precision="fp64", eig="two_stage", gap_tol=None):
+        self.K = K
+        self.state = None
+
+    def sweep(self, Ts, tol, max_steps, warm_start=True, derivative=False):
+        out = []
+        for T in Ts:
+            FakeContext.calls.append(T)
+            K = 1.0 / T
+            # F = K f = -K^2 (an exact quadratic: its central difference is exact)
+            p = {"T": T, "steps": 10, "converged": T != 0.43, "delta": 1e-13, "m_eff": 4, "f": -K,
+                 "E": -2.0 * K, "M": 0.5, "S_E": 0.1, "xi_e": 2.0}
+            if derivative:
+                ok = p["converged"]
+                p["derivative"] = {"dF_dK": -2.0 * K if ok else 0.0, "d2F_dK2": -2.0 if ok else 0.0,
+                                   "dM_dK": 0.1 if ok else 0.0, "iterations": 12 if ok else 0,
+                                   "aligned_steps": 3, "status": 0}
+            out.append(p)
+        return out
+
+    def export_state(self):
+        return b"state"
+
+    def import_state(self, st):
+        self.state = st
+
+    def close(self):
+        pass
+
+
+def test_sweep_driver_summary(tmp_path, monkeypatch):
+    monkeypatch.setattr(sweep.ctmrg, "CTMRG", FakeContext)
+    FakeContext.calls = []
+    out = tmp_path / "s.json"
+    Ts = [0.40, 0.43, 0.46]
+    res = sweep.run(np.zeros((2, 1)), 8, Ts, 1e-12, 100, fd_every=2, dK=1e-3, out_path=str(out))
+    # one call per temperature, then K +- dK around the checked ones (T = 0.40 and 0.46)
+    assert FakeContext.calls[0] == 0.40 and 0.43 in FakeContext.calls and len(FakeContext.calls) == 3 + 2 * 2
+    rows = res["points"]
+    assert [r["T"] for r in rows] == Ts
+    assert rows[1]["derivative"] is False and rows[1]["dF_dK"] is None
+    assert rows[0]["derivative"] and abs(rows[0]["dF_dK"] - (-5.0)) < 1e-12
+    assert abs(rows[0]["specific_heat"] - 2.0 / 0.40 ** 2) < 1e-12
+    assert res["max_abs_dF_dK_minus_E"] == 0.0
+    assert len(res["central_difference_checks"]) == 2
+    for c in res["central_difference_checks"]:
+        assert c["abs_diff"] < 1e-9
+    on_disk = json.loads(out.read_text())
+    assert on_disk["points"] == json.loads(json.dumps(rows))
