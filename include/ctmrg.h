@@ -173,11 +173,17 @@ ctmrg_status ctmrg_init(int q, int dim, const double *vertex_vectors, double K, 
 /* Change K (rebuilds W) and reset the state to the initial one; buffers are reused. */
 ctmrg_status ctmrg_set_K(ctmrg_ctx *ctx, double K);
 
-/* Run nsteps CTMRG steps.  delta_out (nullable) receives Delta of the last step. */
+/* Run nsteps CTMRG steps, each one pass of the loop body of Algorithm 3 (Sec. III): the
+ * extension of the corner by the first Sub-CTMRG contraction and the weight, its
+ * diagonalization, the cut and normalization (with S_E of Eq. 6), the renormalized half-row
+ * by the second Sub-CTMRG contraction and the projection, and its normalization.
+ * delta_out (nullable) receives Delta of the last step (the change of the normalized kept
+ * spectrum, w_j^4, between consecutive steps, the loop's stopping quantity). */
 ctmrg_status ctmrg_step(ctmrg_ctx *ctx, int nsteps, double *delta_out);
 
-/* Step until Delta < tol (after at least two steps) or max_steps steps were taken.
- * Returns CTMRG_E_NOT_CONVERGED if max_steps is reached (the state is kept). */
+/* The loop of Algorithm 3 to its stopping rule: step until Delta < tol (after at least two
+ * steps) or max_steps steps were taken.  Returns CTMRG_E_NOT_CONVERGED if max_steps is reached
+ * (the state is kept). */
 ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *ctx, double tol, int max_steps, int *steps_out, double *delta_out);
 
 /* A sweep over temperatures, the scans of Sec. IV (for one cutoff m: a (T, m) grid is one

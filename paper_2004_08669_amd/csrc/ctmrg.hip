@@ -547,11 +547,23 @@ ctmrg_status ctmrg_set_K(ctmrg_ctx *c, double K)
     return reset_state(c);
 }
 
+// The flags that the last step's eigenvector kernels may have raised (each step checks those of
+// the step before): drained once the stream is idle, before a stepping call returns.
+static ctmrg_status finish_steps(ctmrg_ctx *c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return check_kernel_errors(c);
+}
+
 ctmrg_status ctmrg_step(ctmrg_ctx *c, int nsteps, double *delta_out)
 {
     if (!c || nsteps < 0) return CTMRG_E_INVALID_ARG;
     for (int i = 0; i < nsteps; ++i) {
         ctmrg_status st = one_step(c);
+        if (st != CTMRG_OK) return st;
+    }
+    if (nsteps > 0) {
+        const ctmrg_status st = finish_steps(c);
         if (st != CTMRG_OK) return st;
     }
     if (delta_out) *delta_out = c->delta;
@@ -568,6 +580,10 @@ ctmrg_status ctmrg_run_to_fixed_point(ctmrg_ctx *c, double tol, int max_steps, i
         if (s1 != CTMRG_OK) { st = s1; break; }
         ++taken;
         if (c->steps >= 2 && c->delta < tol) { st = CTMRG_OK; break; }
+    }
+    if (taken > 0 && (st == CTMRG_OK || st == CTMRG_E_NOT_CONVERGED)) {
+        const ctmrg_status sf = finish_steps(c);
+        if (sf != CTMRG_OK) st = sf;
     }
     if (steps_out) *steps_out = taken;
     if (delta_out) *delta_out = c->delta;
@@ -656,7 +672,8 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *c, ctmrg_observables_t *out, double *k
     if (kept_spectrum)
         HIPCHK(c, hipMemcpyAsync(kept_spectrum, c->dOmega, sizeof(double) * c->m, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (c->last_warm) {
+    {
+        // flags of the last step's eigenvector kernels and of this call's eigenvalue solve
         const ctmrg_status st = check_kernel_errors(c);
         if (st != CTMRG_OK) return st;
     }
