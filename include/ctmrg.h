@@ -255,7 +255,7 @@ ctmrg_status ctmrg_observables(ctmrg_ctx *ctx, ctmrg_observables_t *out, double 
  * environment variable CTMRG_PROGRESS set (to anything but 0), every tenth
  * aligned step and every twentieth product J t is reported on stderr.
  * Errors: CTMRG_E_STATE if the state is not converged; CTMRG_E_NOT_CONVERGED
- * if the aligned fixed point or the tangent iteration does not converge;
+ * if the aligned fixed point or the tangent solve does not converge;
  * CTMRG_E_NUMERICAL if the kept dimension changes or a multiplet is larger
  * than 8. */
 typedef struct ctmrg_derivative_s {

@@ -9,7 +9,8 @@ seeded inputs of ctmrg_inputs.py.  Usage (from the repository root):
       random state random_state(seed, 20, m) (Sec. III, Algorithm 3).  Stores, after every
       step, the full spectrum of C', m_eff, n_C, S_E (Eq. 6), the kept omega, n_P, and
       gauge-invariant functions of the new state: the q x q matrix Tr(P_s Om P_sg Om), the
-      environment sums of the observables and M (Eq. 5).
+      environment sums of the observables and M (Eq. 5).  --eig lapack takes numpy's LAPACK driver as the
+      diagonalization step (the two-step m = 256 file, seed 2).
 
   python tests/golden/make_golden.py fixedpoint --m 64 --T 0.40
       The fixed-boundary run from the initial state of Algorithm 3 until the kept spectrum
@@ -57,7 +58,7 @@ def onestep(args):
     P, om = I.random_state(args.seed, 20, args.m)
     o = O.OracleCTMRG(V, K, args.m, eig=args.eig)
     o.import_state(P, om, k=0)
-    out = {"q": 20, "m": args.m, "T": args.T, "seed": args.seed, "steps": args.steps}
+    out = {"q": 20, "m": args.m, "T": args.T, "seed": args.seed, "steps": args.steps, "eig": args.eig}
     for k in range(1, args.steps + 1):
         t0 = time.perf_counter()
         r = o.step()

@@ -1,12 +1,14 @@
 """The HIP path against stored oracle values (tests/golden/, written by make_golden.py, which
 calls only the CPU oracle) at sizes where the oracle takes minutes per step.
 
-* One and two steps at q = 20, m = 128 (C' 2560 x 2560) and one step at m = 256 (5120 x 5120)
+* Two steps at q = 20, m = 128 (C' 2560 x 2560), one step (seed 1) and two steps (seed 2, the
+  oracle's LAPACK diagonalization step) at m = 256 (5120 x 5120)
   from the seeded random states of ctmrg_inputs.random_state, T = 0.4398 (Sec. III,
   Algorithm 3): the full spectrum of C', the cut, the normalized kept spectrum, S_E (Eq. 6),
   and gauge-invariant functions of the new state -- the q x q matrix Tr(P_s Om P_sg Om) (it
   ties the slices together, so slices rotated by different orthogonal matrices fail it), the
-  environment sums of the energy, and M (Eq. 5).  FP64 and the mixed path.
+  environment sums of the energy, and M (Eq. 5); f after two steps.  FP64, and the mixed paths
+  (FP32 and split-bf16 contractions) to their own tolerances.
 * Fixed points of the fixed-boundary run at m = 64, T in {0.40, 0.42, 0.44, 0.46, 0.48},
   each side converged on its own (kept spectrum changing by < 1e-12): f, E, M, S_E and m_eff.
 """
@@ -62,11 +64,14 @@ def _check_step(g, ref, pre, m, tol):
     om = g.get("omega")
     me = int(ref[pre + "m_eff"])
     obs = g.observables()
+    # with a wider multiplet gap (the mixed paths) the cut may sit one multiplet lower: the kept
+    # spectra are compared over the states both kept
+    mc = me if tol["m_eff"] else min(me, int(obs["m_eff"]))
     G = _invariants(g, q, m)
     Go = ref[pre + "G"]
     d = {
         "spectrum": float(np.abs(lam - lam_o).max() / l1),
-        "omega": float(np.abs(om[:me] - ref[pre + "omega"]).max()),
+        "omega": float(np.abs(om[:mc] - ref[pre + "omega"][:mc]).max()),
         "S_E": abs(obs["S_E"] - float(ref[pre + "S_E"])),
         "G": float(np.abs(G - Go).max() / np.abs(Go).max()),
         "E": abs(obs["E"] - float(ref[pre + "E"])),
@@ -111,11 +116,15 @@ TOL_MIXED = {
 }
 
 
+TOL_F_MIXED = {"fp32": 1e-6, "bf16x3": 1e-5}
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("name", sorted(os.path.basename(p) for p in glob.glob(os.path.join(GOLDEN, "onestep_*.npz"))))
 def test_golden_steps_mixed(name, precision):
     """The mixed paths (FP32 contractions, or split-bf16 products with FP32 accumulation) against
-    the FP64 oracle, one step (m = 256 is the precision configuration: T = 0.4398, C' 5120 x 5120)."""
+    the FP64 oracle, every stored step (m = 256 is the precision configuration: T = 0.4398, C'
+    5120 x 5120; the two-step file also gives f)."""
     ct = _lib()
     ref = _load(name)
     m, seed, T = int(ref["m"]), int(ref["seed"]), float(ref["T"])
@@ -123,8 +132,22 @@ def test_golden_steps_mixed(name, precision):
     P, om = I.random_state(seed, 20, m)
     g = ct.CTMRG(I.dodecahedron(), 1.0 / T, m, precision=precision)
     g.set_state(P, om)
-    g.step(1)
-    _check_step(g, ref, "s1_", m, TOL_MIXED[precision])
+    steps = int(ref["steps"])
+    for k in range(1, steps + 1):
+        g.step(1)
+        tol = dict(TOL_MIXED[precision])
+        if k >= 2:
+            # the second step's C' is built from the first step's P~, whose error is the contraction
+            # error carried through the kept eigenvectors (divided by the eigen-gaps at the cut): the
+            # spectrum error grows by about 60 (FP32) and 30 (split-bf16) from the first step to the second
+            # at m = 128; a factor of 100 is allowed
+            tol["spectrum"] *= 100.0
+        obs = _check_step(g, ref, f"s{k}_", m, tol)
+    if steps >= 2:
+        # f from the normalizations of the two steps (R-f), to the accuracy class of the path
+        fo = float(ref["f"])
+        say(f"  f gpu {obs['f']!r} oracle {fo!r} (relative {abs(obs['f'] - fo) / abs(fo):.2e})")
+        assert abs(obs["f"] - fo) <= TOL_F_MIXED[precision] * abs(fo)
     g.close()
 
 
