@@ -453,9 +453,9 @@ reduce_items_kernel(const double *p1, const double *p2, int M, int N, int K, int
 // with FP32 accumulation: each operand value x is split into hi = bf16(x) and
 // lo = bf16(x - hi) (round to nearest even; x - hi is exact in FP32), and
 //   a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi,
-// dropping a_lo b_lo and the rounding of the lo parts, each about 2^-16 |a b|.
-// The bf16 products are exact in FP32, so the sum carries a relative error of order
-// 3 * 2^-16 per term on top of the FP32 accumulation.
+// dropping a_lo b_lo and the rounding of the lo parts: at most about 3 * 2^-16 |a b| per
+// term (2^-18 for a typical one), on top of the FP32 accumulation; the bf16 products
+// themselves are exact in FP32.
 //
 // Tiles: BK = 32 (one bf16 MFMA per 16 x 16 block and product).  In LDS every row
 // (of A: an output row, of B: an output column) holds its 32 k of the slice contiguous,
