@@ -86,3 +86,40 @@ def test_derivative_entry_points_reject_bad_arguments_without_a_gpu_call():
     ob = np.zeros(3)
     kb = ctypes.c_double(0.0)
     assert lib.ctmrg_backward(None, ctmrg._p(ob), ctypes.byref(kb), None) == 1
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a header struct, from a C program compiled against include/ctmrg.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    body = "".join(f'    printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text(f'#include <stdio.h>\n#include <stddef.h>\n#include "ctmrg.h"\nint main(void) {{\n'
+                   f'    printf("%zu\\n", sizeof({struct}));\n{body}    return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    return out[0], out[1:]
+
+
+@pytest.mark.parametrize("struct,cls", [("ctmrg_options", "Options"), ("ctmrg_observables_t", "Observables"),
+                                        ("ctmrg_derivative_t", "Derivative")])
+def test_binding_structs_match_the_header(struct, cls, tmp_path):
+    """The ctypes structures of the binding have the header's fields, in order, at the same offsets,
+    and the same size (what a C caller and the Python binding exchange)."""
+    from paper_2004_08669_amd import ctmrg
+    C = getattr(ctmrg, cls)
+    names = [n for n, _ in C._fields_]
+    size, offsets = _c_layout(struct, names, tmp_path)
+    assert size == ctypes.sizeof(C)
+    assert offsets == [getattr(C, n).offset for n in names]
+    # and the header has no field the binding lacks
+    text = open(os.path.join(ROOT, "include", "ctmrg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    m = re.search(r"typedef struct[^{]*\{([^}]*)\}\s*" + re.escape(struct) + r"\s*;", text)
+    assert m, struct
+    declared = re.findall(r"([A-Za-z_][A-Za-z0-9_]*)\s*;", m.group(1))
+    assert declared == names
