@@ -446,3 +446,23 @@ def test_ising_correlation_length_closed_form(T, ordered):
         prev = r
     assert abs(errs[-1]) <= (0.04 if ordered else 0.01)
     assert abs(errs[-1]) < abs(errs[0]) / 2.5
+
+
+def test_impurity_energy_is_dF_dK_and_its_derivative_is_d2F_dK2_q20():
+    """The identity the GPU's second derivative rests on (dF/dK equals the impurity energy E at
+    every fixed point, so d2F/dK2 = dE/dK), on the oracle's own q = 20, m = 12 fixed points at
+    K and K +- h (tests/golden, converged to 1e-13): the central difference of F equals E at K, and
+    the second difference of F equals the central difference of E, to the accuracy of the
+    differences (h^2 terms and 1e-13 / h^2 of convergence noise)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "derivative_q20_m12_T0.40.npz")
+    with np.load(path, allow_pickle=False) as z:
+        r = {k: float(z[k]) for k in ("h", "F_0", "F_p", "F_m", "E_0", "E_p", "E_m")}
+    h = r["h"]
+    dF = (r["F_p"] - r["F_m"]) / (2 * h)
+    d2F = (r["F_p"] - 2 * r["F_0"] + r["F_m"]) / h ** 2
+    dE = (r["E_p"] - r["E_m"]) / (2 * h)
+    assert abs(dF - r["E_0"]) <= 1e-7
+    assert abs(d2F - dE) <= 2e-4 * abs(dE)
+    # and not by accident: the energy is not the free energy's value, and E changes with K
+    assert abs(r["E_0"] - r["F_0"]) > 1.0 and abs(dE) > 0.1
