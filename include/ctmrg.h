@@ -107,7 +107,7 @@ typedef enum { CTMRG_EIG_TWO_STAGE = 0, CTMRG_EIG_WARM = 1 } ctmrg_eig_solver;
  *     midpoint of the resulting interval for sum lambda^4 is taken.
  *   CTMRG_WARM_TAIL_AUTO (default): the product only in steps where the bound
  *     on the tail's share of sum w^4 exceeds the contractions' own precision
- *     (1e-14 with FP64 contractions, 1e-9 with FP32), the midpoint otherwise. */
+ *     (1e-14 with FP64 contractions, 1e-9 with FP32 or BF16X3), the midpoint otherwise. */
 typedef enum { CTMRG_WARM_TAIL_EXACT = 0, CTMRG_WARM_TAIL_BOUND = 1, CTMRG_WARM_TAIL_AUTO = 2 } ctmrg_warm_tail;
 
 typedef struct {
