@@ -1,4 +1,5 @@
-"""The FP64 path at the size the bench times: q = 20, m = 512 (C' 10240 x 10240), band 16.
+"""The FP64 path at the size the bench times: q = 20, m = 512 (C' 10240 x 10240), band 16, and at the
+paper's largest cutoff, m = 800 (C' 16000 x 16000).
 
 The oracle cannot run a step at this size in a test, so the checks are the outputs it can
 compute one by one and properties that hold at any size:
@@ -136,5 +137,60 @@ def test_fullsize_m512_step():
     assert abs(np.sum(lam ** 4) - s4) <= 1e-12 * s4
     sym = float(np.abs(Pn - Pn.transpose(0, 2, 1)).max())
     say(f"  new P: max |P_s - P_s^T| = {sym:.3e}, max |P| = {np.abs(Pn).max():.3e}")
+    assert sym <= 1e-12 * np.abs(Pn).max()
+    assert abs(np.abs(Pn).max() - 1.0) <= 1e-15
+
+
+def test_fullsize_m800_step():
+    """The paper's largest cutoff, m = 800 (C' 16000 x 16000), FP64: the checks above that cost
+    O(N^2 m) on the host (the inertia and ||C'^2||_F checks, O(N^3), are left to m = 512)."""
+    ct = _lib()
+    V = I.dodecahedron()
+    q, m, K = 20, 800, 1.0 / 0.4398
+    N = q * m
+    say("[full size] q=20 m=800 T=0.4398: 4 steps")
+    g = ct.CTMRG(V, K, m)
+    g.step(4)
+    st = g.export_state()
+    P = g.P_slices()
+    om = g.get("omega")
+    g.extend()
+    C = g.get("cext")
+    cmax = float(np.abs(C).max())
+    W = O.weight(V, K)
+    rng = np.random.default_rng(1)
+    worst = 0.0
+    for _ in range(100):
+        r, c = int(rng.integers(N)), int(rng.integers(N))
+        worst = max(worst, abs(C[r, c] - O.extend_entry(W, P, om, r, c)))
+    asym = max(float(np.abs(C[i0:i0 + 2000, :] - C[:, i0:i0 + 2000].T).max()) for i0 in range(0, N, 2000))
+    say(f"  sampled entries: max |C' - oracle| = {worst:.3e}; max |C' - C'^T| = {asym:.3e} (max |C'| = {cmax:.3e})")
+    assert worst <= 1e-13 * cmax
+    assert asym <= 1e-13 * cmax
+    trace = float(np.trace(C))
+    fro2 = float(np.sum(C * C))
+    g.import_state(st)
+    g.step(1)
+    lam = g.get("spectrum")
+    U = g.get("U")
+    omn = g.get("omega")
+    Pn = g.P_slices()
+    g.close()
+    me = int(np.count_nonzero(omn))
+    l1 = float(np.abs(lam).max())
+    say(f"  m_eff {me}; trace identity {abs(lam.sum() - trace) / np.abs(lam).sum():.3e}, "
+        f"Frobenius identity {abs(np.sum(lam * lam) - fro2) / fro2:.3e}")
+    assert abs(lam.sum() - trace) <= 1e-11 * np.abs(lam).sum()
+    assert abs(np.sum(lam * lam) - fro2) <= 1e-11 * fro2
+    nC = float(np.sum(lam ** 4) ** 0.25)
+    lk = lam[np.lexsort((-lam, -np.abs(lam)))][:me]
+    assert np.abs(omn[:me] - lk / nC).max() <= 1e-12
+    Uk = U[:, :me]
+    res = float(np.linalg.norm(C @ Uk - Uk * lk[None, :], axis=0).max())
+    orth = float(np.abs(Uk.T @ Uk - np.eye(me)).max())
+    say(f"  kept residual max {res:.3e} (|lambda_1| = {l1:.3e}); ||U^T U - I|| = {orth:.3e}")
+    assert res <= 1e-11 * l1
+    assert orth <= 1e-11
+    sym = float(np.abs(Pn - Pn.transpose(0, 2, 1)).max())
     assert sym <= 1e-12 * np.abs(Pn).max()
     assert abs(np.abs(Pn).max() - 1.0) <= 1e-15

@@ -61,3 +61,47 @@ def test_sweep_driver_summary(tmp_path, monkeypatch):
         assert c["abs_diff"] < 1e-9
     on_disk = json.loads(out.read_text())
     assert on_disk["points"] == json.loads(json.dumps(rows))
+
+
+def test_sweep_driver_grid(tmp_path, monkeypatch):
+    """The (T, m) grid: one context per cutoff in order, observables only, the file holding every
+    finished cutoff."""
+    made = []
+
+    class GridContext(FakeContext):
+        def __init__(self, V, K, m, **kw):
+            super().__init__(V, K, m, **kw)
+            made.append(m)
+
+    monkeypatch.setattr(sweep.ctmrg, "CTMRG", GridContext)
+    FakeContext.calls = []
+    out = tmp_path / "g.json"
+    Ts = [0.40, 0.46]
+    res = sweep.run_grid(np.zeros((2, 1)), [8, 16], Ts, 1e-12, 100, fd_every=1, dK=1e-3, out_path=str(out),
+                         derivative=False)
+    assert made == [8, 16]
+    assert FakeContext.calls == Ts + Ts  # no central-difference contexts without derivatives
+    assert [g["m"] for g in res["grid"]] == [8, 16]
+    for g in res["grid"]:
+        assert [r["T"] for r in g["points"]] == Ts
+        assert all(r["derivative"] is False and r["dF_dK"] is None for r in g["points"])
+        assert g["central_difference_checks"] == [] and g["max_abs_dF_dK_minus_E"] is None
+    on_disk = json.loads(out.read_text())
+    assert [g["m"] for g in on_disk["grid"]] == [8, 16]
+
+
+def test_sweep_cli_cutoff_sets(monkeypatch):
+    """--set A/B name the paper's two cutoff sets over 0.35 <= T <= 0.56."""
+    seen = {}
+
+    def fake_grid(V, ms, Ts, *a, **kw):
+        seen.update(ms=list(ms), Ts=list(Ts), derivative=kw["derivative"])
+        return {"grid": []}
+
+    monkeypatch.setattr(sweep, "run_grid", fake_grid)
+    monkeypatch.setattr(sweep, "vertex_set", lambda name: np.zeros((20, 3)))
+    sweep.main(["--set", "A", "--n", "22", "--no-derivative"])
+    assert seen["ms"] == [120, 240, 500, 800] and seen["derivative"] is False
+    assert abs(seen["Ts"][0] - 0.35) < 1e-15 and abs(seen["Ts"][-1] - 0.56) < 1e-15 and len(seen["Ts"]) == 22
+    sweep.main(["--set", "B", "--n", "3"])
+    assert seen["ms"] == [500, 600, 700, 800] and seen["derivative"] is True
