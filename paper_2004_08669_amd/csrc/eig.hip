@@ -974,188 +974,214 @@ post_eigen_kernel(const double *ev, int N, int m, double gap_tol, double rank_to
 // Eigenvectors of the tridiagonal: inverse iteration
 // ============================================================================
 
-// One thread per kept eigenvalue; the LU scratch and the iterate of thread c are
-// interleaved (element i of array a at lu[(a*N + i)*nth + c]) so that the lanes
-// of a wave touch adjacent addresses.  The factorization of T - lambda I with
-// partial pivoting carries its recurrence in registers and reads only d and e;
-// the factorization and the triangular solves work in chunks of IV_CH rows
-// whose loads are all issued before the chunk's recurrence runs.  The
-// normalization of an iterate is folded into the next pass that reads it.
+// One wave per kept eigenvalue.  The pivoted LU of T - lambda I and the two
+// triangular solves of each iteration are recurrences along the rows; the wave
+// walks them in chunks of 64 rows.  Lane l loads the operands of row r0 + l
+// (one coalesced load per array, the next chunk's loads issued before the
+// current chunk runs), every lane evaluates the recurrence with the row's
+// operands broadcast from the lane that loaded them (v_readlane), and lane u
+// keeps the result of row r0 + u for the chunk's store.  With one wave per
+// vector, the m kept vectors occupy m waves across the chip instead of m/64.
+// Each vector's scratch is contiguous, with the rows padded to Np = 64
+// ceil(N / 64): lu[(5 c + a) Np + i] holds the multipliers (a = 0), the
+// reciprocal pivots (1), the first and second superdiagonals of U (2, 3) and
+// the iterate (4); ipiv[c Np + i] the row interchanges.  Every row takes the
+// same form: the operands past the last row are zero, so the last row keeps
+// its pivot and contributes nothing beyond itself, and the padding rows carry
+// zero multipliers and superdiagonals, so that the iterate is zero on them
+// after each forward pass and stays zero through the backward pass.  All loads
+// and stores are unconditional (padded rows, clamped input indices), so the
+// memory counters of a chunk are the same on every path and the waits only
+// cover the chunk that runs.
 // Three iterations from a counter-based random start.  With a shift accurate to
 // eps ||T||, only members of an exactly (or nearly exactly) degenerate cluster
 // can converge to the same direction; cluster_orth_kernel separates them.
-constexpr int IV_CH = 16;
-
-// The vector memory counter covers loads and stores alike, so a wait for loads
-// issued after stores also waits for those stores.  The kernel keeps the two
-// apart: the factorization reads d and e from LDS (staged IV_LDS rows at a time,
-// one global wait per stage), and each chunk of a triangular solve issues its
-// loads before it stores the previous chunk's results (held in registers).
-constexpr int IV_LDS = 2048;
+CTMRG_DEVINL double lane_bcast(double v, int u)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), u);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), u);
+    return __hiloint2double(hi, lo);
+}
 
 __global__ void __launch_bounds__(64)
-invit_kernel(const double *d, const double *e, int N, const double *selval, int me, double *ZT, int ldz, double *lu,
-             int *ipiv, const double *bounds, unsigned *err)
+invit_wave_kernel(const double *d, const double *e, int N, const double *selval, int me, double *ZT, int ldz,
+                  double *lu, int *ipiv, const double *bounds, unsigned *err)
 {
-    __shared__ double sd[IV_LDS], se[IV_LDS + 1];
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nth = gridDim.x * blockDim.x;
-    const bool act = c < me;
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (c >= me) return;
+    const double lam = selval[c];
     const double tn = bounds[3];
     const double pivmin = fmax(DBL_EPSILON * tn, DBL_MIN);
-#define DL(i) lu[((long)0 * N + (i)) * nth + c]
-#define DD(i) lu[((long)1 * N + (i)) * nth + c]
-#define DU(i) lu[((long)2 * N + (i)) * nth + c]
-#define DU2(i) lu[((long)3 * N + (i)) * nth + c]
-#define X(i) lu[((long)4 * N + (i)) * nth + c]
-#define IP(i) ipiv[(long)(i) * nth + c]
-    const double lam = act ? selval[c] : 0.0;
-    // ---- LU with partial pivoting of T - lam I (rows i, i+1 swapped when |e_i| > |pivot|)
-    double ddi = d[0] - lam, dui = (N > 1) ? e[0] : 0.0;
-    for (int base = 0; base < N - 1; base += IV_LDS) {
-        const int cnt = min(IV_LDS, N - 1 - base);
-        __syncthreads();
-        for (int u = threadIdx.x; u <= cnt; u += blockDim.x) {
-            if (u < cnt) sd[u] = d[base + u + 1];
-            se[u] = (base + u < N - 1) ? e[base + u] : 0.0;
+    const int Np = (N + 63) & ~63;
+    const int J = Np / 64;
+    double *const DLp = lu + (5L * c + 0) * Np;
+    double *const RDp = lu + (5L * c + 1) * Np;
+    double *const DUp = lu + (5L * c + 2) * Np;
+    double *const DU2p = lu + (5L * c + 3) * Np;
+    double *const Xp = lu + (5L * c + 4) * Np;
+    int *const IPp = ipiv + (long)c * Np;
+    // e has N - 1 entries (none for N = 1); out-of-range operands read a valid entry and are zeroed
+    const int elast = max(N - 2, 0);
+
+    // ---- LU with partial pivoting of T - lam I: row i's operands are e_i, d_(i+1) - lam and e_(i+1)
+    // (zero past the end); rows i and i+1 are interchanged when |e_i| > |pivot|
+    {
+        double ddi = d[0] - lam;
+        double dui = (N > 1) ? e[0] : 0.0;
+        double cl, cd, cu;
+        {
+            const int i = lane;
+            const double a = e[min(i, elast)], b = d[min(i + 1, N - 1)], g = e[min(i + 1, elast)];
+            cl = (i < N - 1) ? a : 0.0;
+            cd = (i + 1 < N) ? b - lam : 0.0;
+            cu = (i + 1 < N - 1) ? g : 0.0;
         }
-        __syncthreads();
-        if (act) {
-            for (int u = 0; u < cnt; ++u) {
-                const int i = base + u;
-                const double li = se[u];
-                const double dn = sd[u] - lam;
-                const double dun = (i < N - 2) ? se[u + 1] : 0.0;
-                if (fabs(ddi) >= fabs(li)) {
-                    const double piv = (fabs(ddi) < pivmin) ? (ddi < 0.0 ? -pivmin : pivmin) : ddi;
-                    const double f = li / piv;
-                    DD(i) = piv; DL(i) = f; DU(i) = dui; DU2(i) = 0.0; IP(i) = 0;
-                    ddi = dn - f * dui;
-                    dui = dun;
-                } else {
-                    const double f = ddi / li;
-                    DD(i) = li; DL(i) = f; DU(i) = dn; DU2(i) = dun; IP(i) = 1;
-                    ddi = dui - f * dn;
-                    dui = -f * dun;
-                }
+        for (int j = 0; j < J; ++j) {
+            const int r0 = 64 * j;
+            double nl, nd, nu;
+            {
+                const int i = r0 + 64 + lane;  // the next chunk (zero operands past the last chunk)
+                const double a = e[min(i, elast)], b = d[min(i + 1, N - 1)], g = e[min(i + 1, elast)];
+                nl = (i < N - 1) ? a : 0.0;
+                nd = (i + 1 < N) ? b - lam : 0.0;
+                nu = (i + 1 < N - 1) ? g : 0.0;
             }
+            double oL = 0.0, oR = 0.0, oU = 0.0, oU2 = 0.0;
+            int oP = 0;
+#pragma unroll 16
+            for (int u = 0; u < 64; ++u) {
+                const double li = lane_bcast(cl, u), dn = lane_bcast(cd, u), dun = lane_bcast(cu, u);
+                const bool keep = fabs(ddi) >= fabs(li);
+                const double pv = keep ? ((fabs(ddi) < pivmin) ? (ddi < 0.0 ? -pivmin : pivmin) : ddi) : li;
+                const double f = (keep ? li : ddi) / pv;
+                const double rd = 1.0 / pv;
+                const double du = keep ? dui : dn;
+                const double du2 = keep ? 0.0 : dun;
+                const double ndd = keep ? dn - f * dui : dui - f * dn;
+                const double ndu = keep ? dun : -f * dun;
+                const bool mine = lane == u;
+                oL = mine ? f : oL;
+                oR = mine ? rd : oR;
+                oU = mine ? du : oU;
+                oU2 = mine ? du2 : oU2;
+                oP = mine ? (keep ? 0 : 1) : oP;
+                ddi = ndd;
+                dui = ndu;
+            }
+            DLp[r0 + lane] = oL;
+            RDp[r0 + lane] = oR;
+            DUp[r0 + lane] = oU;
+            DU2p[r0 + lane] = oU2;
+            IPp[r0 + lane] = oP;
+            cl = nl; cd = nd; cu = nu;
         }
     }
-    if (!act) return;
-    if (fabs(ddi) < pivmin) ddi = (ddi < 0.0 ? -pivmin : pivmin);
-    DD(N - 1) = ddi;
-    // ---- start vector (counter-based random numbers)
+
+    // ---- start vector (counter-based random numbers; zero on the padding rows) and its norm
+    const uint64_t key = (uint64_t)(c + 1) << 32;
     double nrm2 = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double x = hash_uniform(((uint64_t)(c + 1) << 32) ^ (uint64_t)i);
-        X(i) = x;
+    for (int i = lane; i < Np; i += 64) {
+        const double x = (i < N) ? hash_uniform(key ^ (uint64_t)i) : 0.0;
+        Xp[i] = x;
         nrm2 += x * x;
     }
-    double sc = 1.0 / sqrt(nrm2);  // pending scale of the stored iterate
+    double sc = 1.0 / sqrt(wave_sum(nrm2));  // pending scale of the iterate
     for (int it = 0; it < 3; ++it) {
-        // forward: unit lower factor with row interchanges, applied to sc * X
-        double xi = X(0) * sc;
+        // the stores of the previous pass (other lanes' rows included) are visible from here
+        __syncthreads();
+        // forward: unit lower factor with row interchanges applied to sc x; row i reads x_(i+1)
         {
-            double out[IV_CH];
-            int pend_i0 = -1, pend_n = 0;  // the previous chunk's results, not yet stored
-            for (int i0 = 0; i0 < N - 1; i0 += IV_CH) {
-                const int nI = min(IV_CH, N - 1 - i0);
-                double xn[IV_CH], dl[IV_CH];
-                int ip[IV_CH];
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) { xn[u] = X(i0 + u + 1) * sc; dl[u] = DL(i0 + u); ip[u] = IP(i0 + u); }
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < pend_n) X(pend_i0 + u) = out[u];
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) {
-                        if (ip[u] == 0) { out[u] = xi; xi = xn[u] - dl[u] * xi; }
-                        else { out[u] = xn[u]; xi = xi - dl[u] * xn[u]; }
-                    }
-                pend_i0 = i0;
-                pend_n = nI;
+            double xi = Xp[0] * sc;
+            double cdl, cxn;
+            int cip;
+            {
+                const int i = lane;
+                const double xr = Xp[min(i + 1, Np - 1)];
+                cdl = DLp[i];
+                cip = IPp[i];
+                cxn = (i + 1 < N) ? xr * sc : 0.0;
             }
-#pragma unroll
-            for (int u = 0; u < IV_CH; ++u)
-                if (u < pend_n) X(pend_i0 + u) = out[u];
+            for (int j = 0; j < J; ++j) {
+                const int r0 = 64 * j;
+                double ndl, nxn;
+                int nip;
+                {
+                    const int i = min(r0 + 64, Np - 64) + lane;  // the next chunk (reloads the last one at the end)
+                    const double xr = Xp[min(i + 1, Np - 1)];
+                    ndl = DLp[i];
+                    nip = IPp[i];
+                    nxn = (i + 1 < N) ? xr * sc : 0.0;
+                }
+                double o = 0.0;
+#pragma unroll 16
+                for (int u = 0; u < 64; ++u) {
+                    const double dl = lane_bcast(cdl, u), xn = lane_bcast(cxn, u);
+                    const int ip = __builtin_amdgcn_readlane(cip, u);
+                    const double out = ip ? xn : xi;
+                    xi = ip ? xi - dl * xn : xn - dl * xi;
+                    o = (lane == u) ? out : o;
+                }
+                Xp[r0 + lane] = o;
+                cdl = ndl; cxn = nxn; cip = nip;
+            }
         }
-        X(N - 1) = xi;
-        // backward: upper factor with two superdiagonals; accumulate the norm
-        double x1 = X(N - 1) / DD(N - 1);
-        X(N - 1) = x1;
-        nrm2 = x1 * x1;
-        double x2 = 0.0;
-        if (N > 1) {
-            const double x0 = (X(N - 2) - DU(N - 2) * x1) / DD(N - 2);
-            X(N - 2) = x0;
-            nrm2 += x0 * x0;
-            x2 = x1;
-            x1 = x0;
-        }
+        __syncthreads();
+        // backward: upper factor with two superdiagonals, rows in reverse order (padding rows are zero)
         {
-            double res[IV_CH];
-            int pend_i0 = -1, pend_n = 0;
-            for (int i0 = N - 3; i0 >= 0; i0 -= IV_CH) {
-                const int nI = min(IV_CH, i0 + 1);
-                double xv[IV_CH], du[IV_CH], du2[IV_CH], dd[IV_CH];
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) { xv[u] = X(i0 - u); du[u] = DU(i0 - u); du2[u] = DU2(i0 - u); dd[u] = DD(i0 - u); }
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < pend_n) X(pend_i0 - u) = res[u];
-#pragma unroll
-                for (int u = 0; u < IV_CH; ++u)
-                    if (u < nI) {
-                        const double xnew = (xv[u] - du[u] * x1 - du2[u] * x2) / dd[u];
-                        x2 = x1;
-                        x1 = xnew;
-                        res[u] = xnew;
-                        nrm2 += xnew * xnew;
-                    }
-                pend_i0 = i0;
-                pend_n = nI;
+            double x1 = 0.0, x2 = 0.0, part = 0.0;
+            double cxv, cdu, cdu2, crd;
+            {
+                const int i = Np - 64 + lane;
+                cxv = Xp[i];
+                cdu = DUp[i];
+                cdu2 = DU2p[i];
+                crd = RDp[i];
             }
-#pragma unroll
-            for (int u = 0; u < IV_CH; ++u)
-                if (u < pend_n) X(pend_i0 - u) = res[u];
+            for (int j = J - 1; j >= 0; --j) {
+                const int r0 = 64 * j;
+                double nxv, ndu, ndu2, nrd;
+                {
+                    const int i = max(r0 - 64, 0) + lane;  // the next chunk down (reloads the first at the end)
+                    nxv = Xp[i];
+                    ndu = DUp[i];
+                    ndu2 = DU2p[i];
+                    nrd = RDp[i];
+                }
+                double o = 0.0;
+#pragma unroll 16
+                for (int u = 63; u >= 0; --u) {
+                    const double xv = lane_bcast(cxv, u), du = lane_bcast(cdu, u);
+                    const double du2 = lane_bcast(cdu2, u), rd = lane_bcast(crd, u);
+                    const double xn = (xv - du2 * x2 - du * x1) * rd;
+                    x2 = x1;
+                    x1 = xn;
+                    o = (lane == u) ? xn : o;
+                }
+                Xp[r0 + lane] = o;
+                part += o * o;
+                cxv = nxv; cdu = ndu; cdu2 = ndu2; crd = nrd;
+            }
+            nrm2 = wave_sum(part);
         }
         if (!(nrm2 > 0.0) || !isfinite(nrm2)) {
-            raise_error(err, KERR_NONFINITE);
+            if (lane == 0) raise_error(err, KERR_NONFINITE);
             nrm2 = 1.0;
         }
         sc = 1.0 / sqrt(nrm2);
     }
-    {
-        double v[IV_CH];
-        int pend_i0 = -1, pend_n = 0;
-        for (int i0 = 0; i0 < N; i0 += IV_CH) {
-            const int nI = min(IV_CH, N - i0);
-            double xv[IV_CH];
+    __syncthreads();
+    // the normalized vector, column c of ZT (eight rows per lane in flight)
+    for (int i0 = 0; i0 < Np; i0 += 512) {
+        double v[8];
 #pragma unroll
-            for (int u = 0; u < IV_CH; ++u)
-                if (u < nI) xv[u] = X(i0 + u);
+        for (int t = 0; t < 8; ++t) v[t] = Xp[min(i0 + 64 * t, Np - 64) + lane];
 #pragma unroll
-            for (int u = 0; u < IV_CH; ++u)
-                if (u < pend_n) ZT[(long)(pend_i0 + u) * ldz + c] = v[u];
-#pragma unroll
-            for (int u = 0; u < IV_CH; ++u)
-                if (u < nI) v[u] = xv[u] * sc;
-            pend_i0 = i0;
-            pend_n = nI;
+        for (int t = 0; t < 8; ++t) {
+            const int i = i0 + 64 * t + lane;
+            if (i < N) ZT[(long)i * ldz + c] = v[t] * sc;
         }
-#pragma unroll
-        for (int u = 0; u < IV_CH; ++u)
-            if (u < pend_n) ZT[(long)(pend_i0 + u) * ldz + c] = v[u];
     }
-#undef DL
-#undef DD
-#undef DU
-#undef DU2
-#undef IP
-#undef X
 }
 
 // Modified Gram-Schmidt inside each tight cluster (members in ascending
@@ -1535,7 +1561,7 @@ struct EigReq {
 static std::vector<EigReq> eig_requests(EigWork &w, int Nmax, int kmax, int b)
 {
     const int np = num_panels(Nmax, b);
-    const size_t kpad = ((size_t)kmax + 63) / 64 * 64;  // threads of invit_kernel
+    const size_t npad = ((size_t)Nmax + 63) / 64 * 64;  // rows of invit_wave_kernel's scratch
     w.Nmax = Nmax;
     w.kmax = kmax;
     w.b = b;
@@ -1569,8 +1595,8 @@ static std::vector<EigReq> eig_requests(EigWork &w, int Nmax, int kmax, int b)
         {(void **)&w.ZT, sizeof(double) * (size_t)Nmax * kmax},
         {(void **)&w.Ztmp, sizeof(double) * (size_t)Nmax * kmax},
         {(void **)&w.G, sizeof(double) * (size_t)kmax * kmax},
-        {(void **)&w.lu, sizeof(double) * 5 * (size_t)Nmax * kpad},
-        {(void **)&w.ipiv, sizeof(int) * (size_t)Nmax * kpad},
+        {(void **)&w.lu, sizeof(double) * 5 * npad * (size_t)kmax},
+        {(void **)&w.ipiv, sizeof(int) * npad * (size_t)kmax},
         {(void **)&w.clist, sizeof(int) * (size_t)(kmax + 2) * 2},
         {(void **)&w.cstart, sizeof(int) * (size_t)(kmax + 2)},
     };
@@ -2103,8 +2129,9 @@ hipError_t eig_vectors(EigWork &w, const double *, long, int N, int me, const do
     const double *bounds = w.sm + 3 * b * b;
     hipError_t e;
     mark(w, MK_VEC_START, s);
-    hipLaunchKernelGGL(invit_kernel, dim3(ceil_div(me, 64)), dim3(64), 0, s, w.d, w.e, N, selval, me, w.ZT, ldz, w.lu,
-                       w.ipiv, bounds, w.err);
+    if (me > 0)
+        hipLaunchKernelGGL(invit_wave_kernel, dim3(me), dim3(64), 0, s, w.d, w.e, N, selval, me, w.ZT, ldz, w.lu,
+                           w.ipiv, bounds, w.err);
     if (nclusters < me)
         hipLaunchKernelGGL(cluster_orth_kernel, dim3(nclusters), dim3(256), 0, s, w.ZT, ldz, N, w.clist, w.cstart);
     mark(w, MK_INVIT, s);
