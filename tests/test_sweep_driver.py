@@ -105,3 +105,25 @@ def test_sweep_cli_cutoff_sets(monkeypatch):
     assert abs(seen["Ts"][0] - 0.35) < 1e-15 and abs(seen["Ts"][-1] - 0.56) < 1e-15 and len(seen["Ts"]) == 22
     sweep.main(["--set", "B", "--n", "3"])
     assert seen["ms"] == [500, 600, 700, 800] and seen["derivative"] is True
+
+
+def test_sweep_cli_cutoff_list(monkeypatch):
+    """--m takes one cutoff (a plain scan over 0.40-0.48) or a comma-separated list (a grid)."""
+    seen = {}
+
+    def fake_run(V, m, Ts, *a, **kw):
+        seen.update(kind="run", ms=[m], Ts=list(Ts))
+        return {"points": []}
+
+    def fake_grid(V, ms, Ts, *a, **kw):
+        seen.update(kind="grid", ms=list(ms), Ts=list(Ts))
+        return {"grid": []}
+
+    monkeypatch.setattr(sweep, "run", fake_run)
+    monkeypatch.setattr(sweep, "run_grid", fake_grid)
+    monkeypatch.setattr(sweep, "vertex_set", lambda name: np.zeros((20, 3)))
+    sweep.main(["--m", "64", "--n", "5"])
+    assert seen["kind"] == "run" and seen["ms"] == [64] and len(seen["Ts"]) == 5
+    assert abs(seen["Ts"][0] - 0.40) < 1e-15 and abs(seen["Ts"][-1] - 0.48) < 1e-15
+    sweep.main(["--m", "120,240", "--n", "2", "--T0", "0.5", "--T1", "0.6"])
+    assert seen["kind"] == "grid" and seen["ms"] == [120, 240] and seen["Ts"] == [0.5, 0.6]
